@@ -1,0 +1,108 @@
+/*
+ * Plain FP64 CPU oracle for the short-range force / time-step path of the
+ * two-component CGMD red-cell membrane model (OpenRBC, Tang et al.).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP library; the two meet only through the
+ * seeded input generator.
+ *
+ * Everything here is the plain definition, written for a reader to check by
+ * eye: brute-force or uniform-grid pair enumeration with one exact FP64
+ * distance test, per-pair potentials, per-particle sums, a textbook
+ * velocity-Verlet / linear-rotor step, and the deterministic Voronoi
+ * (k-means) reference steps used to unit-test the GPU cell build.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off (no fast-math): every FP64
+ * operation is rounded separately, which the bit-exact neighbour test needs.
+ *
+ * Pins (what fixes each function besides itself; see tests/test_oracle_*.py):
+ *   orc_pair_lipid   central finite differences of U for F and torque; closed
+ *                    values at r_min (parallel -eps, antiparallel (2mu-1)eps,
+ *                    stacked (mu-1)eps); zero at and beyond r_c; continuity at
+ *                    r_min and r_c; swap, rotation and n -> -n invariance;
+ *                    per-pair momentum and angular-momentum identities.
+ *                    The potential's form and constants are a reading: the
+ *                    paper cites its membrane model without stating it, so
+ *                    they are parity unpinned against the paper itself.
+ *   orc_pair_wca     textbook closed form; zero value and force at 2^(1/6) sigma.
+ *   orc_bond         harmonic closed form; dimer period 2 pi / sqrt(2k/m).
+ *   orc_pairs_*      brute force O(N^2) == uniform grid, bit for bit; the flat
+ *                    patch has exactly 18 lipid neighbours per lipid.
+ *   orc_forces*      FD of the total energy; sum F = 0; sum(r x F + tau) = 0
+ *                    on open boundaries; energy == sum of pair energies.
+ *   orc_assign       brute-force argmin (the definition itself).
+ *   orc_seed_update  Lloyd objective non-increasing; centroid of a cell.
+ *   orc_morton       hand-computed keys for known points.
+ *   orc_vv_run       energy error falls ~4x when dt halves; time reversal;
+ *                    free rotor; harmonic dimer period.
+ */
+#ifndef RBC_ORACLE_H
+#define RBC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double box[3];
+    int32_t periodic[3];
+    double rc[3][3];          /* cutoff per type pair; rc[0][0] is the lipid r_c */
+    double eps, zeta, mu, sin_theta0, r_min;
+    double wca_eps, wca_sigma;
+    double k_bond;
+    double mass[3];
+    double inertia;
+} orc_params;
+
+/* Min-image difference d = x_i - x_j and the exact FP64 squared distance. */
+double orc_dist2(const orc_params *p, const double *xi, const double *xj, double *d);
+
+/* Lipid-lipid orientation-dependent pair.  d = x_i - x_j.  Returns U; writes the
+ * force on i (force on j is -Fi) and the torques on i and j. */
+double orc_pair_lipid(const orc_params *p, const double *d, const double *ni, const double *nj,
+                      double *Fi, double *ti, double *tj);
+/* WCA pair for any pair involving a protein bead.  Returns U; writes force on i. */
+double orc_pair_wca(const orc_params *p, const double *d, double *Fi);
+/* Harmonic bond.  Returns U; writes force on i. */
+double orc_bond(const orc_params *p, const double *d, double r0, double *Fi);
+
+/* Neighbour set: all pairs (i<j) with dist2 < fl(rc*rc); written as sorted (i,j).
+ * Returns the pair count (writes at most cap pairs). */
+int64_t orc_pairs_brute(const orc_params *p, int64_t n, const double *x, const int32_t *type,
+                        int64_t cap, int32_t *ij);
+int64_t orc_pairs_grid(const orc_params *p, int64_t n, const double *x, const int32_t *type,
+                       int64_t cap, int32_t *ij);
+
+/* Forces, torques, U and the scalar virial W over all pairs of the neighbour
+ * set and all bonds.  energy[0] = U, energy[1] = W.  nthreads <= 0: OpenMP default. */
+int orc_forces(const orc_params *p, int64_t n, const double *x, const double *nrm,
+               const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
+               double *F, double *T, double *energy, int nthreads);
+/* Forces on the listed particles only, by brute force over every partner. */
+int orc_forces_subset(const orc_params *p, int64_t n, const double *x, const double *nrm,
+                      const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
+                      int64_t nsub, const int64_t *idx, double *F, double *T, int nthreads);
+
+/* Voronoi reference steps. */
+void orc_assign(const orc_params *p, int64_t n, const double *x, int64_t k, const double *seeds,
+                int32_t *owner);
+void orc_seed_update(const orc_params *p, int64_t n, const double *x, const int32_t *type,
+                     const int32_t *owner, int64_t k, double *seeds);
+void orc_morton(const orc_params *p, int64_t k, const double *seeds, uint64_t *keys);
+void orc_cell_bounds(const orc_params *p, int64_t n, const double *x, const int32_t *owner,
+                     int64_t k, const double *seeds, double *R);
+int64_t orc_cell_pairs(const orc_params *p, int64_t k, const double *seeds, const double *R,
+                       double rs, double skin, int64_t cap, int32_t *ab);
+
+/* NVE velocity Verlet with the free linear-rotor drift.  energies (nsteps+1) x 3:
+ * KE, U, KE+U at every step (entry 0 = initial).  State arrays updated in place. */
+int orc_vv_run(const orc_params *p, int64_t n, double *x, double *v, double *nrm, double *w,
+               const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
+               double dt, int64_t nsteps, double *energies, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
