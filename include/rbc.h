@@ -1,0 +1,178 @@
+/*
+ * rbc.h -- C ABI of the MI355X (gfx950) short-range force / time-step library
+ * for the two-component CGMD red-cell membrane model (OpenRBC, Tang et al.).
+ *
+ * What the library computes (paper sections cited by name; the paper gives
+ * no potential, so the model constants are parameters):
+ *  - rbc_update_cells: the adaptive "lattice-free" cell list of the Spatial
+ *    Searching Algorithm section -- Voronoi cells of k-means centroids over
+ *    the lipid particles, kept current by an online expectation-maximisation
+ *    update (nearest-centroid assignment, centroid move), centroids ordered
+ *    along a Morton curve and particles reordered by owning cell (the
+ *    two-level reordering), plus the cell-pair and per-particle neighbour
+ *    lists derived from them.
+ *  - rbc_forces: pairwise forces and torques between lipids, lipids and
+ *    proteins and between proteins found through those cells, plus the bond
+ *    list of physically linked proteins (Force Evaluation section).
+ *  - rbc_step: the time-stepping loop of the Software Overview section: force
+ *    and torque on every particle drive position and orientation updates
+ *    (velocity Verlet with a free linear-rotor drift for lipid orientations).
+ *
+ * Conventions.
+ *  - Array pointers marked [device] are HIP device pointers (for example
+ *    torch CUDA tensors' data_ptr()).  n x 3 arrays are C-contiguous row-major
+ *    FP64.  All device work is enqueued on the library's own stream, which is
+ *    ordered after the caller's stream (passed at create) on entry and before
+ *    it on return, so callers may treat every call as stream-ordered on their
+ *    stream.  Calls marked (sync) also wait for completion.
+ *  - Ownership: the caller owns every buffer it passes.  Inputs are copied
+ *    into library-owned, cell-sorted storage before the call returns
+ *    (stream-ordered); outputs are written in the caller's particle order.
+ *  - Errors: every call returns rbc_status.  Argument errors return before
+ *    any work is enqueued.  Device-side errors (capacity overflow, non-finite
+ *    state, a missed neighbour-list rebuild) are reported by the call that
+ *    observes them.  rbc_last_error() gives text.  A handle is not
+ *    thread-safe.
+ *  - Particle types: 0 = lipid, 1 = spectrin bead, 2 = junction.  Only lipids
+ *    carry an orientation (unit vector) and angular velocity; proteins'
+ *    orientation and angular velocity entries are ignored and returned zero.
+ */
+#ifndef RBC_H
+#define RBC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbc_ctx *rbc_handle;
+
+typedef enum {
+    RBC_OK = 0,
+    RBC_ERR_INVALID_ARG = 1,   /* bad pointer, size or parameter; nothing was enqueued */
+    RBC_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+    RBC_ERR_HIP = 3,           /* HIP runtime error (no device, launch failure, ...) */
+    RBC_ERR_NOT_READY = 4,     /* no system loaded / slot not live */
+    RBC_ERR_CAPACITY = 5,      /* a neighbour or cell-pair list overflowed, or no slot / budget left */
+    RBC_ERR_NONFINITE = 6,     /* NaN or Inf in the state */
+    RBC_ERR_UNSUPPORTED = 7,   /* parameter combination the kernels do not implement */
+    RBC_ERR_SKIN = 8           /* a particle moved beyond the skin before the lists were rebuilt */
+} rbc_status;
+
+typedef enum { RBC_FP64 = 0, RBC_MIXED = 1 } rbc_precision;
+
+/* Model and cell-list parameters (sigma = epsilon = m = 1 units).
+ * rc[t][u]: pair cutoff for types t,u; rc[0][0] is the lipid potential's r_c.
+ * The neighbour set is every pair whose min-image FP64 squared distance,
+ * summed as (dx*dx + dy*dy) + dz*dz with no fused multiply-add, is strictly
+ * below fl(rc*rc).  zeta must be a positive integer (<= 16). */
+typedef struct {
+    double rc[3][3];
+    double eps, zeta, mu, sin_theta0, r_min;   /* lipid orientation-dependent pair law */
+    double wca_eps, wca_sigma;                  /* WCA for pairs involving proteins */
+    double k_bond;                              /* harmonic bonds; rest length per bond */
+    double mass[3];                             /* per type */
+    double inertia;                             /* lipid rotational inertia */
+    int32_t cell_target;                        /* mean lipids per Voronoi cell (k = ceil(N_L / m)) */
+    int32_t update_every;                       /* online-EM cell update period in steps */
+    double skin;                                /* displacement bound between updates (sigma) */
+    int32_t lloyd_iters;                        /* k-means iterations when cells are first built */
+    int32_t precision;                          /* rbc_precision: FP32 pair arithmetic or FP64 */
+} rbc_params;
+
+/* ---- single-system context (an ensemble with one slot) ---- */
+
+/* Create a context on the current HIP device.  hip_stream: the caller's
+ * hipStream_t (0 = the null stream).  No device memory is sized until a system
+ * is set. */
+rbc_status rbc_create(const rbc_params *params, void *hip_stream, rbc_handle *out);
+
+/* Load a system (sync).  [device] x, nrm, v, w: n x 3; type: n; bonds: nbond x 2
+ * particle ids; r0: nbond rest lengths.  [host] box[3] lengths and periodic[3]
+ * flags (1 = periodic axis; box ignored on open axes).  Periodic lengths must
+ * exceed twice the largest cutoff plus skin.  n = 0 clears the context.
+ * Builds the initial Voronoi cells (params.lloyd_iters k-means iterations). */
+rbc_status rbc_set_system(rbc_handle h, int64_t n, const double *x, const double *nrm,
+                          const int32_t *type, const double *v, const double *w,
+                          int64_t nbond, const int32_t *bonds, const double *r0,
+                          const double *box, const int32_t *periodic);
+
+/* Rebuild the cells now.  lloyd_iters > 0: re-seed from the lipids and run that
+ * many k-means iterations first; 0: one online-EM update (assign, move
+ * centroids, Morton reorder, particle reorder, cell and neighbour lists). */
+rbc_status rbc_update_cells(rbc_handle h, int32_t lloyd_iters);
+
+/* Forces and torques at the current positions.  [device] F, T: n x 3 outputs in
+ * caller order (either may be NULL).  [device, nullable] energy: 2 doubles,
+ * potential energy U and scalar virial W = sum over pairs and bonds of
+ * r_ij . F_ij. */
+rbc_status rbc_forces(rbc_handle h, double *F, double *T, double *energy);
+
+/* Advance nsteps of NVE velocity Verlet with time step dt (sync at the end).
+ * Cells are updated every update_every steps and earlier when a particle
+ * could move more than the skin. */
+rbc_status rbc_step(rbc_handle h, int64_t nsteps, double dt);
+
+/* Copy the state out in caller order.  [device] n x 3 each; any may be NULL. */
+rbc_status rbc_get_state(rbc_handle h, double *x, double *nrm, double *v, double *w);
+
+/* The current neighbour set as sorted pairs (i < j) of caller ids (sync).
+ * [host] ij: cap x 2.  *npairs receives the full count even when it exceeds cap. */
+rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs);
+
+/* Energies of the current state (sync).  [host] out[6]: U, W, kinetic energy
+ * (translational + lipid rotational), total E = KE + U, |sum F|, |sum (r x F + tau)|. */
+rbc_status rbc_energy(rbc_handle h, double *out);
+
+/* Counters (sync).  [host] out[8]: steps done, cell updates, early (skin)
+ * updates, cells k, max neighbour-list rows, max cell-pair row, particles n,
+ * lipids. */
+rbc_status rbc_stats(rbc_handle h, int64_t *out);
+
+/* Cell structure for inspection (sync).  [host] owner: n ints, the cell of
+ * each particle in caller order; seeds: k x 3 cell centroids in cell order;
+ * either may be NULL. */
+rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds);
+
+/* Average duration in milliseconds of the pair-force kernel launches since the
+ * last call (measured with HIP events on the library stream around each launch
+ * when timing is enabled), and the number of launches timed. */
+rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_t *launches);
+
+rbc_status rbc_sync(rbc_handle h);
+rbc_status rbc_destroy(rbc_handle h);
+const char *rbc_status_string(rbc_status s);
+const char *rbc_last_error(rbc_handle h);
+
+/* ---- ensemble: continuous batching of independent systems ----
+ * Systems live in slots; every call to rbc_ensemble_step advances all live
+ * slots together with batched launches.  A system's trajectory does not depend
+ * on which other systems share the batch. */
+
+/* max_slots <= 256; hbm_budget_bytes: admission limit on device memory (0 = no limit). */
+rbc_status rbc_ensemble_create(const rbc_params *params, void *hip_stream, int32_t max_slots,
+                               int64_t hbm_budget_bytes, rbc_handle *out);
+/* Device bytes a system of n particles (nlip lipids) and nbond bonds would take. */
+rbc_status rbc_ensemble_footprint(rbc_handle h, int64_t n, int64_t nlip, int64_t nbond, int64_t *bytes);
+/* Admit a system (arrays as rbc_set_system).  Returns RBC_ERR_CAPACITY when no
+ * slot is free or the footprint exceeds the remaining budget; *slot receives
+ * the slot index. */
+rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const double *nrm,
+                              const int32_t *type, const double *v, const double *w,
+                              int64_t nbond, const int32_t *bonds, const double *r0,
+                              const double *box, const int32_t *periodic, int32_t *slot);
+/* Advance every live slot by nsteps (sync at the end). */
+rbc_status rbc_ensemble_step(rbc_handle h, int64_t nsteps, double dt);
+/* State of one slot in its caller order ([device] n x 3 each, any may be NULL). */
+rbc_status rbc_ensemble_get_state(rbc_handle h, int32_t slot, double *x, double *nrm, double *v, double *w);
+/* Energies of one slot ([host] out[6] as rbc_energy). */
+rbc_status rbc_ensemble_energy(rbc_handle h, int32_t slot, double *out);
+/* Free a slot and its memory. */
+rbc_status rbc_ensemble_retire(rbc_handle h, int32_t slot);
+/* [host] out[4]: live slots, device bytes in use, budget, steps done by the ensemble. */
+rbc_status rbc_ensemble_info(rbc_handle h, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

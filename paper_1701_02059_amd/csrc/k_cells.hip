@@ -1,0 +1,940 @@
+// Voronoi ("lattice-free") cell list on gfx950: the online k-means update of the
+// Spatial Searching Algorithm section, batched over every system of a context.
+//
+//   E-step   exact nearest centroid per particle (FP64 distance of the
+//            neighbour-set definition, ties to the lower index), warm-started
+//            from the particle's current cell -- the paper's warm-start
+//            heuristic -- and certified by an expanding search over a uniform
+//            grid of centroids (the GPU stand-in for its k-d tree).
+//   sort     stable LSD radix sort of particles by owning cell (segmented per
+//            system), then a gather of the particle state.
+//   M-step   each centroid moves to the mean of its lipid members.
+//   Morton   centroids ordered along a Morton curve (21 bits per axis), cells
+//            renumbered, and particle blocks moved with their cells: the
+//            two-level reordering.
+//   lists    cell radii, the cell-pair list (sphere test with skin) and
+//            per-particle neighbour lists in 64-particle ELL chunks.
+//
+// Every kernel is predicated on SysScal::rebuild so that one launch serves all
+// systems that update at this step; the others are untouched.
+#include "rbc_dev.h"
+
+namespace rbc {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ int wave_max_int(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Exclusive scan across the block (blockDim.x a multiple of 64, <= 1024).
+__device__ int block_excl_scan(int v, int *s_w, int &total) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int s = (lane < nw) ? s_w[lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(s, o);
+            if (lane >= o) s += y;
+        }
+        if (lane < nw) s_w[lane] = s;
+    }
+    __syncthreads();
+    int base = (w > 0) ? s_w[w - 1] : 0;
+    total = s_w[nw - 1];
+    __syncthreads();
+    return base + x - v;
+}
+
+// In-place exclusive scan of a[0..n) by one block; a[n] receives the total.
+__device__ void block_scan_array(int *a, int n, int *s_w) {
+    int carry = 0;
+    const int per = 4;
+    for (int base = 0; base < n; base += blockDim.x * per) {
+        int v[per];
+        int loc = 0;
+        for (int q = 0; q < per; ++q) {
+            int idx = base + threadIdx.x * per + q;
+            v[q] = (idx < n) ? a[idx] : 0;
+            loc += v[q];
+        }
+        int tot;
+        int ex = block_excl_scan(loc, s_w, tot);
+        int run = carry + ex;
+        for (int q = 0; q < per; ++q) {
+            int idx = base + threadIdx.x * per + q;
+            if (idx < n) a[idx] = run;
+            run += v[q];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) a[n] = carry;
+    __syncthreads();
+}
+
+#define SYS_FROM(map) \
+    const int s = find_sys(L_maps.map, L_maps.nsys, blockIdx.x); \
+    const SysDev &S = Sd[s]; \
+    const int lb = blockIdx.x - L_maps.map[s];
+
+// ------------------------------------------------------------------ rebuild flags
+
+__global__ void k_set_rebuild(const SysDev *Sd, int nsys, unsigned long long m0, unsigned long long m1,
+                              unsigned long long m2, unsigned long long m3) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    unsigned long long w = (s < 64) ? m0 : (s < 128) ? m1 : (s < 192) ? m2 : m3;
+    int bit = (int)((w >> (s & 63)) & 1ull);
+    SysScal *sc = Sd[s].sc;
+    sc->rebuild = bit;
+    if (bit) {
+        sc->rmax = 0ull;
+        sc->nlrows = 0;
+        sc->cnbr_maxrow = 0;
+        sc->err &= ~(ERR_NLIST | ERR_CNBR | ERR_ASSIGN);
+    }
+}
+
+// ------------------------------------------------------------------ packing
+
+__device__ void pack_one(const SysDev &S, const double *x, const double *n, const int32_t *type, const double *v,
+                       const double *w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    const int t = type[i];
+    D4 p = {x[3 * i], x[3 * i + 1], x[3 * i + 2], (double)t};
+    S.pos[i] = p;
+    S.xb[i] = p;
+    S.vel[i] = D4{v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0};
+    if (t == 0) {
+        S.ori[i] = D4{n[3 * i], n[3 * i + 1], n[3 * i + 2], 0.0};
+        S.angv[i] = D4{w[3 * i], w[3 * i + 1], w[3 * i + 2], 0.0};
+    } else {
+        S.ori[i] = D4{0.0, 0.0, 0.0, 0.0};
+        S.angv[i] = D4{0.0, 0.0, 0.0, 0.0};
+    }
+    S.frc[i] = D4{0.0, 0.0, 0.0, 0.0};
+    S.trq[i] = D4{0.0, 0.0, 0.0, 0.0};
+    S.gid[i] = i;
+    S.slot[i] = i;
+    S.owner[i] = -1;
+}
+
+__global__ void k_pack_multi(const SysDev *Sd, int s, const double *x, const double *n, const int32_t *type,
+                             const double *v, const double *w) {
+    pack_one(Sd[s], x, n, type, v, w);
+}
+
+// ------------------------------------------------------------------ seeds from lipids
+
+// Seed j starts at the position of lipid number floor(j * N_L / k) (lipids in id
+// order; `lip` lists their ids).  No warm start for the first assignment.
+__global__ void k_init_seeds(const SysDev *Sd, Maps L_maps, const int32_t *const *lipids) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c < S.k) {
+        long long j = (long long)c * S.nlip / S.k;
+        int g = lipids[s][j];
+        D4 p = S.pos[S.slot[g]];
+        p.x = wrap_coord(p.x, S.per[0], S.box[0]);
+        p.y = wrap_coord(p.y, S.per[1], S.box[1]);
+        p.z = wrap_coord(p.z, S.per[2], S.box[2]);
+        p.w = 0.0;
+        S.seed[c] = p;
+    }
+}
+
+// no warm start for the first assignment after seeding
+__global__ void k_clear_owner(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int i = lb * BLOCK + threadIdx.x;
+    if (i < S.n) S.owner[i] = -1;
+}
+
+// ------------------------------------------------------------------ seed grid
+
+// Bounding boxes and grid geometry, one block per system.
+__global__ void k_grid_setup(const SysDev *Sd, int nsys) {
+    const SysDev &S = Sd[blockIdx.x];
+    if (!S.sc->rebuild) return;
+    __shared__ double s_mn[6][16], s_mx[6][16];
+    double mn[6], mx[6];
+    for (int a = 0; a < 6; ++a) { mn[a] = INFINITY; mx[a] = -INFINITY; }
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        D4 p = S.pos[i];
+        double v[3] = {wrap_coord(p.x, S.per[0], S.box[0]), wrap_coord(p.y, S.per[1], S.box[1]),
+                       wrap_coord(p.z, S.per[2], S.box[2])};
+        for (int a = 0; a < 3; ++a) { mn[a] = fmin(mn[a], v[a]); mx[a] = fmax(mx[a], v[a]); }
+    }
+    for (int c = threadIdx.x; c < S.k; c += blockDim.x) {
+        D4 p = S.seed[c];
+        double v[3] = {p.x, p.y, p.z};
+        for (int a = 0; a < 3; ++a) { mn[3 + a] = fmin(mn[3 + a], v[a]); mx[3 + a] = fmax(mx[3 + a], v[a]); }
+    }
+    for (int a = 0; a < 6; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = fmin(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+        }
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (lane == 0)
+        for (int a = 0; a < 6; ++a) { s_mn[a][w] = mn[a]; s_mx[a][w] = mx[a]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 6; ++a)
+            for (int q = 1; q < nw; ++q) { mn[a] = fmin(mn[a], s_mn[a][q]); mx[a] = fmax(mx[a], s_mx[a][q]); }
+        SysScal *sc = S.sc;
+        double ext[3];
+        for (int a = 0; a < 3; ++a) {
+            // seed box for Morton keys: the box on periodic axes, the seeds' extent otherwise
+            sc->slo[a] = S.per[a] ? 0.0 : mn[3 + a];
+            sc->shi[a] = S.per[a] ? S.box[a] : mx[3 + a];
+            if (S.per[a]) {
+                sc->glo[a] = 0.0;
+                ext[a] = S.box[a];
+            } else {
+                double lo = fmin(mn[a], mn[3 + a]), hi = fmax(mx[a], mx[3 + a]);
+                if (!(lo <= hi)) { lo = 0.0; hi = 0.0; }
+                double pad = 1e-6 * (hi - lo) + 1e-6;
+                sc->glo[a] = lo - pad;
+                ext[a] = (hi - lo) + 2.0 * pad;
+            }
+        }
+        double cap = (double)max(1, S.gcap);
+        double vol = fmax(ext[0], 1.0) * fmax(ext[1], 1.0) * fmax(ext[2], 1.0);
+        double h = fmax(1.0, cbrt(vol / cap));
+        int dims[3];
+        for (int it = 0; it < 200; ++it) {
+            double prod = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                if (S.per[a]) dims[a] = max(1, (int)floor(ext[a] / h));
+                else dims[a] = max(1, (int)ceil(ext[a] / h));
+                prod *= dims[a];
+            }
+            if (prod <= cap) break;
+            h *= 1.1;
+        }
+        if ((double)dims[0] * dims[1] * dims[2] > cap || !isfinite(h)) {
+            dims[0] = dims[1] = dims[2] = 1;
+            h = fmax(ext[0], fmax(ext[1], ext[2]));
+            if (!isfinite(h) || !(h > 0.0)) h = 1.0;
+        }
+        for (int a = 0; a < 3; ++a) {
+            sc->gdim[a] = dims[a];
+            sc->gh[a] = S.per[a] ? ext[a] / dims[a] : h;
+        }
+        sc->gtot = dims[0] * dims[1] * dims[2];
+    }
+}
+
+__device__ __forceinline__ int grid_coord(const SysScal *sc, const SysDev &S, int a, double v, double &u) {
+    u = wrap_coord(v, S.per[a], S.box[a]) - sc->glo[a];
+    int c = (int)floor(u / sc->gh[a]);
+    c = max(0, min(c, sc->gdim[a] - 1));
+    return c;
+}
+
+__global__ void k_grid_clear(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(g);
+    if (!S.sc->rebuild) return;
+    int g = lb * BLOCK + threadIdx.x;
+    if (g < S.gcap) S.gcount[g] = 0;
+}
+
+__global__ void k_grid_count(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    const SysScal *sc = S.sc;
+    D4 p = S.seed[c];
+    double u;
+    int gx = grid_coord(sc, S, 0, p.x, u), gy = grid_coord(sc, S, 1, p.y, u), gz = grid_coord(sc, S, 2, p.z, u);
+    int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
+    S.sgcell[c] = g;
+    atomicAdd(&S.gcount[g], 1);
+}
+
+// which: 0 = seed grid (gcount -> gstart), 1 = cell counts (ccount2 -> cstart2),
+//        2 = cell counts (ccount -> cstart), 3 = cell-pair counts (cnbr_start)
+__global__ void k_scan_sys(const SysDev *Sd, int which) {
+    const SysDev &S = Sd[blockIdx.x];
+    if (!S.sc->rebuild) return;
+    __shared__ int s_w[16];
+    if (which == 0) {
+        int n = S.sc->gtot;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) S.gstart[i] = S.gcount[i];
+        __syncthreads();
+        block_scan_array(S.gstart, n, s_w);
+    } else if (which == 1 || which == 2) {
+        int *src = which == 1 ? S.ccount2 : S.ccount;
+        int *dst = which == 1 ? S.cstart2 : S.cstart;
+        for (int i = threadIdx.x; i < S.k; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+        block_scan_array(dst, S.k, s_w);
+    } else {
+        block_scan_array(S.cnbr_start, S.k, s_w);
+    }
+}
+
+__global__ void k_grid_fill(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    int g = S.sgcell[c];
+    int p = S.gstart[g] + atomicAdd(&S.gcount[g], 1);
+    S.gseed[p] = c;
+}
+
+// Seeds inside a grid cell in ascending index order (deterministic scans).
+__global__ void k_grid_sortcells(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(g);
+    if (!S.sc->rebuild) return;
+    int g = lb * BLOCK + threadIdx.x;
+    if (g >= S.sc->gtot) return;
+    int b = S.gstart[g], e = S.gstart[g + 1];
+    for (int i = b + 1; i < e; ++i) {
+        int v = S.gseed[i];
+        int j = i - 1;
+        while (j >= b && S.gseed[j] > v) { S.gseed[j + 1] = S.gseed[j]; --j; }
+        S.gseed[j + 1] = v;
+    }
+}
+
+void launch_grid_build(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_grid_setup, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_grid_clear, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_grid_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 0);
+    hipLaunchKernelGGL(k_grid_clear, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_grid_fill, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_grid_sortcells, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
+}
+
+// ------------------------------------------------------------------ E-step
+
+// Per-axis window of grid offsets searched at radius r: open axes are clipped at
+// the grid edge, periodic axes stop growing once every cell is covered.
+__device__ __forceinline__ void axis_window(int c, int dim, int per, int r, int &lo, int &hi) {
+    if (per) {
+        int half = (dim - 1) / 2;
+        lo = -min(r, half);
+        hi = min(r, dim - 1 - half);
+    } else {
+        lo = max(-r, -c);
+        hi = min(r, dim - 1 - c);
+    }
+}
+
+__device__ int nearest_seed(const SysDev &S, const SysScal *sc, double xi, double yi, double zi, int warm,
+                            double &bestd2) {
+    int best = -1;
+    bestd2 = INFINITY;
+    double dx, dy, dz;
+    if (warm >= 0 && warm < S.k) {
+        D4 c = S.seed[warm];
+        bestd2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
+        best = warm;
+    }
+    double u[3];
+    int cc[3];
+    cc[0] = grid_coord(sc, S, 0, xi, u[0]);
+    cc[1] = grid_coord(sc, S, 1, yi, u[1]);
+    cc[2] = grid_coord(sc, S, 2, zi, u[2]);
+    int plo[3] = {1, 1, 1}, phi[3] = {-1, -1, -1};
+    int rmax = max(sc->gdim[0], max(sc->gdim[1], sc->gdim[2]));
+    for (int r = 0; r <= rmax; ++r) {
+        int lo[3], hi[3];
+        bool grew = false;
+        for (int a = 0; a < 3; ++a) {
+            axis_window(cc[a], sc->gdim[a], S.per[a], r, lo[a], hi[a]);
+            if (lo[a] < plo[a] || hi[a] > phi[a]) grew = true;
+        }
+        if (!grew) break;   // every cell visited
+        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+            bool nx = (ox < plo[0] || ox > phi[0]);
+            int gx = cc[0] + ox;
+            if (S.per[0]) gx = (gx % sc->gdim[0] + sc->gdim[0]) % sc->gdim[0];
+            for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+                bool ny = nx || (oy < plo[1] || oy > phi[1]);
+                int gy = cc[1] + oy;
+                if (S.per[1]) gy = (gy % sc->gdim[1] + sc->gdim[1]) % sc->gdim[1];
+                for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+                    bool nz = ny || (oz < plo[2] || oz > phi[2]);
+                    if (!nz) continue;   // visited at a smaller radius
+                    int gz = cc[2] + oz;
+                    if (S.per[2]) gz = (gz % sc->gdim[2] + sc->gdim[2]) % sc->gdim[2];
+                    int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
+                    for (int q = S.gstart[g]; q < S.gstart[g + 1]; ++q) {
+                        int sd = S.gseed[q];
+                        D4 c = S.seed[sd];
+                        double d2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
+                        if (d2 < bestd2 || (d2 == bestd2 && sd < best)) { bestd2 = d2; best = sd; }
+                    }
+                }
+            }
+        }
+        for (int a = 0; a < 3; ++a) { plo[a] = lo[a]; phi[a] = hi[a]; }
+        // distance from the particle to the nearest cell not yet visited
+        double m = INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            int dim = sc->gdim[a];
+            bool full = S.per[a] ? (hi[a] - lo[a] + 1 >= dim) : false;
+            if (full) continue;
+            bool lo_open = S.per[a] ? true : (cc[a] + lo[a] > 0);
+            bool hi_open = S.per[a] ? true : (cc[a] + hi[a] < dim - 1);
+            if (lo_open) m = fmin(m, u[a] - (double)(cc[a] + lo[a]) * sc->gh[a]);
+            if (hi_open) m = fmin(m, (double)(cc[a] + hi[a] + 1) * sc->gh[a] - u[a]);
+        }
+        if (m == INFINITY) break;
+        if (best >= 0 && m > 0.0) {
+            double mm = m * (1.0 - 1e-9);
+            if (bestd2 < mm * mm) break;
+        }
+    }
+    return best;
+}
+
+__global__ void k_assign(const SysDev *Sd, Maps L_maps, int warm) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int i = lb * BLOCK + threadIdx.x;
+    if (i >= S.n) return;
+    D4 p = S.pos[i];
+    double d2;
+    int best = nearest_seed(S, S.sc, p.x, p.y, p.z, warm ? S.owner[i] : -1, d2);
+    if (best < 0) { atomicOr(&S.sc->err, ERR_ASSIGN); best = 0; }
+    S.key[i] = (uint64_t)best;
+    S.val[i] = (uint32_t)i;
+}
+
+void launch_assign(const LaunchCtx &L, int warm) {
+    hipLaunchKernelGGL(k_assign, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, warm);
+}
+
+// ------------------------------------------------------------------ segmented stable radix sort
+
+// kind 0: particles (S.n keys, tiles map tp); kind 1: seeds (S.k keys, map ts).
+__global__ __launch_bounds__(BLOCK) void k_sort_hist(const SysDev *Sd, Maps L_maps, int kind, int pass) {
+    const int32_t *map = kind ? L_maps.ts : L_maps.tp;
+    const int s = find_sys(map, L_maps.nsys, blockIdx.x);
+    const SysDev &S = Sd[s];
+    if (!S.sc->rebuild) return;
+    const int tile = blockIdx.x - map[s];
+    const int cnt = kind ? S.k : S.n;
+    const uint64_t *keys = (pass & 1) ? S.key2 : S.key;
+    const int shift = 8 * pass;
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int base = tile * SORT_TILE;
+    for (int r = 0; r < SORT_IPT; ++r) {
+        int idx = base + r * BLOCK + threadIdx.x;
+        if (idx < cnt) atomicAdd(&h[(int)((keys[idx] >> shift) & 255ull)], 1);
+    }
+    __syncthreads();
+    S.hist[tile * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_sort_scan(const SysDev *Sd, int kind) {
+    const SysDev &S = Sd[blockIdx.x];
+    if (!S.sc->rebuild) return;
+    const int cnt = kind ? S.k : S.n;
+    const int ntile = (cnt + SORT_TILE - 1) / SORT_TILE;
+    __shared__ int s_w[16];
+    const int d = threadIdx.x;
+    int run = 0;
+    for (int t = 0; t < ntile; ++t) {
+        int c = S.hist[t * 256 + d];
+        S.hist[t * 256 + d] = run;
+        run += c;
+    }
+    int tot;
+    int base = block_excl_scan(run, s_w, tot);
+    for (int t = 0; t < ntile; ++t) S.hist[t * 256 + d] += base;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sort_scatter(const SysDev *Sd, Maps L_maps, int kind, int pass) {
+    const int32_t *map = kind ? L_maps.ts : L_maps.tp;
+    const int s = find_sys(map, L_maps.nsys, blockIdx.x);
+    const SysDev &S = Sd[s];
+    if (!S.sc->rebuild) return;
+    const int tile = blockIdx.x - map[s];
+    const int cnt = kind ? S.k : S.n;
+    const uint64_t *kin = (pass & 1) ? S.key2 : S.key;
+    const uint32_t *vin = (pass & 1) ? S.val2 : S.val;
+    uint64_t *kout = (pass & 1) ? S.key : S.key2;
+    uint32_t *vout = (pass & 1) ? S.val : S.val2;
+    const int shift = 8 * pass;
+    __shared__ int s_base[256];
+    __shared__ int s_cnt[BLOCK / WAVE][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    s_base[tid] = S.hist[tile * 256 + tid];
+    const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < SORT_IPT; ++r) {
+        for (int q = tid; q < (BLOCK / WAVE) * 256; q += BLOCK) s_cnt[q >> 8][q & 255] = 0;
+        __syncthreads();
+        int idx = tile * SORT_TILE + r * BLOCK + tid;
+        bool valid = idx < cnt;
+        uint64_t k = valid ? kin[idx] : 0ull;
+        uint32_t v = valid ? vin[idx] : 0u;
+        int d = (int)((k >> shift) & 255ull);
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            unsigned long long mb = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? mb : ~mb;
+        }
+        int rank = __popcll(peers & lt);
+        if (valid && rank == 0) s_cnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int pre = 0;
+            for (int q = 0; q < w; ++q) pre += s_cnt[q][d];
+            int pos = s_base[d] + pre + rank;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) add += s_cnt[q][tid];
+        s_base[tid] += add;
+        __syncthreads();
+    }
+}
+
+static void sort_segments(const LaunchCtx &L, int kind, int key_bits) {
+    int passes = (key_bits + 7) / 8;
+    if (passes & 1) ++passes;           // even: the result lands back in key/val
+    int nblk = kind ? L.nblk_ts : L.nblk_tp;
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(BLOCK), 0, L.st, L.S, L.maps, kind, p);
+        hipLaunchKernelGGL(k_sort_scan, dim3(L.nsys), dim3(256), 0, L.st, L.S, kind);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(BLOCK), 0, L.st, L.S, L.maps, kind, p);
+    }
+}
+
+void launch_sort_particles(const LaunchCtx &L, int key_bits) { sort_segments(L, 0, key_bits); }
+
+// ------------------------------------------------------------------ gather / commit
+
+// new slot j takes old slot val[j]; owner of j is key[j]
+__global__ void k_gather(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int j = lb * BLOCK + threadIdx.x;
+    if (j >= S.n) return;
+    int src = (int)S.val[j];
+    S.pos2[j] = S.pos[src];
+    S.vel2[j] = S.vel[src];
+    S.ori2[j] = S.ori[src];
+    S.angv2[j] = S.angv[src];
+    S.gid2[j] = S.gid[src];
+}
+
+// copy the gathered state back; owner from key (mode 0) or val (mode 1)
+__global__ void k_commit(const SysDev *Sd, Maps L_maps, int mode) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int j = lb * BLOCK + threadIdx.x;
+    if (j >= S.n) return;
+    S.pos[j] = S.pos2[j];
+    S.vel[j] = S.vel2[j];
+    S.ori[j] = S.ori2[j];
+    S.angv[j] = S.angv2[j];
+    int g = S.gid2[j];
+    S.gid[j] = g;
+    S.slot[g] = j;
+    S.owner[j] = mode ? (int)S.val[j] : (int)S.key[j];
+}
+
+void launch_gather_particles(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_gather, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_commit, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, 0);
+}
+
+// ------------------------------------------------------------------ cell ranges
+
+__global__ void k_cell_clear(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c < S.k) S.ccount[c] = 0;
+}
+
+__global__ void k_cell_count(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int i = lb * BLOCK + threadIdx.x;
+    if (i < S.n) atomicAdd(&S.ccount[S.owner[i]], 1);
+}
+
+void launch_cell_ranges(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_cell_clear, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_cell_count, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 2);
+}
+
+// ------------------------------------------------------------------ M-step
+
+// Each centroid with lipid members moves by the mean min-image offset of those
+// members (summed in slot order); centroids without lipids stay; periodic axes wrap.
+__global__ void k_mstep(const SysDev *Sd, Maps L_maps) {
+#pragma clang fp contract(off)
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    D4 sd = S.seed[c];
+    double sx = 0, sy = 0, sz = 0;
+    int cnt = 0;
+    int b = S.cstart[c], e = b + S.ccount[c];
+    for (int i = b; i < e; ++i) {
+        D4 p = S.pos[i];
+        if (p.w != 0.0) continue;
+        double dx, dy, dz;
+        (void)dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz);
+        sx += dx; sy += dy; sz += dz;
+        ++cnt;
+    }
+    if (cnt > 0) {
+        double inv = (double)cnt;
+        double v[3] = {sd.x + sx / inv, sd.y + sy / inv, sd.z + sz / inv};
+        for (int a = 0; a < 3; ++a)
+            if (S.per[a]) v[a] = v[a] - S.box[a] * floor(v[a] / S.box[a]);
+        sd.x = v[0]; sd.y = v[1]; sd.z = v[2];
+        S.seed[c] = sd;
+    }
+}
+
+void launch_mstep(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_mstep, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+}
+
+// ------------------------------------------------------------------ Morton order of centroids
+
+__global__ void k_seed_bbox(const SysDev *Sd, int nsys) {
+    const SysDev &S = Sd[blockIdx.x];
+    if (!S.sc->rebuild) return;
+    __shared__ double s_mn[3][16], s_mx[3][16];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int c = threadIdx.x; c < S.k; c += blockDim.x) {
+        D4 p = S.seed[c];
+        mn[0] = fmin(mn[0], p.x); mx[0] = fmax(mx[0], p.x);
+        mn[1] = fmin(mn[1], p.y); mx[1] = fmax(mx[1], p.y);
+        mn[2] = fmin(mn[2], p.z); mx[2] = fmax(mx[2], p.z);
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = fmin(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+        }
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (lane == 0) for (int a = 0; a < 3; ++a) { s_mn[a][w] = mn[a]; s_mx[a][w] = mx[a]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            for (int q = 1; q < nw; ++q) { mn[a] = fmin(mn[a], s_mn[a][q]); mx[a] = fmax(mx[a], s_mx[a][q]); }
+            S.sc->slo[a] = S.per[a] ? 0.0 : mn[a];
+            S.sc->shi[a] = S.per[a] ? S.box[a] : mx[a];
+        }
+    }
+}
+
+// 21-bit quantisation per axis, bits interleaved x (most significant), y, z.
+__global__ void k_morton(const SysDev *Sd, Maps L_maps) {
+#pragma clang fp contract(off)
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    D4 p = S.seed[c];
+    double v[3] = {p.x, p.y, p.z};
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        double ext = S.sc->shi[a] - S.sc->slo[a];
+        if (!(ext > 0.0)) { q[a] = 0; continue; }
+        double f = (v[a] - S.sc->slo[a]) / ext;
+        double t = floor(f * 2097152.0);
+        if (t < 0.0) t = 0.0;
+        if (t > 2097151.0) t = 2097151.0;
+        q[a] = (uint64_t)t;
+    }
+    uint64_t key = 0;
+    for (int b = 20; b >= 0; --b)
+        key = (key << 3) | (((q[0] >> b) & 1ull) << 2) | (((q[1] >> b) & 1ull) << 1) | ((q[2] >> b) & 1ull);
+    S.key[c] = key;
+    S.val[c] = (uint32_t)c;
+}
+
+// new cell c' takes old cell val[c']; cmap[old] = new
+__global__ void k_seed_permute(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    int old = (int)S.val[c];
+    S.seed2[c] = S.seed[old];
+    S.ccount2[c] = S.ccount[old];
+    S.cmap[old] = c;
+}
+
+void launch_morton_sort_seeds(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_seed_bbox, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_morton, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    sort_segments(L, 1, 63);
+    hipLaunchKernelGGL(k_seed_permute, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 1);
+}
+
+// particles move with their renumbered cells, keeping their order inside a cell
+__global__ void k_block_permute(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int j = lb * BLOCK + threadIdx.x;
+    if (j >= S.n) return;
+    int c = S.owner[j];
+    int cn = S.cmap[c];
+    int dst = S.cstart2[cn] + (j - S.cstart[c]);
+    S.pos2[dst] = S.pos[j];
+    S.vel2[dst] = S.vel[j];
+    S.ori2[dst] = S.ori[j];
+    S.angv2[dst] = S.angv[j];
+    S.gid2[dst] = S.gid[j];
+    S.val[dst] = (uint32_t)cn;
+}
+
+__global__ void k_cell_commit(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    S.seed[c] = S.seed2[c];
+    S.ccount[c] = S.ccount2[c];
+    S.cstart[c] = S.cstart2[c];
+    if (c == S.k - 1) S.cstart[S.k] = S.cstart2[S.k];
+}
+
+void launch_block_permute(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_block_permute, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_commit, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, 1);
+    hipLaunchKernelGGL(k_cell_commit, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+}
+
+// ------------------------------------------------------------------ cell radii and cell pairs
+
+__global__ void k_cell_bounds(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    D4 sd = S.seed[c];
+    double r2 = 0.0;
+    int b = S.cstart[c], e = b + S.ccount[c];
+    for (int i = b; i < e; ++i) {
+        D4 p = S.pos[i];
+        double dx, dy, dz;
+        r2 = fmax(r2, dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz));
+    }
+    double R = sqrt(r2);
+    S.seed[c].w = R;
+    atomicMax(&S.sc->rmax, dbits(R));
+}
+
+// Cells B paired with A: |minimg(c_A - c_B)| <= R_A + R_B + search + 1e-9 with
+// search = largest (rc + 2 skin).  mode 0 counts, mode 1 writes (grid-scan order).
+__device__ int cell_query(const SysDev &S, const SysScal *sc, int A, double search, int mode, int *out, int cap) {
+    D4 ca = S.seed[A];
+    double Ra = ca.w;
+    double rho = Ra + bitsd(sc->rmax) + search + 1e-9;
+    double xa[3] = {ca.x, ca.y, ca.z};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = wrap_coord(xa[a], S.per[a], S.box[a]) - sc->glo[a];
+        int dim = sc->gdim[a];
+        double fl = floor((u - rho) / sc->gh[a]), fh = floor((u + rho) / sc->gh[a]);
+        if (!(fl > -1e9 && fh < 1e9)) { fl = 0.0; fh = (double)(dim - 1); }   // non-finite: scan the axis
+        int l = (int)fl;
+        int h = (int)fh;
+        if (S.per[a]) {
+            if (h - l + 1 >= dim) { l = 0; h = dim - 1; }
+        } else {
+            l = max(l, 0);
+            h = min(h, dim - 1);
+        }
+        lo[a] = l;
+        hi[a] = h;
+    }
+    int cnt = 0;
+    double dx, dy, dz;
+    for (int gx0 = lo[0]; gx0 <= hi[0]; ++gx0) {
+        int gx = S.per[0] ? ((gx0 % sc->gdim[0]) + sc->gdim[0]) % sc->gdim[0] : gx0;
+        for (int gy0 = lo[1]; gy0 <= hi[1]; ++gy0) {
+            int gy = S.per[1] ? ((gy0 % sc->gdim[1]) + sc->gdim[1]) % sc->gdim[1] : gy0;
+            for (int gz0 = lo[2]; gz0 <= hi[2]; ++gz0) {
+                int gz = S.per[2] ? ((gz0 % sc->gdim[2]) + sc->gdim[2]) % sc->gdim[2] : gz0;
+                int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
+                for (int q = S.gstart[g]; q < S.gstart[g + 1]; ++q) {
+                    int B = S.gseed[q];
+                    D4 cb = S.seed[B];
+                    double d = sqrt(dist2_exact(S, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, dx, dy, dz));
+                    if (d <= Ra + cb.w + search + 1e-9) {
+                        if (mode && cnt < cap) out[cnt] = B;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+__global__ void k_cnbr_count(const SysDev *Sd, Maps L_maps, double search) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    int n = cell_query(S, S.sc, c, search, 0, nullptr, 0);
+    atomicMax(&S.sc->cnbr_maxrow, n);
+    if (n > CNBR_ROW_MAX) {              // keeps the scanned total inside int32
+        atomicOr(&S.sc->err, ERR_CNBR);
+        n = 0;
+    }
+    S.cnbr_start[c] = n;
+}
+
+__global__ void k_cnbr_fill(const SysDev *Sd, Maps L_maps, double search) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    int c = lb * BLOCK + threadIdx.x;
+    if (c >= S.k) return;
+    int total = S.cnbr_start[S.k];
+    if (c == 0) S.sc->cnbr_total = total;
+    if (total > S.cnbr_cap || (S.sc->err & ERR_CNBR)) {
+        if (c == 0) atomicOr(&S.sc->err, ERR_CNBR);
+        return;
+    }
+    int b = S.cnbr_start[c];
+    int room = S.cnbr_start[c + 1] - b;
+    (void)cell_query(S, S.sc, c, search, 1, S.cnbr + b, room);
+}
+
+void launch_cell_bounds(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_cell_bounds, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
+}
+
+void launch_cell_pairs(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_cnbr_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 3);
+    hipLaunchKernelGGL(k_cnbr_fill, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+}
+
+// ------------------------------------------------------------------ neighbour lists
+
+// One wavefront per chunk of 64 consecutive slots: every partner within the list
+// radius (rc + 2 skin of the pair's types) of each particle, found by scanning the
+// particles of every cell paired with the particle's cell.  Column `lane` of the
+// chunk's ELL block holds the partners of slot base + lane, padded with -1.
+__global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    const int chunk = lb * (BLOCK / WAVE) + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (chunk >= S.nchunk) return;
+    if (S.sc->err & ERR_CNBR) {          // no valid cell pairs: publish empty lists
+        if (lane == 0) S.nlk[chunk] = 0;
+        return;
+    }
+    const int i = chunk * CHUNK + lane;
+    const bool valid = i < S.n;
+    int cnt = 0;
+    int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
+    if (valid) {
+        D4 pi = S.pos[i];
+        int ti = (int)pi.w;
+        int A = S.owner[i];
+        for (int q = S.cnbr_start[A]; q < S.cnbr_start[A + 1]; ++q) {
+            int B = S.cnbr[q];
+            int b = S.cstart[B], e = b + S.ccount[B];
+            for (int j = b; j < e; ++j) {
+                if (j == i) continue;
+                D4 pj = S.pos[j];
+                double dx, dy, dz;
+                double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+                if (d2 < P.rl2[ti][(int)pj.w]) {
+                    if (cnt < MAXNB) col[cnt * CHUNK] = j;
+                    ++cnt;
+                }
+            }
+        }
+    }
+    int rows = wave_max_int(cnt);
+    if (rows > MAXNB) {
+        if (lane == 0) atomicOr(&S.sc->err, ERR_NLIST);
+        rows = MAXNB;
+    }
+    for (int r = min(cnt, MAXNB); r < rows; ++r) col[r * CHUNK] = -1;
+    if (lane == 0) {
+        S.nlk[chunk] = rows;
+        atomicMax(&S.sc->nlrows, rows);
+    }
+}
+
+void launch_nlist(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_nlist, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm);
+}
+
+// ------------------------------------------------------------------ finish
+
+__global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int i = lb * BLOCK + threadIdx.x;
+    if (i < S.n) S.xb[i] = S.pos[i];
+}
+
+__global__ void k_finish_sys(const SysDev *Sd, int nsys) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    SysScal *sc = Sd[s].sc;
+    if (!sc->rebuild) return;
+    sc->maxdisp2 = 0ull;
+    sc->maxv2 = 0ull;
+    sc->rebuild = 0;
+}
+
+void launch_finish_update(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_finish_particles, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_finish_sys, dim3((L.nsys + 63) / 64), dim3(64), 0, L.st, L.S, L.nsys);
+}
+
+// ------------------------------------------------------------------ entry points used by the runtime
+
+void launch_set_rebuild(const LaunchCtx &L, const unsigned long long m[4]) {
+    hipLaunchKernelGGL(k_set_rebuild, dim3((L.nsys + 63) / 64), dim3(64), 0, L.st, L.S, L.nsys, m[0], m[1], m[2],
+                       m[3]);
+}
+
+void launch_init_seeds(const LaunchCtx &L, const int32_t *const *lipids) {
+    hipLaunchKernelGGL(k_init_seeds, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, lipids);
+    hipLaunchKernelGGL(k_clear_owner, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+}
+
+void launch_pack(const LaunchCtx &L, int s, const double *x, const double *n, const int32_t *type,
+                 const double *v, const double *w, int count) {
+    hipLaunchKernelGGL(k_pack_multi, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, L.st, L.S, s, x, n, type,
+                       v, w);
+}
+
+}  // namespace rbc

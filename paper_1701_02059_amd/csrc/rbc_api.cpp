@@ -1,0 +1,878 @@
+// Host runtime of librbc: the C ABI declared in include/rbc.h.
+//
+// A context holds up to max_slots independent systems.  Each system owns one
+// device allocation carved into its arrays; a device-side table of system
+// descriptors plus block->system prefix maps lets every kernel launch serve all
+// live systems at once.  The time-step loop is driven from the host with one
+// step of lookahead: after each kick-drift the per-system displacement statistics
+// are copied to pinned memory, and while the force kernel of step s runs the
+// host decides which systems need a cell update before the force of step s+1.
+#include "../../include/rbc.h"
+#include "rbc_dev.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace rbc;
+
+namespace {
+
+constexpr int RING = 8;
+
+struct HostSys {
+    bool live = false;
+    int64_t n = 0, nlip = 0, nbond = 0;
+    int32_t k = 0, nchunk = 0, gcap = 0, cnbr_cap = 0, ntile_p = 0, ntile_s = 0;
+    double box[3] = {0, 0, 0};
+    int32_t per[3] = {0, 0, 0};
+    void *mem = nullptr;
+    size_t bytes = 0;
+    void *pairs_mem = nullptr;
+    int64_t pairs_cap = 0;
+    SysDev dev{};
+    int32_t *lip = nullptr;          // device: lipid ids in id order (the seed list)
+    int64_t steps_since = 0, steps_total = 0, updates = 0, early = 0;
+    bool have_stats = false, rebuilt_last = false;
+    double disp2 = 0.0, v2 = 0.0;
+};
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct rbc_ctx {
+    rbc_params prm{};
+    DevParams dprm{};
+    hipStream_t user = nullptr, st = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int device = 0;
+    int32_t max_slots = 1;
+    int64_t budget = 0, used = 0;
+    bool ensemble = false;
+    std::vector<HostSys> sys;
+    SysDev *d_sys = nullptr;
+    SysScal *d_sc = nullptr;
+    int32_t *d_maps = nullptr;
+    const int32_t **d_lip = nullptr;
+    SysScal *h_ring = nullptr;
+    hipEvent_t ring_ev[RING] = {};
+    int64_t ring_pos = 0;
+    LaunchCtx L{};
+    int32_t nsys = 0;                 // descriptors in use (highest live slot + 1)
+    bool forces_valid = false;
+    int sticky = RBC_OK;
+    std::string err;
+    int64_t ens_steps = 0;
+    // force-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> tb, te;
+    int tcount = 0;
+    double tsum_ms = 0.0;
+    int64_t tlaunches = 0;
+};
+
+namespace {
+
+rbc_status fail(rbc_ctx *h, rbc_status s, const std::string &msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t _e = (call);                                                                   \
+        if (_e != hipSuccess)                                                                     \
+            return fail(h, RBC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e));        \
+    } while (0)
+
+struct Scope {   // orders the library stream after the caller's stream and back
+    rbc_ctx *h;
+    explicit Scope(rbc_ctx *hh) : h(hh) {
+        hipEventRecord(h->ev_in, h->user);
+        hipStreamWaitEvent(h->st, h->ev_in, 0);
+    }
+    ~Scope() {
+        hipEventRecord(h->ev_out, h->st);
+        hipStreamWaitEvent(h->user, h->ev_out, 0);
+    }
+};
+
+bool valid_params(const rbc_params *p, std::string &why) {
+    if (!p) { why = "params is NULL"; return false; }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (!(p->rc[a][b] > 0.0) || p->rc[a][b] != p->rc[b][a]) { why = "rc must be positive and symmetric"; return false; }
+    if (!(p->r_min > 0.0) || !(p->rc[0][0] > p->r_min)) { why = "need 0 < r_min < rc[0][0]"; return false; }
+    double z = p->zeta;
+    if (!(z >= 1.0 && z <= 16.0) || z != std::floor(z)) { why = "zeta must be an integer in [1, 16]"; return false; }
+    for (int a = 0; a < 3; ++a) if (!(p->mass[a] > 0.0)) { why = "masses must be positive"; return false; }
+    if (!(p->inertia > 0.0)) { why = "inertia must be positive"; return false; }
+    if (p->cell_target < 1) { why = "cell_target must be >= 1"; return false; }
+    if (p->update_every < 1) { why = "update_every must be >= 1"; return false; }
+    if (!(p->skin >= 0.0)) { why = "skin must be >= 0"; return false; }
+    if (p->lloyd_iters < 1) { why = "lloyd_iters must be >= 1"; return false; }
+    if (p->precision != RBC_FP64 && p->precision != RBC_MIXED) { why = "unknown precision"; return false; }
+    if (!(p->wca_sigma > 0.0) || !(p->k_bond >= 0.0)) { why = "bad WCA / bond constants"; return false; }
+    return true;
+}
+
+void make_dev_params(rbc_ctx *h) {
+    const rbc_params &p = h->prm;
+    DevParams &d = h->dprm;
+    double search = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            d.rc2[a][b] = p.rc[a][b] * p.rc[a][b];
+            double rl = p.rc[a][b] + 2.0 * p.skin;
+            d.rl2[a][b] = rl * rl * (1.0 + 1e-12);
+            search = std::max(search, rl);
+        }
+    d.rc_lipid = p.rc[0][0];
+    d.r_min = p.r_min;
+    d.eps = p.eps;
+    d.mu = p.mu;
+    d.st0 = p.sin_theta0;
+    d.wca_eps = p.wca_eps;
+    d.wca_sig2 = p.wca_sigma * p.wca_sigma;
+    d.k_bond = p.k_bond;
+    for (int a = 0; a < 3; ++a) d.inv_mass[a] = 1.0 / p.mass[a];
+    d.inv_inertia = 1.0 / p.inertia;
+    d.cell_search = search;
+    d.zeta = (int32_t)p.zeta;
+}
+
+// Sizes of one system and (with base != null) its device layout.
+size_t layout(HostSys &s, char *base) {
+    Carve c{base};
+    const int64_t n = s.n;
+    const int32_t k = s.k;
+    SysDev &d = s.dev;
+    d.pos = c.take<D4>(n); d.vel = c.take<D4>(n); d.ori = c.take<D4>(n); d.angv = c.take<D4>(n);
+    d.frc = c.take<D4>(n); d.trq = c.take<D4>(n); d.xb = c.take<D4>(n);
+    d.pos2 = c.take<D4>(n); d.vel2 = c.take<D4>(n); d.ori2 = c.take<D4>(n); d.angv2 = c.take<D4>(n);
+    d.gid = c.take<int32_t>(n); d.gid2 = c.take<int32_t>(n); d.slot = c.take<int32_t>(n);
+    d.owner = c.take<int32_t>(n);
+    d.key = c.take<uint64_t>(n); d.key2 = c.take<uint64_t>(n);
+    d.val = c.take<uint32_t>(n); d.val2 = c.take<uint32_t>(n);
+    d.hist = c.take<int32_t>((size_t)256 * std::max(s.ntile_p, s.ntile_s));
+    d.seed = c.take<D4>(k); d.seed2 = c.take<D4>(k);
+    d.cstart = c.take<int32_t>(k + 1); d.ccount = c.take<int32_t>(k); d.cstart2 = c.take<int32_t>(k + 1);
+    d.ccount2 = c.take<int32_t>(k); d.cmap = c.take<int32_t>(k);
+    d.cnbr_start = c.take<int32_t>(k + 1); d.cnbr = c.take<int32_t>(s.cnbr_cap);
+    d.gstart = c.take<int32_t>(s.gcap + 1); d.gcount = c.take<int32_t>(s.gcap);
+    d.gseed = c.take<int32_t>(k); d.sgcell = c.take<int32_t>(k);
+    d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
+    d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
+    d.epart = c.take<double>((size_t)s.nchunk * 9);
+    s.lip = c.take<int32_t>(s.nlip);
+    return c.off + 256;
+}
+
+void size_system(const rbc_ctx *h, HostSys &s, int64_t n, int64_t nlip, int64_t nbond) {
+    s.n = n;
+    s.nlip = nlip > 0 ? nlip : n;
+    s.nbond = nbond;
+    const int64_t m = h->prm.cell_target;
+    s.k = (int32_t)std::max<int64_t>(1, (s.nlip + m - 1) / m);
+    s.nchunk = (int32_t)((n + CHUNK - 1) / CHUNK);
+    s.gcap = 8 * s.k + 64;
+    s.cnbr_cap = 96 * s.k + 1024;
+    s.ntile_p = (int32_t)((n + SORT_TILE - 1) / SORT_TILE);
+    s.ntile_s = (s.k + SORT_TILE - 1) / SORT_TILE;
+}
+
+int key_bits(int32_t k) {
+    int b = 1;
+    while ((1ll << b) < (int64_t)k) ++b;
+    return b;
+}
+
+// Rebuild the device descriptor table and the block maps after a membership change.
+rbc_status refresh_tables(rbc_ctx *h) {
+    int top = 0;
+    for (int s = 0; s < h->max_slots; ++s)
+        if (h->sys[s].live) top = s + 1;
+    h->nsys = std::max(top, 1);
+    const int ns = h->nsys;
+    std::vector<SysDev> tab(ns);
+    std::vector<const int32_t *> lips(ns, nullptr);
+    std::vector<int32_t> maps(5 * (ns + 1), 0);
+    int32_t *mp = maps.data(), *mc = mp + (ns + 1), *mg = mc + (ns + 1), *mtp = mg + (ns + 1), *mts = mtp + (ns + 1);
+    for (int s = 0; s < ns; ++s) {
+        HostSys &hs = h->sys[s];
+        SysDev d{};
+        if (hs.live) {
+            d = hs.dev;
+            lips[s] = hs.lip;
+        }
+        d.sc = h->d_sc + s;
+        tab[s] = d;
+        const int64_t n = hs.live ? hs.n : 0;
+        const int32_t k = hs.live ? hs.k : 0;
+        mp[s + 1] = mp[s] + (int32_t)((n + BLOCK - 1) / BLOCK);
+        mc[s + 1] = mc[s] + (k + BLOCK - 1) / BLOCK;
+        mg[s + 1] = mg[s] + (hs.live ? (hs.gcap + BLOCK - 1) / BLOCK : 0);
+        mtp[s + 1] = mtp[s] + (hs.live ? hs.ntile_p : 0);
+        mts[s + 1] = mts[s] + (hs.live ? hs.ntile_s : 0);
+    }
+    HIPCHK(hipMemcpyAsync(h->d_sys, tab.data(), sizeof(SysDev) * ns, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(h->d_maps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(h->d_lip, lips.data(), sizeof(void *) * ns, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));   // host staging vectors go out of scope
+    LaunchCtx &L = h->L;
+    L.S = h->d_sys;
+    L.maps.p = h->d_maps;
+    L.maps.c = h->d_maps + (ns + 1);
+    L.maps.g = h->d_maps + 2 * (ns + 1);
+    L.maps.tp = h->d_maps + 3 * (ns + 1);
+    L.maps.ts = h->d_maps + 4 * (ns + 1);
+    L.maps.nsys = ns;
+    L.nblk_p = mp[ns];
+    L.nblk_c = mc[ns];
+    L.nblk_g = mg[ns];
+    L.nblk_tp = mtp[ns];
+    L.nblk_ts = mts[ns];
+    L.nsys = ns;
+    L.prm = h->dprm;
+    L.st = h->st;
+    return RBC_OK;
+}
+
+bool any_live(const rbc_ctx *h) {
+    for (const auto &s : h->sys)
+        if (s.live) return true;
+    return false;
+}
+
+// Run the cell update for the systems in `mask`.  lloyd > 0: seed from lipids and
+// run that many k-means iterations first.
+void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
+    if (which.empty()) return;
+    unsigned long long m[4] = {0, 0, 0, 0};
+    int32_t kmax = 1;
+    for (int s : which) {
+        m[s >> 6] |= 1ull << (s & 63);
+        kmax = std::max(kmax, h->sys[s].k);
+    }
+    const LaunchCtx &L = h->L;
+    launch_set_rebuild(L, m);
+    const int bits = key_bits(kmax);
+    auto estep_msteps = [&](int iters) {
+        for (int it = 0; it < iters; ++it) {
+            if (it > 0) launch_grid_build(L);
+            launch_assign(L, 1);
+            launch_sort_particles(L, bits);
+            launch_gather_particles(L);
+            launch_cell_ranges(L);
+            launch_mstep(L);
+        }
+    };
+    if (lloyd > 0) {
+        launch_init_seeds(L, h->d_lip);
+        launch_grid_build(L);
+        estep_msteps(lloyd);
+    } else {
+        estep_msteps(1);    // the seed grid of the current centroids is still valid
+    }
+    launch_morton_sort_seeds(L);
+    launch_block_permute(L);
+    launch_grid_build(L);
+    launch_cell_bounds(L);
+    launch_cell_pairs(L);
+    launch_nlist(L);
+    launch_finish_update(L);
+    for (int s : which) {
+        HostSys &hs = h->sys[s];
+        hs.updates++;
+        hs.steps_since = 0;
+    }
+}
+
+rbc_status read_errors(rbc_ctx *h, const SysScal *sc) {
+    for (int s = 0; s < h->nsys; ++s) {
+        if (!h->sys[s].live) continue;
+        int e = sc[s].err;
+        if (e & ERR_NONFINITE) return fail(h, RBC_ERR_NONFINITE, "non-finite positions or velocities in slot " + std::to_string(s));
+        if (e & ERR_NLIST) return fail(h, RBC_ERR_CAPACITY, "a particle has more than 64 neighbours within rc + 2 skin (slot " + std::to_string(s) + ")");
+        if (e & ERR_CNBR) return fail(h, RBC_ERR_CAPACITY, "cell-pair list capacity exceeded (slot " + std::to_string(s) + ")");
+        if (e & ERR_ASSIGN) return fail(h, RBC_ERR_CAPACITY, "nearest-seed search failed (slot " + std::to_string(s) + ")");
+    }
+    return RBC_OK;
+}
+
+rbc_status sync_and_check(rbc_ctx *h) {
+    HIPCHK(hipMemcpyAsync(h->h_ring, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return read_errors(h, h->h_ring);
+}
+
+void force_launch(rbc_ctx *h, int energy, int kick, double dt) {
+    const bool t = h->timing && h->tcount < (int)h->tb.size();
+    if (t) hipEventRecord(h->tb[h->tcount], h->st);
+    launch_force(h->L, h->prm.precision == RBC_MIXED, energy, kick, dt);
+    if (t) {
+        hipEventRecord(h->te[h->tcount], h->st);
+        h->tcount++;
+    }
+}
+
+void harvest_timing(rbc_ctx *h) {
+    for (int q = 0; q < h->tcount; ++q) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->tb[q], h->te[q]) == hipSuccess) {
+            h->tsum_ms += ms;
+            h->tlaunches++;
+        }
+    }
+    h->tcount = 0;
+}
+
+rbc_status ensure_forces(rbc_ctx *h) {
+    if (!h->forces_valid) {
+        force_launch(h, 0, 0, 0.0);
+        h->forces_valid = true;
+    }
+    return RBC_OK;
+}
+
+// The time-step loop over every live system.
+rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
+    if (!any_live(h)) return RBC_OK;
+    ensure_forces(h);
+    const double skin = h->prm.skin;
+    const int64_t K = h->prm.update_every;
+    rbc_status out = RBC_OK;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        launch_kick_drift(h->L, dt);
+        const int slot = (int)(h->ring_pos % RING);
+        h->ring_pos++;
+        SysScal *ring = h->h_ring + (size_t)slot * MAX_SLOTS;
+        hipMemcpyAsync(ring, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st);
+        hipEventRecord(h->ring_ev[slot], h->st);
+        // decide which systems update before this step's force, from the previous step's statistics
+        std::vector<int> which;
+        for (int s = 0; s < h->nsys; ++s) {
+            HostSys &hs = h->sys[s];
+            if (!hs.live) continue;
+            hs.steps_since++;
+            bool need = hs.steps_since >= K;
+            if (!need && hs.have_stats) {
+                double pred = (hs.rebuilt_last ? 0.0 : std::sqrt(hs.disp2)) + 2.0 * dt * std::sqrt(hs.v2);
+                if (pred > 0.9 * skin) {
+                    need = true;
+                    hs.early++;
+                }
+            }
+            if (need) which.push_back(s);
+        }
+        run_update(h, which, 0);
+        force_launch(h, 0, 1, dt);
+        // while the force runs, read this step's kick-drift statistics
+        hipEventSynchronize(h->ring_ev[slot]);
+        for (int s = 0; s < h->nsys; ++s) {
+            HostSys &hs = h->sys[s];
+            if (!hs.live) continue;
+            const bool rebuilt = std::find(which.begin(), which.end(), s) != which.end();
+            double d2;
+            std::memcpy(&d2, &ring[s].maxdisp2, sizeof(double));
+            double v2;
+            std::memcpy(&v2, &ring[s].maxv2, sizeof(double));
+            if (!rebuilt && d2 > skin * skin && out == RBC_OK)
+                out = fail(h, RBC_ERR_SKIN, "a particle moved beyond the skin before its lists were rebuilt (slot " + std::to_string(s) + ")");
+            hs.disp2 = d2;
+            hs.v2 = std::max(v2, hs.rebuilt_last ? 0.0 : hs.v2);
+            hs.have_stats = true;
+            hs.rebuilt_last = rebuilt;
+            hs.steps_total++;
+        }
+        if (h->tcount >= (int)h->tb.size()) {
+            HIPCHK(hipStreamSynchronize(h->st));
+            harvest_timing(h);
+        }
+    }
+    h->ens_steps += nsteps;
+    rbc_status e = sync_and_check(h);
+    harvest_timing(h);
+    if (e != RBC_OK) return e;
+    return out;
+}
+
+size_t footprint(const rbc_ctx *h, int64_t n, int64_t nlip, int64_t nbond) {
+    HostSys tmp;
+    size_system(h, tmp, n, nlip, nbond);
+    return layout(tmp, nullptr);
+}
+
+rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const double *nrm, const int32_t *type,
+                 const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
+                 const double *box, const int32_t *periodic) {
+    if (n < 0 || n > (1ll << 30)) return fail(h, RBC_ERR_INVALID_ARG, "n out of range");
+    if (n > 0 && (!x || !nrm || !type || !v || !w)) return fail(h, RBC_ERR_INVALID_ARG, "NULL state array");
+    if (nbond < 0 || (nbond > 0 && (!bonds || !r0))) return fail(h, RBC_ERR_INVALID_ARG, "bad bond arrays");
+    if (!box || !periodic) return fail(h, RBC_ERR_INVALID_ARG, "box and periodic are required");
+    double search = h->dprm.cell_search;
+    for (int a = 0; a < 3; ++a) {
+        if (periodic[a] != 0 && periodic[a] != 1) return fail(h, RBC_ERR_INVALID_ARG, "periodic flags must be 0 or 1");
+        if (periodic[a] && !(box[a] > 2.0 * search))
+            return fail(h, RBC_ERR_INVALID_ARG, "periodic box length must exceed twice the largest cutoff plus skin");
+    }
+    HostSys &hs = h->sys[slot];
+    // type histogram and bond topology are needed on the host
+    std::vector<int32_t> ht(n);
+    std::vector<int32_t> hb(2 * nbond);
+    std::vector<double> hr(nbond);
+    if (n > 0) HIPCHK(hipMemcpy(ht.data(), type, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (nbond > 0) {
+        HIPCHK(hipMemcpy(hb.data(), bonds, sizeof(int32_t) * 2 * nbond, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hr.data(), r0, sizeof(double) * nbond, hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> lip;
+    for (int64_t i = 0; i < n; ++i) {
+        if (ht[i] < 0 || ht[i] > 2) return fail(h, RBC_ERR_INVALID_ARG, "particle type must be 0, 1 or 2");
+        if (ht[i] == 0) lip.push_back((int32_t)i);
+    }
+    if (lip.empty())
+        for (int64_t i = 0; i < n; ++i) lip.push_back((int32_t)i);   // no lipids: seed from every particle
+    for (int64_t e = 0; e < nbond; ++e)
+        if (hb[2 * e] < 0 || hb[2 * e] >= n || hb[2 * e + 1] < 0 || hb[2 * e + 1] >= n || hb[2 * e] == hb[2 * e + 1])
+            return fail(h, RBC_ERR_INVALID_ARG, "bond index out of range");
+    HostSys fresh;
+    size_system(h, fresh, n, (int64_t)lip.size(), nbond);
+    const size_t bytes = layout(fresh, nullptr);
+    if (h->budget > 0 && h->used + (int64_t)bytes > h->budget)
+        return fail(h, RBC_ERR_CAPACITY, "footprint exceeds the remaining device-memory budget");
+    void *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(h, RBC_ERR_OUT_OF_MEMORY, "device allocation failed");
+    if (hipMemset(mem, 0, bytes) != hipSuccess) {
+        hipFree(mem);
+        return fail(h, RBC_ERR_HIP, "hipMemset of a new system failed");
+    }
+    fresh.mem = mem;
+    fresh.bytes = bytes;
+    layout(fresh, (char *)mem);
+    fresh.live = true;
+    for (int a = 0; a < 3; ++a) {
+        fresh.box[a] = periodic[a] ? box[a] : 0.0;
+        fresh.per[a] = periodic[a];
+    }
+    SysDev &d = fresh.dev;
+    d.n = (int32_t)n;
+    d.nlip = (int32_t)fresh.nlip;
+    d.k = fresh.k;
+    d.nchunk = fresh.nchunk;
+    d.gcap = fresh.gcap;
+    d.cnbr_cap = fresh.cnbr_cap;
+    d.ntile_p = fresh.ntile_p;
+    d.ntile_s = fresh.ntile_s;
+    for (int a = 0; a < 3; ++a) { d.per[a] = fresh.per[a]; d.box[a] = fresh.box[a]; }
+    // bond CSR by caller id
+    std::vector<int32_t> bst(n + 1, 0), bpa(2 * nbond);
+    std::vector<double> br(2 * nbond);
+    for (int64_t e = 0; e < nbond; ++e) { bst[hb[2 * e] + 1]++; bst[hb[2 * e + 1] + 1]++; }
+    for (int64_t i = 0; i < n; ++i) bst[i + 1] += bst[i];
+    std::vector<int32_t> fill(n, 0);
+    for (int64_t e = 0; e < nbond; ++e) {
+        int32_t a = hb[2 * e], b = hb[2 * e + 1];
+        int32_t pa = bst[a] + fill[a]++, pb = bst[b] + fill[b]++;
+        bpa[pa] = b; br[pa] = hr[e];
+        bpa[pb] = a; br[pb] = hr[e];
+    }
+    HIPCHK(hipMemcpy(d.bstart, bst.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+    if (nbond > 0) {
+        HIPCHK(hipMemcpy(d.bpart, bpa.data(), sizeof(int32_t) * 2 * nbond, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d.br0, br.data(), sizeof(double) * 2 * nbond, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(fresh.lip, lip.data(), sizeof(int32_t) * lip.size(), hipMemcpyHostToDevice));
+    SysScal zero{};
+    HIPCHK(hipMemcpy(h->d_sc + slot, &zero, sizeof(SysScal), hipMemcpyHostToDevice));
+    hs = fresh;
+    h->used += (int64_t)bytes;
+    rbc_status r = refresh_tables(h);
+    if (r != RBC_OK) return r;
+    {
+        Scope sc(h);
+        launch_pack(h->L, slot, x, nrm, type, v, w, (int)n);
+        run_update(h, std::vector<int>{slot}, h->prm.lloyd_iters);
+        hs.steps_since = 0;
+        hs.have_stats = false;
+        hs.updates = 1;
+        h->forces_valid = false;
+    }
+    return sync_and_check(h);
+}
+
+void release(rbc_ctx *h, int32_t slot) {
+    HostSys &hs = h->sys[slot];
+    if (!hs.live) return;
+    hipStreamSynchronize(h->st);
+    if (hs.mem) hipFree(hs.mem);
+    if (hs.pairs_mem) hipFree(hs.pairs_mem);
+    h->used -= (int64_t)hs.bytes;
+    hs = HostSys{};
+    refresh_tables(h);
+}
+
+rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int64_t budget, bool ensemble,
+                  rbc_handle *out) {
+    rbc_ctx *h = nullptr;
+    if (!out) return RBC_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::string why;
+    if (!valid_params(params, why)) return RBC_ERR_INVALID_ARG;
+    if (max_slots < 1 || max_slots > MAX_SLOTS || budget < 0) return RBC_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return RBC_ERR_HIP;
+    h = new rbc_ctx();
+    h->prm = *params;
+    make_dev_params(h);
+    h->max_slots = max_slots;
+    h->budget = budget;
+    h->ensemble = ensemble;
+    h->sys.resize(max_slots);
+    h->user = (hipStream_t)stream;
+    hipGetDevice(&h->device);
+    bool ok = hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(&h->d_sys, sizeof(SysDev) * max_slots) == hipSuccess &&
+              hipMalloc(&h->d_sc, sizeof(SysScal) * max_slots) == hipSuccess &&
+              hipMalloc(&h->d_maps, sizeof(int32_t) * 5 * (max_slots + 1)) == hipSuccess &&
+              hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
+              hipHostMalloc((void **)&h->h_ring, sizeof(SysScal) * MAX_SLOTS * RING, hipHostMallocDefault) == hipSuccess;
+    for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->ring_ev[q], hipEventDisableTiming) == hipSuccess;
+    if (ok) ok = hipMemset(h->d_sc, 0, sizeof(SysScal) * max_slots) == hipSuccess;
+    if (ok) ok = refresh_tables(h) == RBC_OK;
+    if (!ok) {
+        rbc_destroy(h);
+        return RBC_ERR_HIP;
+    }
+    *out = h;
+    return RBC_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char *rbc_status_string(rbc_status s) {
+    switch (s) {
+        case RBC_OK: return "ok";
+        case RBC_ERR_INVALID_ARG: return "invalid argument";
+        case RBC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case RBC_ERR_HIP: return "HIP runtime error";
+        case RBC_ERR_NOT_READY: return "no system loaded";
+        case RBC_ERR_CAPACITY: return "capacity exceeded";
+        case RBC_ERR_NONFINITE: return "non-finite state";
+        case RBC_ERR_UNSUPPORTED: return "unsupported parameters";
+        case RBC_ERR_SKIN: return "skin exceeded before a cell update";
+    }
+    return "unknown status";
+}
+
+const char *rbc_last_error(rbc_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+rbc_status rbc_create(const rbc_params *params, void *hip_stream, rbc_handle *out) {
+    return create(params, hip_stream, 1, 0, false, out);
+}
+
+rbc_status rbc_ensemble_create(const rbc_params *params, void *hip_stream, int32_t max_slots, int64_t hbm_budget_bytes,
+                               rbc_handle *out) {
+    return create(params, hip_stream, max_slots, hbm_budget_bytes, true, out);
+}
+
+rbc_status rbc_destroy(rbc_handle h) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (h->st) hipStreamSynchronize(h->st);
+    for (int s = 0; s < (int)h->sys.size(); ++s) {
+        if (h->sys[s].mem) hipFree(h->sys[s].mem);
+        if (h->sys[s].pairs_mem) hipFree(h->sys[s].pairs_mem);
+    }
+    for (auto e : h->tb) hipEventDestroy(e);
+    for (auto e : h->te) hipEventDestroy(e);
+    for (int q = 0; q < RING; ++q) if (h->ring_ev[q]) hipEventDestroy(h->ring_ev[q]);
+    if (h->d_sys) hipFree(h->d_sys);
+    if (h->d_sc) hipFree(h->d_sc);
+    if (h->d_maps) hipFree(h->d_maps);
+    if (h->d_lip) hipFree(h->d_lip);
+    if (h->h_ring) hipHostFree(h->h_ring);
+    if (h->ev_in) hipEventDestroy(h->ev_in);
+    if (h->ev_out) hipEventDestroy(h->ev_out);
+    if (h->st) hipStreamDestroy(h->st);
+    delete h;
+    return RBC_OK;
+}
+
+rbc_status rbc_set_system(rbc_handle h, int64_t n, const double *x, const double *nrm, const int32_t *type,
+                          const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
+                          const double *box, const int32_t *periodic) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (h->ensemble) return fail(h, RBC_ERR_INVALID_ARG, "use rbc_ensemble_admit on an ensemble context");
+    release(h, 0);
+    h->forces_valid = false;
+    h->sticky = RBC_OK;
+    if (n == 0) return RBC_OK;
+    return admit(h, 0, n, x, nrm, type, v, w, nbond, bonds, r0, box, periodic);
+}
+
+rbc_status rbc_update_cells(rbc_handle h, int32_t lloyd_iters) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (lloyd_iters < 0) return fail(h, RBC_ERR_INVALID_ARG, "lloyd_iters must be >= 0");
+    if (!any_live(h)) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    std::vector<int> which;
+    for (int s = 0; s < h->nsys; ++s)
+        if (h->sys[s].live) which.push_back(s);
+    {
+        Scope sc(h);
+        run_update(h, which, lloyd_iters);
+        for (int s : which) h->sys[s].have_stats = false;
+        h->forces_valid = false;
+    }
+    return sync_and_check(h);
+}
+
+static rbc_status forces_slot(rbc_handle h, int32_t slot, double *F, double *T, double *energy) {
+    HostSys &hs = h->sys[slot];
+    {
+        Scope sc(h);
+        force_launch(h, energy != nullptr, 0, 0.0);
+        h->forces_valid = true;
+        launch_scatter_forces(h->L, slot, F, T, (int)hs.n);
+        if (energy) {
+            launch_reduce_energy(h->L);
+            // U and W are the first two entries of the system's energy record
+            hipMemcpyAsync(energy, &h->d_sc[slot].energy[0], 2 * sizeof(double), hipMemcpyDeviceToDevice, h->st);
+        }
+    }
+    return RBC_OK;
+}
+
+rbc_status rbc_forces(rbc_handle h, double *F, double *T, double *energy) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (!h->sys[0].live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    return forces_slot(h, 0, F, T, energy);
+}
+
+rbc_status rbc_step(rbc_handle h, int64_t nsteps, double dt) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(h, RBC_ERR_INVALID_ARG, "need nsteps >= 0 and dt > 0");
+    if (!any_live(h)) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    rbc_status r;
+    {
+        Scope sc(h);
+        r = step_all(h, nsteps, dt);
+    }
+    return r;
+}
+
+rbc_status rbc_ensemble_step(rbc_handle h, int64_t nsteps, double dt) { return rbc_step(h, nsteps, dt); }
+
+static rbc_status state_slot(rbc_handle h, int32_t slot, double *x, double *nrm, double *v, double *w) {
+    if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
+    Scope sc(h);
+    launch_scatter_state(h->L, slot, x, nrm, v, w, (int)h->sys[slot].n);
+    return RBC_OK;
+}
+
+rbc_status rbc_get_state(rbc_handle h, double *x, double *nrm, double *v, double *w) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    return state_slot(h, 0, x, nrm, v, w);
+}
+
+rbc_status rbc_ensemble_get_state(rbc_handle h, int32_t slot, double *x, double *nrm, double *v, double *w) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    return state_slot(h, slot, x, nrm, v, w);
+}
+
+rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs) {
+    if (!h || !npairs || cap < 0 || (cap > 0 && !ij)) return RBC_ERR_INVALID_ARG;
+    HostSys &hs = h->sys[0];
+    if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    int64_t want = std::max<int64_t>(1024, 32 * hs.n);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (hs.pairs_cap < want) {
+            if (hs.pairs_mem) { hipStreamSynchronize(h->st); hipFree(hs.pairs_mem); }
+            hs.pairs_mem = nullptr;
+            if (hipMalloc(&hs.pairs_mem, sizeof(int32_t) * 2 * want) != hipSuccess)
+                return fail(h, RBC_ERR_OUT_OF_MEMORY, "pair export buffer");
+            hs.pairs_cap = want;
+            hs.dev.pairs = (int32_t *)hs.pairs_mem;
+            hs.dev.pairs_cap = want;
+            rbc_status r = refresh_tables(h);
+            if (r != RBC_OK) return r;
+        }
+        int32_t count = 0;
+        {
+            Scope sc(h);
+            HIPCHK(hipMemsetAsync(&h->d_sc[0].npairs, 0, sizeof(int32_t), h->st));
+            launch_export_pairs(h->L, 0, (int)hs.n);
+            HIPCHK(hipMemcpyAsync(&count, &h->d_sc[0].npairs, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+        }
+        if (count > hs.pairs_cap) { want = count; continue; }
+        std::vector<int32_t> buf(2 * (size_t)count);
+        if (count > 0) HIPCHK(hipMemcpy(buf.data(), hs.pairs_mem, sizeof(int32_t) * 2 * count, hipMemcpyDeviceToHost));
+        std::vector<int64_t> keys(count);
+        for (int32_t q = 0; q < count; ++q) keys[q] = ((int64_t)buf[2 * q] << 32) | (uint32_t)buf[2 * q + 1];
+        std::sort(keys.begin(), keys.end());
+        const int64_t m = std::min<int64_t>(cap, count);
+        for (int64_t q = 0; q < m; ++q) {
+            ij[2 * q] = (int32_t)(keys[q] >> 32);
+            ij[2 * q + 1] = (int32_t)(keys[q] & 0xffffffff);
+        }
+        *npairs = count;
+        return RBC_OK;
+    }
+    return fail(h, RBC_ERR_CAPACITY, "pair export overflow");
+}
+
+static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
+    if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
+    {
+        Scope sc(h);
+        force_launch(h, 1, 0, 0.0);
+        h->forces_valid = true;
+        launch_reduce_energy(h->L);
+    }
+    rbc_status r = sync_and_check(h);
+    if (r != RBC_OK) return r;
+    const double *e = h->h_ring[slot].energy;
+    out[0] = e[0];
+    out[1] = e[1];
+    out[2] = e[2];
+    out[3] = e[0] + e[2];
+    out[4] = std::sqrt(e[3] * e[3] + e[4] * e[4] + e[5] * e[5]);
+    out[5] = std::sqrt(e[6] * e[6] + e[7] * e[7] + e[8] * e[8]);
+    return RBC_OK;
+}
+
+rbc_status rbc_energy(rbc_handle h, double *out) {
+    if (!h || !out) return RBC_ERR_INVALID_ARG;
+    return energy_slot(h, 0, out);
+}
+
+rbc_status rbc_ensemble_energy(rbc_handle h, int32_t slot, double *out) {
+    if (!h || !out) return RBC_ERR_INVALID_ARG;
+    return energy_slot(h, slot, out);
+}
+
+rbc_status rbc_stats(rbc_handle h, int64_t *out) {
+    if (!h || !out) return RBC_ERR_INVALID_ARG;
+    HostSys &hs = h->sys[0];
+    if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    rbc_status r = sync_and_check(h);
+    if (r != RBC_OK) return r;
+    out[0] = hs.steps_total;
+    out[1] = hs.updates;
+    out[2] = hs.early;
+    out[3] = hs.k;
+    out[4] = h->h_ring[0].nlrows;
+    out[5] = h->h_ring[0].cnbr_maxrow;
+    out[6] = hs.n;
+    out[7] = hs.nlip;
+    return RBC_OK;
+}
+
+rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    HostSys &hs = h->sys[0];
+    if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (owner) {
+        std::vector<int32_t> own(hs.n), gid(hs.n);
+        HIPCHK(hipMemcpy(own.data(), hs.dev.owner, sizeof(int32_t) * hs.n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(gid.data(), hs.dev.gid, sizeof(int32_t) * hs.n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < hs.n; ++i) owner[gid[i]] = own[i];
+    }
+    if (seeds) {
+        std::vector<D4> sd(hs.k);
+        HIPCHK(hipMemcpy(sd.data(), hs.dev.seed, sizeof(D4) * hs.k, hipMemcpyDeviceToHost));
+        for (int32_t c = 0; c < hs.k; ++c) {
+            seeds[3 * c] = sd[c].x;
+            seeds[3 * c + 1] = sd[c].y;
+            seeds[3 * c + 2] = sd[c].z;
+        }
+    }
+    return RBC_OK;
+}
+
+rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_t *launches) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(h->st));
+    harvest_timing(h);
+    if (avg_ms) *avg_ms = h->tlaunches ? h->tsum_ms / (double)h->tlaunches : 0.0;
+    if (launches) *launches = h->tlaunches;
+    h->tsum_ms = 0.0;
+    h->tlaunches = 0;
+    h->timing = enable != 0;
+    if (h->timing && h->tb.empty()) {
+        h->tb.resize(256);
+        h->te.resize(256);
+        for (int q = 0; q < 256; ++q) {
+            hipEventCreate(&h->tb[q]);
+            hipEventCreate(&h->te[q]);
+        }
+    }
+    return RBC_OK;
+}
+
+rbc_status rbc_sync(rbc_handle h) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    return sync_and_check(h);
+}
+
+rbc_status rbc_ensemble_footprint(rbc_handle h, int64_t n, int64_t nlip, int64_t nbond, int64_t *bytes) {
+    if (!h || !bytes || n <= 0 || nlip < 0 || nlip > n || nbond < 0) return RBC_ERR_INVALID_ARG;
+    *bytes = (int64_t)footprint(h, n, nlip, nbond);
+    return RBC_OK;
+}
+
+rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const double *nrm, const int32_t *type,
+                              const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
+                              const double *box, const int32_t *periodic, int32_t *slot) {
+    if (!h || !slot) return RBC_ERR_INVALID_ARG;
+    if (n <= 0) return fail(h, RBC_ERR_INVALID_ARG, "an admitted system needs n > 0");
+    int32_t free_slot = -1;
+    for (int s = 0; s < h->max_slots; ++s)
+        if (!h->sys[s].live) { free_slot = s; break; }
+    if (free_slot < 0) return fail(h, RBC_ERR_CAPACITY, "no free slot");
+    rbc_status r = admit(h, free_slot, n, x, nrm, type, v, w, nbond, bonds, r0, box, periodic);
+    if (r == RBC_OK) *slot = free_slot;
+    else release(h, free_slot);
+    return r;
+}
+
+rbc_status rbc_ensemble_retire(rbc_handle h, int32_t slot) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
+    release(h, slot);
+    return RBC_OK;
+}
+
+rbc_status rbc_ensemble_info(rbc_handle h, int64_t *out) {
+    if (!h || !out) return RBC_ERR_INVALID_ARG;
+    int64_t live = 0;
+    for (const auto &s : h->sys) live += s.live;
+    out[0] = live;
+    out[1] = h->used;
+    out[2] = h->budget;
+    out[3] = h->ens_steps;
+    return RBC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Internal declarations shared by the HIP kernels and the host runtime of librbc.
+// gfx950 only: 64-lane wavefronts, FP64 at full vector rate.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rbc {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;            // threads per block for particle / cell kernels
+constexpr int CHUNK = 64;             // particles per neighbour-list chunk (one wavefront)
+constexpr int MAXNB = 64;             // neighbour-list rows per chunk
+constexpr int SORT_IPT = 16;          // items per thread in the radix sort
+constexpr int SORT_TILE = BLOCK * SORT_IPT;
+constexpr int MAX_SLOTS = 256;
+constexpr int CNBR_ROW_MAX = 2048;      // cell pairs per cell before the build reports overflow
+
+// error bits in SysScal::err
+constexpr int ERR_NLIST = 1;          // a particle had more than MAXNB list neighbours
+constexpr int ERR_CNBR = 2;           // cell-pair list capacity exceeded
+constexpr int ERR_NONFINITE = 4;      // NaN / Inf in positions or velocities
+constexpr int ERR_ASSIGN = 8;         // nearest-seed search found no seed
+
+struct alignas(16) D4 {
+    double x, y, z, w;
+};
+
+// Per-system scalars living in device memory.
+struct alignas(256) SysScal {
+    unsigned long long maxdisp2;      // bits of the largest |x - x_build|^2 since the last build
+    unsigned long long maxv2;         // bits of the largest |v|^2 used in a drift since the build
+    unsigned long long rmax;          // bits of the largest cell radius
+    int32_t err;
+    int32_t rebuild;                  // this system takes part in the running cell update
+    int32_t nlrows;                   // largest neighbour-list row count of the last build
+    int32_t cnbr_total;
+    int32_t cnbr_maxrow;
+    int32_t npairs;
+    int32_t pad0, pad1;
+    double slo[3], shi[3];            // seed bounding box (Morton quantisation)
+    double glo[3], gh[3];             // seed-grid origin and spacing
+    int32_t gdim[3];
+    int32_t gtot;
+    double energy[9];                 // U, W, KE, sum F (3), sum r x F + tau (3)
+};
+
+// One system (slot): sizes and device arrays.  Particle arrays are in cell-sorted
+// slot order; `gid` maps a slot to the caller's particle id, `slot` the inverse.
+struct SysDev {
+    int32_t n, nlip, k, nchunk, gcap, cnbr_cap, ntile_p, ntile_s;
+    int32_t per[3];
+    int32_t pad;
+    double box[3];
+    D4 *pos, *vel, *ori, *angv, *frc, *trq, *xb;   // pos.w = particle type
+    D4 *pos2, *vel2, *ori2, *angv2;
+    int32_t *gid, *gid2, *slot, *owner;
+    uint64_t *key, *key2;
+    uint32_t *val, *val2;
+    int32_t *hist;                                  // sort histograms: tiles x 256
+    D4 *seed, *seed2;                               // centroid xyz, w = cell radius
+    int32_t *cstart, *ccount, *cstart2, *ccount2, *cmap;
+    int32_t *cnbr_start, *cnbr;                     // full cell-pair CSR (k+1, cnbr_cap)
+    int32_t *gstart, *gcount, *gseed, *sgcell;      // seed grid (gcap+1, gcap, k, k)
+    int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
+    int32_t *bstart, *bpart;                        // bonds by caller id (n+1, 2 nbond)
+    double *br0;
+    double *epart;                                  // per-chunk energy partials (nchunk x 9)
+    int32_t *pairs;                                 // scratch for exporting the pair set
+    int64_t pairs_cap;
+    SysScal *sc;
+};
+
+// Model constants, passed by value to kernels.
+struct DevParams {
+    double rc2[3][3];      // fl(rc*rc): exact neighbour test
+    double rl2[3][3];      // (rc + 2 skin)^2 with a small relative margin: list radius
+    double rc_lipid, r_min, eps, mu, st0, wca_eps, wca_sig2, k_bond;
+    double inv_mass[3];
+    double inv_inertia;
+    double cell_search;    // largest rc + 2 skin (cell-pair test slack)
+    int32_t zeta;
+    int32_t pad;
+};
+
+// Block -> system maps: off[s] = first block of system s, off[nsys] = total blocks.
+struct Maps {
+    const int32_t *p;      // particle blocks (BLOCK particles, also 4 chunks)
+    const int32_t *c;      // cell blocks
+    const int32_t *g;      // seed-grid cell blocks
+    const int32_t *tp;     // particle sort tiles
+    const int32_t *ts;     // seed sort tiles
+    int32_t nsys;
+};
+
+__device__ __forceinline__ int find_sys(const int32_t *off, int nsys, int b) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Min-image difference and squared distance exactly as the neighbour-set
+// definition states: per periodic axis q = d/L, k = rint(q) (half to even),
+// d - (k*L) with the product rounded; then (dx*dx + dy*dy) + dz*dz with every
+// operation rounded (no contraction into fused multiply-adds).
+__device__ __forceinline__ double minimg1(double d, int per, double L) {
+#pragma clang fp contract(off)
+    if (per) {
+        double q = d / L;
+        double k = __builtin_rint(q);
+        double kl = k * L;
+        d = d - kl;
+    }
+    return d;
+}
+
+__device__ __forceinline__ double dist2_exact(const SysDev &S, double xi, double yi, double zi,
+                                              double xj, double yj, double zj,
+                                              double &dx, double &dy, double &dz) {
+#pragma clang fp contract(off)
+    dx = minimg1(xi - xj, S.per[0], S.box[0]);
+    dy = minimg1(yi - yj, S.per[1], S.box[1]);
+    dz = minimg1(zi - zj, S.per[2], S.box[2]);
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double s = xx + yy;
+    return s + zz;
+}
+
+__device__ __forceinline__ double wrap_coord(double v, int per, double L) {
+    if (!per) return v;
+    double w = v - L * floor(v / L);
+    if (w >= L) w -= L;
+    if (w < 0) w = 0;
+    return w;
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v) {
+    return (unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ double bitsd(unsigned long long b) {
+    return __longlong_as_double((long long)b);
+}
+
+}  // namespace rbc
+
+// ---------------------------------------------------------------- launch API (host)
+namespace rbc {
+
+struct LaunchCtx {
+    const SysDev *S;         // device array of systems
+    Maps maps;
+    int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts;   // totals over systems
+    int32_t nsys;
+    DevParams prm;
+    hipStream_t st;
+};
+
+// step kernels
+void launch_kick_drift(const LaunchCtx &L, double dt);
+void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt);
+void launch_reduce_energy(const LaunchCtx &L);
+void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count);
+void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, int count);
+void launch_export_pairs(const LaunchCtx &L, int sys, int count);
+// cell update kernels (each predicated on SysScal::rebuild)
+void launch_set_rebuild(const LaunchCtx &L, const unsigned long long m[4]);
+void launch_init_seeds(const LaunchCtx &L, const int32_t *const *lipids);
+void launch_grid_build(const LaunchCtx &L);
+void launch_assign(const LaunchCtx &L, int warm);
+void launch_sort_particles(const LaunchCtx &L, int key_bits);
+void launch_gather_particles(const LaunchCtx &L);
+void launch_cell_ranges(const LaunchCtx &L);
+void launch_mstep(const LaunchCtx &L);
+void launch_morton_sort_seeds(const LaunchCtx &L);
+void launch_block_permute(const LaunchCtx &L);
+void launch_cell_bounds(const LaunchCtx &L);
+void launch_cell_pairs(const LaunchCtx &L);
+void launch_nlist(const LaunchCtx &L);
+void launch_finish_update(const LaunchCtx &L);
+void launch_pack(const LaunchCtx &L, int sys, const double *x, const double *n, const int32_t *type,
+                 const double *v, const double *w, int count);
+
+}  // namespace rbc
