@@ -1,0 +1,212 @@
+#!/usr/bin/env python
+"""Benchmark: particle-steps/s of the whole-cell workload on one MI355X.
+
+Workload: the whole red cell, 3,999,952 particles (3.6M lipids on an Evans-Fung
+biconcave surface, 16,000 junctions and 383,952 spectrin beads in a triangular
+network of 8-bead chains under it), NVE velocity Verlet with dt = 0.01 tau and
+Voronoi cell updates every 100 steps (earlier when the skin demands).  The
+headline value is mixed precision (FP32 pair arithmetic, FP64 positions,
+integration and sums); plain FP64 is reported beside it, with the pair-force
+kernel's roofline fraction, the FP64 CPU oracle timed on this host's cores, and
+the continuous-batching serving ensemble (p50/p99 step latency).
+
+One JSON line on stdout; progress on stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DT = 0.01
+# Algorithmic work per force launch (operation counts of the pair laws as
+# written: add/sub/mul 1 flop each, FMA 2, sqrt/rsqrt/sin/cos/div 1).
+FLOPS_LIPID_PAIR = 147      # per unordered lipid pair: F_i, F_j, tau_i, tau_j, U, W and the distance test
+FLOPS_WCA_PAIR = 37         # per unordered pair with a protein bead
+FLOPS_BOND = 28             # per bond
+BYTES_MIXED = 56            # per particle: 32 B position/type + orientation in, 24 B force + torque out
+BYTES_FP64 = 112            # per particle in FP64
+PEAK_FP32 = 157.3           # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
+PEAK_FP64 = 78.6            # TFLOP/s, MI355X FP64 vector
+PEAK_HBM = 8000.0           # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pair_counts(ctx, system):
+    pairs = ctx.get_pairs()
+    t = system.type
+    ll = int(np.sum((t[pairs[:, 0]] == 0) & (t[pairs[:, 1]] == 0)))
+    return ll, int(pairs.shape[0] - ll)
+
+
+def timed_run(R, mp, system, precision, steps, warmup, label):
+    import torch
+    ctx = R.Context(mp, precision)
+    t0 = time.perf_counter()
+    ctx.set_system(system)
+    log(f"[{label}] cells built in {time.perf_counter() - t0:.2f} s: {ctx.stats()}")
+    ctx.step(warmup, DT)
+    torch.cuda.synchronize()
+    ctx.force_timing(True)
+    st0 = ctx.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps, DT)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    avg_ms, launches = ctx.force_timing(False)
+    st1 = ctx.stats()
+    e = ctx.energy()
+    out = {"seconds": t1 - t0, "ms_per_step": (t1 - t0) * 1e3 / steps,
+           "particle_steps_per_s": system.N * steps / (t1 - t0),
+           "force_ms": avg_ms, "force_launches": launches,
+           "cell_updates": st1["updates"] - st0["updates"], "early_updates": st1["early_updates"] - st0["early_updates"],
+           "max_list_rows": st1["max_list_rows"], "energy": e.tolist()}
+    log(f"[{label}] {steps} steps in {t1 - t0:.3f} s -> {out['particle_steps_per_s']:.4g} particle-steps/s, "
+        f"force kernel {avg_ms * 1e3:.1f} us avg over {launches} launches, {out['cell_updates']} cell updates")
+    return ctx, out
+
+
+def cpu_baseline(system, mp):
+    """FP64 oracle on this host: velocity-Verlet steps of the full cell (difference of a
+    3-step and a 1-step run, so the initial force evaluation is not counted)."""
+    from oracle import oracle as O
+    p = O.params_for(system, mp)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    t0 = time.perf_counter()
+    O.vv_run(p, system, DT, 1, nthreads=threads)
+    t1 = time.perf_counter()
+    O.vv_run(p, system, DT, 3, nthreads=threads)
+    t2 = time.perf_counter()
+    per_step = ((t2 - t1) - (t1 - t0)) / 2.0
+    if per_step <= 0:
+        per_step = (t2 - t1) / 4.0
+    return {"value": system.N / per_step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"2 velocity-Verlet steps of the full {system.N:,}-particle cell (3-step minus 1-step run, "
+                      f"{(t2 - t0):.1f} s of CPU work)", "seconds_per_step": per_step}
+
+
+def serving_run(R, mp, count, rate, steps, saturated=False):
+    from paper_1701_02059_amd import inputs as I
+    from paper_1701_02059_amd import serving as SV
+    reqs = I.serving_requests(count, rate=rate, steps=steps)
+    if saturated:
+        for r in reqs:
+            r["arrival"] = 0.0
+    t0 = time.perf_counter()
+    systems = {r["id"]: I.build_request(r, params=mp) for r in reqs}
+    log(f"[serving] built {count} requests in {time.perf_counter() - t0:.1f} s "
+        f"({sum(s.N for s in systems.values()):,} particles)")
+    ens = R.Ensemble(mp, R.RBC_MIXED, max_slots=128, hbm_budget=96 << 30)
+    st = SV.serve(reqs, systems, ens, dt=DT, chunk=10)
+    ens.close()
+    s = st.summary()
+    log(f"[serving{' saturated' if saturated else ''}] {s}")
+    return s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--workload", default="rbc4m")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-steps", type=int, default=500)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1701_02059_amd import inputs as I
+    from paper_1701_02059_amd import rbc as R
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    R.lib()
+    mp = I.ModelParams()
+    t0 = time.perf_counter()
+    system = I.config(args.workload)
+    log(f"[gen] {args.workload}: N={system.N:,} {system.counts()} in {time.perf_counter() - t0:.1f} s")
+
+    ctx, mixed = timed_run(R, mp, system, R.RBC_MIXED, args.steps, args.warmup, "mixed")
+    n_ll, n_wca = pair_counts(ctx, system)
+    n_bond = int(system.bonds.shape[0])
+    ctx.close()
+    flops = FLOPS_LIPID_PAIR * n_ll + FLOPS_WCA_PAIR * n_wca + FLOPS_BOND * n_bond
+    t_force = mixed["force_ms"] * 1e-3
+    achieved = flops / t_force / 1e12
+    bytes_alg = BYTES_MIXED * system.N
+    t_roof = max(flops / (PEAK_FP32 * 1e12), bytes_alg / (PEAK_HBM * 1e9))
+    bound = "alu" if flops / (PEAK_FP32 * 1e12) >= bytes_alg / (PEAK_HBM * 1e9) else "hbm"
+    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32, 4), "traffic": None,
+            "kernel": "k_force<mixed,kick> (pair force + bonds + half-kick)",
+            "flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_alg,
+            "avg_launch_us": round(mixed["force_ms"] * 1e3, 2), "launches_timed": mixed["force_launches"],
+            "roofline_time_us": round(t_roof * 1e6, 2), "time_frac": round(t_roof / t_force, 4),
+            "lipid_pairs": n_ll, "wca_pairs": n_wca, "bonds": n_bond}
+    log(f"[roofline] {roof}")
+
+    fp64 = None
+    if not args.no_fp64:
+        ctx64, fp64 = timed_run(R, mp, system, R.RBC_FP64, args.fp64_steps, min(args.warmup, 10), "fp64")
+        ctx64.close()
+        fp64["force_tflops"] = flops / (fp64["force_ms"] * 1e-3) / 1e12
+        fp64["force_frac_fp64_peak"] = fp64["force_tflops"] / PEAK_FP64
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(system, mp)
+        log(f"[cpu] {cpu}")
+
+    serving = None
+    if not args.no_serving:
+        serving = serving_run(R, mp, args.serving_requests, 20.0, args.serving_steps)
+
+    line = {
+        "metric": "particle-steps/s at 4M-particle RBC; p50/p99 batched-ensemble step latency",
+        "value": mixed["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic / f64 state",
+        "data": "synthetic (seeded generator; no dataset)",
+        "config": {"workload": f"whole-RBC biconcave cell ({args.workload}), {system.N:,} particles: "
+                               f"{system.counts()['L']:,} lipids, {system.counts()['J']:,} junctions, "
+                               f"{system.counts()['S']:,} spectrin beads; dt={DT}, NVE, cells updated every "
+                               f"{mp.update_every} steps, skin {mp.skin}",
+                   "particles": system.N, "precision": "mixed", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "mixed": mixed,
+        "serving": serving,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
