@@ -139,6 +139,14 @@ rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds);
  * when timing is enabled), and the number of launches timed. */
 rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_t *launches);
 
+/* Internal cell-list arrays of the single system, for inspection and tests (sync).
+ * which: 0 owner (n, slot order), 1 cell start (k+1), 2 cell count (k), 3 cell-pair
+ * row start (k+1), 4 cell-pair entries (row start[k]), 5 seed-grid start (cells+1),
+ * 6 seeds in grid order (k), 7 centroids with radius (k x 4 doubles), 8 list rows per
+ * 64-particle chunk, 9 staged count per 256-particle block, 10 caller id per slot (n).
+ * Integer arrays are int32.  [host] out receives at most cap bytes; *bytes the full size. */
+rbc_status rbc_debug_array(rbc_handle h, int32_t which, int64_t cap, void *out, int64_t *bytes);
+
 rbc_status rbc_sync(rbc_handle h);
 rbc_status rbc_destroy(rbc_handle h);
 const char *rbc_status_string(rbc_status s);

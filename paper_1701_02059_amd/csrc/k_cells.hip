@@ -19,6 +19,8 @@
 // systems that update at this step; the others are untouched.
 #include "rbc_dev.h"
 
+#include <climits>
+
 namespace rbc {
 
 // ------------------------------------------------------------------ helpers
@@ -164,18 +166,47 @@ __global__ void k_clear_owner(const SysDev *Sd, Maps L_maps) {
 
 // ------------------------------------------------------------------ seed grid
 
-// Bounding boxes and grid geometry, one block per system.
+// Per-block bounding boxes of the (wrapped) particle positions: BRED partials 2..7.
+__global__ __launch_bounds__(BLOCK) void k_bbox_partial(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    __shared__ double s_v[6][BLOCK / WAVE];
+    const int i = lb * BLOCK + threadIdx.x;
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (i < S.n) {
+        D4 p = S.pos[i];
+        double v[3] = {wrap_coord(p.x, S.per[0], S.box[0]), wrap_coord(p.y, S.per[1], S.box[1]),
+                       wrap_coord(p.z, S.per[2], S.box[2])};
+        for (int a = 0; a < 3; ++a) { mn[a] = v[a]; mx[a] = v[a]; }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = fmin(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+        }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) { s_v[a][w] = mn[a]; s_v[3 + a][w] = mx[a]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        double r = s_v[a][0];
+        for (int q = 1; q < BLOCK / WAVE; ++q) r = (a < 3) ? fmin(r, s_v[a][q]) : fmax(r, s_v[a][q]);
+        S.bred[(size_t)lb * BRED + 2 + a] = r;
+    }
+}
+
+// Bounding boxes and grid geometry, one block per system (from the per-block partials).
 __global__ void k_grid_setup(const SysDev *Sd, int nsys) {
     const SysDev &S = Sd[blockIdx.x];
     if (!S.sc->rebuild) return;
     __shared__ double s_mn[6][16], s_mx[6][16];
     double mn[6], mx[6];
     for (int a = 0; a < 6; ++a) { mn[a] = INFINITY; mx[a] = -INFINITY; }
-    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
-        D4 p = S.pos[i];
-        double v[3] = {wrap_coord(p.x, S.per[0], S.box[0]), wrap_coord(p.y, S.per[1], S.box[1]),
-                       wrap_coord(p.z, S.per[2], S.box[2])};
-        for (int a = 0; a < 3; ++a) { mn[a] = fmin(mn[a], v[a]); mx[a] = fmax(mx[a], v[a]); }
+    const int nblk = (S.n + BLOCK - 1) / BLOCK;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        const double *r = S.bred + (size_t)b * BRED + 2;
+        for (int a = 0; a < 3; ++a) { mn[a] = fmin(mn[a], r[a]); mx[a] = fmax(mx[a], r[3 + a]); }
     }
     for (int c = threadIdx.x; c < S.k; c += blockDim.x) {
         D4 p = S.seed[c];
@@ -266,25 +297,105 @@ __global__ void k_grid_count(const SysDev *Sd, Maps L_maps) {
     atomicAdd(&S.gcount[g], 1);
 }
 
-// which: 0 = seed grid (gcount -> gstart), 1 = cell counts (ccount2 -> cstart2),
-//        2 = cell counts (ccount -> cstart), 3 = cell-pair counts (cnbr_start)
-__global__ void k_scan_sys(const SysDev *Sd, int which) {
+// Segmented exclusive scans, three launches (tile sums, per-system scan of the
+// tile sums, tile scans), specialised at compile time per array.  WHICH: 0 = seed
+// grid (gcount -> gstart over gtot cells), 1 = ccount2 -> cstart2, 2 = ccount ->
+// cstart, 3 = cnbr_start in place (k cells).  dst[len] receives the total.
+template <int WHICH>
+__device__ __forceinline__ const int *scan_src(const SysDev &S) {
+    if constexpr (WHICH == 0) return S.gcount;
+    else if constexpr (WHICH == 1) return S.ccount2;
+    else if constexpr (WHICH == 2) return S.ccount;
+    else return S.cnbr_start;
+}
+template <int WHICH>
+__device__ __forceinline__ int *scan_dst(const SysDev &S) {
+    if constexpr (WHICH == 0) return S.gstart;
+    else if constexpr (WHICH == 1) return S.cstart2;
+    else if constexpr (WHICH == 2) return S.cstart;
+    else return S.cnbr_start;
+}
+template <int WHICH>
+__device__ __forceinline__ int scan_len(const SysDev &S) {
+    if constexpr (WHICH == 0) return S.sc->gtot;
+    else return S.k;
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(BLOCK) void k_scan_a(const SysDev *Sd, Maps L_maps) {
+    const int32_t *map = WHICH == 0 ? L_maps.sg : L_maps.sc;
+    const int s = find_sys(map, L_maps.nsys, blockIdx.x);
+    const SysDev &S = Sd[s];
+    if (!S.sc->rebuild) return;
+    const int tile = blockIdx.x - map[s];
+    const int *src = scan_src<WHICH>(S);
+    const int len = scan_len<WHICH>(S);
+    __shared__ int s_w[16];
+    constexpr int per = SCAN_TILE / BLOCK;
+    int loc = 0;
+    for (int q = 0; q < per; ++q) {
+        const int idx = tile * SCAN_TILE + threadIdx.x * per + q;
+        if (idx < len) loc += src[idx];
+    }
+    int tot;
+    (void)block_excl_scan(loc, s_w, tot);
+    if (threadIdx.x == 0) S.tsum[tile] = tot;
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(1024) void k_scan_b(const SysDev *Sd) {
     const SysDev &S = Sd[blockIdx.x];
     if (!S.sc->rebuild) return;
     __shared__ int s_w[16];
-    if (which == 0) {
-        int n = S.sc->gtot;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) S.gstart[i] = S.gcount[i];
-        __syncthreads();
-        block_scan_array(S.gstart, n, s_w);
-    } else if (which == 1 || which == 2) {
-        int *src = which == 1 ? S.ccount2 : S.ccount;
-        int *dst = which == 1 ? S.cstart2 : S.cstart;
-        for (int i = threadIdx.x; i < S.k; i += blockDim.x) dst[i] = src[i];
-        __syncthreads();
-        block_scan_array(dst, S.k, s_w);
-    } else {
-        block_scan_array(S.cnbr_start, S.k, s_w);
+    const int ntile = (scan_len<WHICH>(S) + SCAN_TILE - 1) / SCAN_TILE;
+    block_scan_array(S.tsum, ntile, s_w);
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(BLOCK) void k_scan_c(const SysDev *Sd, Maps L_maps) {
+    const int32_t *map = WHICH == 0 ? L_maps.sg : L_maps.sc;
+    const int s = find_sys(map, L_maps.nsys, blockIdx.x);
+    const SysDev &S = Sd[s];
+    if (!S.sc->rebuild) return;
+    const int tile = blockIdx.x - map[s];
+    const int *src = scan_src<WHICH>(S);
+    int *dst = scan_dst<WHICH>(S);
+    const int len = scan_len<WHICH>(S);
+    const int ntile = (len + SCAN_TILE - 1) / SCAN_TILE;
+    if (tile >= ntile) return;
+    __shared__ int s_w[16];
+    constexpr int per = SCAN_TILE / BLOCK;
+    int v[per];
+    int loc = 0;
+    for (int q = 0; q < per; ++q) {
+        const int idx = tile * SCAN_TILE + threadIdx.x * per + q;
+        v[q] = (idx < len) ? src[idx] : 0;
+        loc += v[q];
+    }
+    int tot;
+    int run = S.tsum[tile] + block_excl_scan(loc, s_w, tot);
+    for (int q = 0; q < per; ++q) {
+        const int idx = tile * SCAN_TILE + threadIdx.x * per + q;
+        if (idx < len) dst[idx] = run;
+        run += v[q];
+    }
+    if (tile == ntile - 1 && threadIdx.x == 0) dst[len] = S.tsum[ntile];
+}
+
+template <int WHICH>
+static void launch_scan_t(const LaunchCtx &L) {
+    const int nblk = WHICH == 0 ? L.nblk_sg : L.nblk_sc;
+    hipLaunchKernelGGL(k_scan_a<WHICH>, dim3(nblk), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_scan_b<WHICH>, dim3(L.nsys), dim3(1024), 0, L.st, L.S);
+    hipLaunchKernelGGL(k_scan_c<WHICH>, dim3(nblk), dim3(BLOCK), 0, L.st, L.S, L.maps);
+}
+
+static void launch_scan(const LaunchCtx &L, int which) {
+    switch (which) {
+        case 0: launch_scan_t<0>(L); break;
+        case 1: launch_scan_t<1>(L); break;
+        case 2: launch_scan_t<2>(L); break;
+        default: launch_scan_t<3>(L); break;
     }
 }
 
@@ -314,10 +425,11 @@ __global__ void k_grid_sortcells(const SysDev *Sd, Maps L_maps) {
 }
 
 void launch_grid_build(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_bbox_partial, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_setup, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys);
     hipLaunchKernelGGL(k_grid_clear, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 0);
+    launch_scan(L, 0);
     hipLaunchKernelGGL(k_grid_clear, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_fill, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_sortcells, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
@@ -455,11 +567,15 @@ __global__ __launch_bounds__(256) void k_sort_scan(const SysDev *Sd, int kind) {
     const int ntile = (cnt + SORT_TILE - 1) / SORT_TILE;
     __shared__ int s_w[16];
     const int d = threadIdx.x;
+    constexpr int B = 16;            // tiles per batch: independent loads in flight
     int run = 0;
-    for (int t = 0; t < ntile; ++t) {
-        int c = S.hist[t * 256 + d];
-        S.hist[t * 256 + d] = run;
-        run += c;
+    for (int t0 = 0; t0 < ntile; t0 += B) {
+        int c[B];
+        for (int q = 0; q < B; ++q) c[q] = (t0 + q < ntile) ? S.hist[(t0 + q) * 256 + d] : 0;
+        for (int q = 0; q < B; ++q) {
+            if (t0 + q < ntile) S.hist[(t0 + q) * 256 + d] = run;
+            run += c[q];
+        }
     }
     int tot;
     int base = block_excl_scan(run, s_w, tot);
@@ -583,7 +699,7 @@ __global__ void k_cell_count(const SysDev *Sd, Maps L_maps) {
 void launch_cell_ranges(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_cell_clear, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_cell_count, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 2);
+    launch_scan(L, 2);
 }
 
 // ------------------------------------------------------------------ M-step
@@ -695,7 +811,7 @@ void launch_morton_sort_seeds(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_morton, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     sort_segments(L, 1, 63);
     hipLaunchKernelGGL(k_seed_permute, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 1);
+    launch_scan(L, 1);
 }
 
 // particles move with their renumbered cells, keeping their order inside a cell
@@ -739,17 +855,21 @@ __global__ void k_cell_bounds(const SysDev *Sd, Maps L_maps) {
     if (!S.sc->rebuild) return;
     int c = lb * BLOCK + threadIdx.x;
     if (c >= S.k) return;
-    D4 sd = S.seed[c];
-    double r2 = 0.0;
-    int b = S.cstart[c], e = b + S.ccount[c];
-    for (int i = b; i < e; ++i) {
-        D4 p = S.pos[i];
-        double dx, dy, dz;
-        r2 = fmax(r2, dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz));
+    double R = 0.0;
+    if (c < S.k) {
+        D4 sd = S.seed[c];
+        double r2 = 0.0;
+        int b = S.cstart[c], e = b + S.ccount[c];
+        for (int i = b; i < e; ++i) {
+            D4 p = S.pos[i];
+            double dx, dy, dz;
+            r2 = fmax(r2, dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz));
+        }
+        R = sqrt(r2);
+        S.seed[c].w = R;
     }
-    double R = sqrt(r2);
-    S.seed[c].w = R;
-    atomicMax(&S.sc->rmax, dbits(R));
+    for (int o = 32; o > 0; o >>= 1) R = fmax(R, __shfl_xor(R, o));
+    if ((threadIdx.x & 63) == 0 && c - (int)(threadIdx.x & 63) < S.k) atomicMax(&S.sc->rmax, dbits(R));
 }
 
 // Cells B paired with A: |minimg(c_A - c_B)| <= R_A + R_B + search + 1e-9 with
@@ -804,14 +924,17 @@ __global__ void k_cnbr_count(const SysDev *Sd, Maps L_maps, double search) {
     SYS_FROM(c);
     if (!S.sc->rebuild) return;
     int c = lb * BLOCK + threadIdx.x;
-    if (c >= S.k) return;
-    int n = cell_query(S, S.sc, c, search, 0, nullptr, 0);
-    atomicMax(&S.sc->cnbr_maxrow, n);
-    if (n > CNBR_ROW_MAX) {              // keeps the scanned total inside int32
-        atomicOr(&S.sc->err, ERR_CNBR);
-        n = 0;
+    int n = 0;
+    if (c < S.k) {
+        n = cell_query(S, S.sc, c, search, 0, nullptr, 0);
+        if (n > CNBR_ROW_MAX) {          // keeps the scanned total inside int32
+            atomicOr(&S.sc->err, ERR_CNBR);
+            n = 0;
+        }
+        S.cnbr_start[c] = n;
     }
-    S.cnbr_start[c] = n;
+    int m = wave_max_int(n);
+    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(&S.sc->cnbr_maxrow, m);
 }
 
 __global__ void k_cnbr_fill(const SysDev *Sd, Maps L_maps, double search) {
@@ -836,30 +959,74 @@ void launch_cell_bounds(const LaunchCtx &L) {
 
 void launch_cell_pairs(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_cnbr_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
-    hipLaunchKernelGGL(k_scan_sys, dim3(L.nsys), dim3(1024), 0, L.st, L.S, 3);
+    launch_scan(L, 3);
     hipLaunchKernelGGL(k_cnbr_fill, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
 }
 
 // ------------------------------------------------------------------ neighbour lists
 
-// One wavefront per chunk of 64 consecutive slots: every partner within the list
-// radius (rc + 2 skin of the pair's types) of each particle, found by scanning the
-// particles of every cell paired with the particle's cell.  Column `lane` of the
-// chunk's ELL block holds the partners of slot base + lane, padded with -1.
+// In-place exclusive scan of a[0..n), n <= 8 * BLOCK, by the whole block; returns the total.
+__device__ int block_scan_lds(int *a, int n, int *s_w) {
+    int v[8];
+    int loc = 0;
+    const int base = threadIdx.x * 8;
+    for (int q = 0; q < 8; ++q) {
+        const int idx = base + q;
+        v[q] = idx < n ? a[idx] : 0;
+        loc += v[q];
+    }
+    int tot;
+    int ex = block_excl_scan(loc, s_w, tot);
+    for (int q = 0; q < 8; ++q) {
+        const int idx = base + q;
+        if (idx < n) a[idx] = ex;
+        ex += v[q];
+    }
+    __syncthreads();
+    return tot;
+}
+
+__device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (a[m] < v) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+// One block per 256 consecutive cell-sorted particles (four 64-particle chunks).
+// Pass 1: each lane collects every partner within the list radius (rc + 2 skin of
+// the pair's types) by scanning the particles of every cell paired with its cell;
+// column `lane` of the chunk's ELL block holds them, padded with -1.
+// Pass 2: the union of all partners of the block is staged: the cell-pair entries
+// of the block's (consecutive) cells are sorted and deduplicated in LDS, partners
+// are marked in a bitmap over those cells' particles, a prefix popcount numbers
+// them, the block's stage list receives their slots and every list entry is
+// rewritten as its index in the stage list.  Blocks whose union does not fit keep
+// global slots (stage count -1).
 __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
-    const int chunk = lb * (BLOCK / WAVE) + (threadIdx.x >> 6);
-    const int lane = lane_id();
-    if (chunk >= S.nchunk) return;
-    if (S.sc->err & ERR_CNBR) {          // no valid cell pairs: publish empty lists
-        if (lane == 0) S.nlk[chunk] = 0;
+    __shared__ int s_cand[CANDMAX];
+    __shared__ int s_ofs[CANDMAX + 1];
+    __shared__ unsigned s_bits[SSMAX / 32];
+    __shared__ int s_wpre[SSMAX / 32 + 1];
+    __shared__ int s_w[16];
+    __shared__ int s_flag, s_rows;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int chunk = lb * (BLOCK / WAVE) + wv;
+    const bool chunk_ok = chunk < S.nchunk;
+    const int i = lb * BLOCK + tid;
+    const bool valid = i < S.n;
+    if (S.sc->err & ERR_CNBR) {          // no valid cell pairs: publish empty lists (block-uniform)
+        if (lane == 0 && chunk_ok) S.nlk[chunk] = 0;
+        if (tid == 0) { S.scount[lb] = 0; S.blkrows[lb] = 0; }
         return;
     }
-    const int i = chunk * CHUNK + lane;
-    const bool valid = i < S.n;
+    // ---- pass 1
     int cnt = 0;
-    int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
+    int32_t *col = S.nl + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
     if (valid) {
         D4 pi = S.pos[i];
         int ti = (int)pi.w;
@@ -884,11 +1051,107 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         if (lane == 0) atomicOr(&S.sc->err, ERR_NLIST);
         rows = MAXNB;
     }
-    for (int r = min(cnt, MAXNB); r < rows; ++r) col[r * CHUNK] = -1;
-    if (lane == 0) {
-        S.nlk[chunk] = rows;
-        atomicMax(&S.sc->nlrows, rows);
+    const int mycnt = min(cnt, MAXNB);
+    if (chunk_ok) {
+        for (int r = mycnt; r < rows; ++r) col[r * CHUNK] = -1;
+        if (lane == 0) S.nlk[chunk] = rows;
     }
+    if (tid == 0) { s_flag = 0; s_rows = 0; }
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_rows, rows);
+    // ---- pass 2: candidate cells = the contiguous cell-pair slice of the block's cells
+    const int first = lb * BLOCK;
+    const int last = min(S.n - 1, first + BLOCK - 1);
+    const int c0 = S.owner[first], c1 = S.owner[last];
+    const int q0 = S.cnbr_start[c0];
+    const int ncand = S.cnbr_start[c1 + 1] - q0;
+    bool overflow = (ncand <= 0 || ncand > CANDMAX || c1 < c0);
+    int nsc = 0;
+    if (!overflow) {
+        int pw = 1;
+        while (pw < ncand) pw <<= 1;
+        for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? S.cnbr[q0 + q] : INT_MAX;
+        __syncthreads();
+        for (int kk = 2; kk <= pw; kk <<= 1)
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int t = tid; t < pw; t += BLOCK) {
+                    int ixj = t ^ jj;
+                    if (ixj > t) {
+                        int va = s_cand[t], vb = s_cand[ixj];
+                        bool up = (t & kk) == 0;
+                        if ((va > vb) == up) { s_cand[t] = vb; s_cand[ixj] = va; }
+                    }
+                }
+                __syncthreads();
+            }
+        // deduplicate in place
+        int vals[8], fl[8], loc = 0;
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid * 8 + q;
+            vals[q] = idx < pw ? s_cand[idx] : INT_MAX;
+            const int prev = (idx > 0 && idx < pw) ? s_cand[idx - 1] : INT_MIN;
+            fl[q] = (idx < ncand && (idx == 0 || vals[q] != prev)) ? 1 : 0;
+            loc += fl[q];
+        }
+        int p = block_excl_scan(loc, s_w, nsc);
+        for (int q = 0; q < 8; ++q)
+            if (fl[q]) s_cand[p++] = vals[q];
+        __syncthreads();
+        // particle offsets of the candidate cells
+        for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = S.ccount[s_cand[q]];
+        __syncthreads();
+        const int ss = block_scan_lds(s_ofs, nsc, s_w);
+        if (tid == 0) s_ofs[nsc] = ss;
+        for (int w = tid; w < SSMAX / 32; w += BLOCK) s_bits[w] = 0u;
+        __syncthreads();
+        overflow = ss > SSMAX;
+        if (!overflow) {
+            if (valid)
+                for (int r = 0; r < mycnt; ++r) {
+                    const int j = col[r * CHUNK];
+                    const int B = S.owner[j];
+                    const int pos = lds_lower_bound(s_cand, nsc, B);
+                    if (pos >= nsc || s_cand[pos] != B) { s_flag = 1; continue; }
+                    const int sidx = s_ofs[pos] + (j - S.cstart[B]);
+                    atomicOr(&s_bits[sidx >> 5], 1u << (sidx & 31));
+                }
+            __syncthreads();
+            for (int w = tid; w < SSMAX / 32; w += BLOCK) s_wpre[w] = __popc(s_bits[w]);
+            __syncthreads();
+            const int staged = block_scan_lds(s_wpre, SSMAX / 32, s_w);
+            overflow = staged > SMAX || s_flag != 0;
+            if (!overflow) {
+                for (int w = tid; w < SSMAX / 32; w += BLOCK) {
+                    unsigned bits = s_bits[w];
+                    int r = s_wpre[w];
+                    while (bits) {
+                        const int b = __ffs(bits) - 1;
+                        bits &= bits - 1u;
+                        const int sidx = w * 32 + b;
+                        int lo = 0, hi = nsc;                 // last cell with offset <= sidx
+                        while (hi - lo > 1) {
+                            int m = (lo + hi) >> 1;
+                            if (s_ofs[m] <= sidx) lo = m; else hi = m;
+                        }
+                        S.stage[(size_t)lb * SMAX + r] = S.cstart[s_cand[lo]] + (sidx - s_ofs[lo]);
+                        ++r;
+                    }
+                }
+                if (valid)
+                    for (int r = 0; r < mycnt; ++r) {
+                        const int j = col[r * CHUNK];
+                        const int B = S.owner[j];
+                        const int pos = lds_lower_bound(s_cand, nsc, B);
+                        const int sidx = s_ofs[pos] + (j - S.cstart[B]);
+                        const int w = sidx >> 5;
+                        col[r * CHUNK] = s_wpre[w] + __popc(s_bits[w] & ((1u << (sidx & 31)) - 1u));
+                    }
+                if (tid == 0) S.scount[lb] = staged;
+            }
+        }
+    }
+    if (overflow && tid == 0) S.scount[lb] = -1;     // entries keep global slots
+    if (tid == 0) S.blkrows[lb] = s_rows;
 }
 
 void launch_nlist(const LaunchCtx &L) {
@@ -904,19 +1167,28 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
     if (i < S.n) S.xb[i] = S.pos[i];
 }
 
-__global__ void k_finish_sys(const SysDev *Sd, int nsys) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsys) return;
-    SysScal *sc = Sd[s].sc;
+__global__ __launch_bounds__(256) void k_finish_sys(const SysDev *Sd, int nsys) {
+    const SysDev &S = Sd[blockIdx.x];
+    SysScal *sc = S.sc;
     if (!sc->rebuild) return;
-    sc->maxdisp2 = 0ull;
-    sc->maxv2 = 0ull;
-    sc->rebuild = 0;
+    int m = 0;
+    const int nblk = (S.n + BLOCK - 1) / BLOCK;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = max(m, S.blkrows[b]);
+    m = wave_max_int(m);
+    __shared__ int s_m[4];
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sc->nlrows = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+        sc->maxdisp2 = 0ull;
+        sc->maxv2 = 0ull;
+        sc->rebuild = 0;
+    }
 }
 
 void launch_finish_update(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_finish_particles, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_finish_sys, dim3((L.nsys + 63) / 64), dim3(64), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_finish_sys, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys);
 }
 
 // ------------------------------------------------------------------ entry points used by the runtime

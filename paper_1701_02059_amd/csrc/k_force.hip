@@ -162,16 +162,54 @@ __device__ __forceinline__ T wca_pair(const DevParams &P, T dx, T dy, T dz, T &f
 
 // ------------------------------------------------------------------ force kernel
 
+template <int MIXED>
+struct Staged;
+template <>
+struct Staged<1> {
+    using P = D4;          // raw FP64 position, type in w (the separation is formed in FP64)
+    using N = float4;      // orientation (FP32)
+};
+template <>
+struct Staged<0> {
+    using P = D4;          // raw FP64 position, type in w
+    using N = D4;          // FP64 orientation
+};
+
+// One workgroup per 256 consecutive cell-sorted particles.  The block's partners
+// (its stage list) are read once from HBM into LDS; lane i then walks column i of
+// its chunk's list, whose entries index the LDS stage.  Every candidate takes the
+// exact FP64 neighbour test on FP64 positions in both modes; mixed mode rounds the
+// separation and orientations to FP32 for the pair law.
 template <int MIXED, int ENERGY, int KICK>
 __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     using T = typename std::conditional<MIXED, float, double>::type;
+    using SP = typename Staged<MIXED>::P;
+    using SN = typename Staged<MIXED>::N;
+    __shared__ SP s_p[SMAX];
+    __shared__ SN s_n[SMAX];
     const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
     const SysDev &S = Sd[s];
-    const int chunk = (blockIdx.x - L_maps.p[s]) * (BLOCK / WAVE) + (threadIdx.x >> 6);
-    if (chunk >= S.nchunk) return;                // uniform per wavefront
-    const int lane = lane_id_f();
-    const int i = chunk * CHUNK + lane;
+    const int lb = blockIdx.x - L_maps.p[s];
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int chunk = lb * (BLOCK / WAVE) + (tid >> 6);
+    const int i = lb * BLOCK + tid;
     const bool valid = i < S.n;
+    const int scnt = S.scount[lb];
+    for (int q = tid; q < scnt; q += BLOCK) {
+        const int slot = S.stage[(size_t)lb * SMAX + q];
+        const D4 p = S.pos[slot];
+        const D4 o = S.ori[slot];
+        if constexpr (MIXED) {
+            s_p[q] = p;
+            s_n[q] = make_float4((float)o.x, (float)o.y, (float)o.z, 0.0f);
+        } else {
+            s_p[q] = p;
+            s_n[q] = o;
+        }
+    }
+    __syncthreads();
+    if (chunk >= S.nchunk) return;
     const D4 pi = valid ? S.pos[i] : D4{0.0, 0.0, 0.0, 0.0};
     const D4 ni = valid ? S.ori[i] : D4{0.0, 0.0, 0.0, 0.0};
     const int ti = (int)pi.w;
@@ -180,29 +218,83 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     double U = 0.0, W = 0.0;
     const int rows = min(S.nlk[chunk], MAXNB);
     const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
-    for (int r = 0; r < rows; ++r) {
-        const int j = valid ? col[r * CHUNK] : -1;
-        if (j < 0 || j >= S.n) continue;
-        const D4 pj = S.pos[j];
-        const int tj = (int)pj.w;
-        double dx, dy, dz;
-        const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
-        if (!(d2 < P.rc2[ti][tj])) continue;
-        T ax = 0, ay = 0, az = 0;
-        T u;
-        if ((ti | tj) == 0) {
-            const D4 nj = S.ori[j];
-            u = lipid_pair<T>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, (T)nj.x, (T)nj.y, (T)nj.z, ax, ay, az, tx, ty,
-                              tz);
+    if (scnt >= 0) {
+        if constexpr (MIXED) {
+            for (int r = 0; r < rows; ++r) {
+                const int e = valid ? col[r * CHUNK] : -1;
+                if (e < 0 || e >= scnt) continue;
+                const D4 pj = s_p[e];
+                const int tj = (int)pj.w;
+                double dx, dy, dz;
+                const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+                if (!(d2 < P.rc2[ti][tj])) continue;
+                float ax = 0.f, ay = 0.f, az = 0.f, u;
+                if ((ti | tj) == 0) {
+                    const float4 nj = s_n[e];
+                    u = lipid_pair<float>(P, (float)dx, (float)dy, (float)dz, nix, niy, niz, nj.x, nj.y, nj.z, ax, ay,
+                                          az, tx, ty, tz);
+                } else {
+                    u = wca_pair<float>(P, (float)dx, (float)dy, (float)dz, ax, ay, az);
+                }
+                fx += ax;
+                fy += ay;
+                fz += az;
+                if (ENERGY) {
+                    U += 0.5 * (double)u;
+                    W += 0.5 * (dx * (double)ax + dy * (double)ay + dz * (double)az);
+                }
+            }
         } else {
-            u = wca_pair<T>(P, (T)dx, (T)dy, (T)dz, ax, ay, az);
+            for (int r = 0; r < rows; ++r) {
+                const int e = valid ? col[r * CHUNK] : -1;
+                if (e < 0 || e >= scnt) continue;
+                const D4 pj = s_p[e];
+                const int tj = (int)pj.w;
+                double dx, dy, dz;
+                const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+                if (!(d2 < P.rc2[ti][tj])) continue;
+                double ax = 0, ay = 0, az = 0, u;
+                if ((ti | tj) == 0) {
+                    const D4 nj = s_n[e];
+                    u = lipid_pair<double>(P, dx, dy, dz, nix, niy, niz, nj.x, nj.y, nj.z, ax, ay, az, tx, ty, tz);
+                } else {
+                    u = wca_pair<double>(P, dx, dy, dz, ax, ay, az);
+                }
+                fx += ax;
+                fy += ay;
+                fz += az;
+                if (ENERGY) {
+                    U += 0.5 * u;
+                    W += 0.5 * (dx * ax + dy * ay + dz * az);
+                }
+            }
         }
-        fx += ax;
-        fy += ay;
-        fz += az;
-        if (ENERGY) {
-            U += 0.5 * (double)u;
-            W += 0.5 * (dx * (double)ax + dy * (double)ay + dz * (double)az);
+    } else {
+        // block whose partners did not fit the stage: entries are global slots
+        for (int r = 0; r < rows; ++r) {
+            const int j = valid ? col[r * CHUNK] : -1;
+            if (j < 0 || j >= S.n) continue;
+            const D4 pj = S.pos[j];
+            const int tj = (int)pj.w;
+            double dx, dy, dz;
+            const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+            if (!(d2 < P.rc2[ti][tj])) continue;
+            T ax = 0, ay = 0, az = 0;
+            T u;
+            if ((ti | tj) == 0) {
+                const D4 nj = S.ori[j];
+                u = lipid_pair<T>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, (T)nj.x, (T)nj.y, (T)nj.z, ax, ay, az, tx,
+                                  ty, tz);
+            } else {
+                u = wca_pair<T>(P, (T)dx, (T)dy, (T)dz, ax, ay, az);
+            }
+            fx += ax;
+            fy += ay;
+            fz += az;
+            if (ENERGY) {
+                U += 0.5 * (double)u;
+                W += 0.5 * (dx * (double)ax + dy * (double)ay + dz * (double)az);
+            }
         }
     }
     double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
@@ -344,15 +436,47 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
     disp2 = wave_maxd(disp2);
     v2 = wave_maxd(v2);
     const unsigned long long anybad = __ballot(bad);
-    if (lane_id_f() == 0 && i - lane_id_f() < S.n) {
-        atomicMax(&S.sc->maxdisp2, dbits(disp2));
-        atomicMax(&S.sc->maxv2, dbits(v2));
+    __shared__ double s_m[2][BLOCK / WAVE];
+    if (lane_id_f() == 0) {
+        s_m[0][threadIdx.x >> 6] = disp2;
+        s_m[1][threadIdx.x >> 6] = v2;
         if (anybad) atomicOr(&S.sc->err, ERR_NONFINITE);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double m = s_m[threadIdx.x][0];
+        for (int q = 1; q < BLOCK / WAVE; ++q) m = fmax(m, s_m[threadIdx.x][q]);
+        S.bred[(size_t)(blockIdx.x - L_maps.p[s]) * BRED + threadIdx.x] = m;
+    }
+}
+
+// Largest displacement since the last build and largest drift speed, per system,
+// from the kick-drift block partials.
+__global__ __launch_bounds__(256) void k_stats_reduce(const SysDev *Sd, int nsys) {
+    const SysDev &S = Sd[blockIdx.x];
+    const int nblk = (S.n + BLOCK - 1) / BLOCK;
+    double d = 0.0, v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        d = fmax(d, S.bred[(size_t)b * BRED]);
+        v = fmax(v, S.bred[(size_t)b * BRED + 1]);
+    }
+    d = wave_maxd(d);
+    v = wave_maxd(v);
+    __shared__ double s_m[2][4];
+    if ((threadIdx.x & 63) == 0) { s_m[0][threadIdx.x >> 6] = d; s_m[1][threadIdx.x >> 6] = v; }
+    __syncthreads();
+    if (threadIdx.x == 0 && nblk > 0) {
+        d = fmax(fmax(s_m[0][0], s_m[0][1]), fmax(s_m[0][2], s_m[0][3]));
+        v = fmax(fmax(s_m[1][0], s_m[1][1]), fmax(s_m[1][2], s_m[1][3]));
+        SysScal *sc = S.sc;
+        if (dbits(d) > sc->maxdisp2) sc->maxdisp2 = dbits(d);
+        if (dbits(v) > sc->maxv2) sc->maxv2 = dbits(v);
     }
 }
 
 void launch_kick_drift(const LaunchCtx &L, double dt) {
     hipLaunchKernelGGL(k_kick_drift, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm, dt);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys);
 }
 
 // ------------------------------------------------------------------ energy reduction
@@ -411,32 +535,63 @@ void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, in
 
 // ------------------------------------------------------------------ neighbour-set export
 
-// Pairs (gid_i < gid_j) of the list that pass the exact test, appended in any order.
+// Pairs (gid_i < gid_j) of the list that pass the exact FP64 test, appended in any
+// order (one atomic per wavefront).  Staged entries are mapped back to slots.
+__device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, int e) {
+    return scnt >= 0 ? S.stage[(size_t)blk * SMAX + e] : e;
+}
+
 __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
     const SysDev &S = Sd[s];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.n) return;
-    const int chunk = i / CHUNK, lane = i % CHUNK;
-    const D4 pi = S.pos[i];
-    const int ti = (int)pi.w;
-    const int gi = S.gid[i];
-    const int rows = min(S.nlk[chunk], MAXNB);
-    const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
-    for (int r = 0; r < rows; ++r) {
-        const int j = col[r * CHUNK];
-        if (j < 0 || j >= S.n) continue;
-        const int gj = S.gid[j];
-        if (gj <= gi) continue;
-        const D4 pj = S.pos[j];
-        double dx, dy, dz;
-        const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
-        if (d2 < P.rc2[ti][(int)pj.w]) {
-            const int idx = atomicAdd(&S.sc->npairs, 1);
-            if ((int64_t)idx < S.pairs_cap) {
-                S.pairs[2 * idx] = gi;
-                S.pairs[2 * idx + 1] = gj;
+    const bool valid = i < S.n;
+    const int chunk = i / CHUNK, lane = i % CHUNK, blk = i / BLOCK;
+    D4 pi = {0, 0, 0, 0};
+    int ti = 0, gi = 0, rows = 0, scnt = -1;
+    const int32_t *col = nullptr;
+    if (valid) {
+        pi = S.pos[i];
+        ti = (int)pi.w;
+        gi = S.gid[i];
+        rows = min(S.nlk[chunk], MAXNB);
+        scnt = S.scount[blk];
+        col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
+    }
+    int mine = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int base = 0;
+        if (pass == 1) {
+            int tot = mine, ex = mine;
+            for (int o = 1; o < 64; o <<= 1) {
+                int y = __shfl_up(ex, o);
+                if (lane_id_f() >= o) ex += y;
+            }
+            tot = __shfl(ex, 63);
+            ex -= mine;
+            int wb = 0;
+            if (lane_id_f() == 0 && tot > 0) wb = atomicAdd(&S.sc->npairs, tot);
+            base = __shfl(wb, 0) + ex;
+        }
+        int k = 0;
+        for (int r = 0; r < rows; ++r) {
+            const int e = col[r * CHUNK];
+            if (e < 0) continue;
+            const int j = entry_slot(S, blk, scnt, e);
+            if (j < 0 || j >= S.n) continue;
+            const int gj = S.gid[j];
+            if (gj <= gi) continue;
+            const D4 pj = S.pos[j];
+            double dx, dy, dz;
+            const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+            if (d2 < P.rc2[ti][(int)pj.w]) {
+                if (pass == 1 && (int64_t)(base + k) < S.pairs_cap) {
+                    S.pairs[2 * (base + k)] = gi;
+                    S.pairs[2 * (base + k) + 1] = gj;
+                }
+                ++k;
             }
         }
+        mine = k;
     }
 }
 

@@ -178,6 +178,12 @@ size_t layout(HostSys &s, char *base) {
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
     d.epart = c.take<double>((size_t)s.nchunk * 9);
+    const int64_t nblkp = (n + BLOCK - 1) / BLOCK;
+    d.stage = c.take<int32_t>((size_t)nblkp * SMAX);
+    d.scount = c.take<int32_t>(nblkp);
+    d.blkrows = c.take<int32_t>(nblkp);
+    d.bred = c.take<double>((size_t)nblkp * BRED);
+    d.tsum = c.take<int32_t>((size_t)std::max((k + SCAN_TILE - 1) / SCAN_TILE, (s.gcap + SCAN_TILE - 1) / SCAN_TILE) + 2);
     s.lip = c.take<int32_t>(s.nlip);
     return c.off + 256;
 }
@@ -210,8 +216,9 @@ rbc_status refresh_tables(rbc_ctx *h) {
     const int ns = h->nsys;
     std::vector<SysDev> tab(ns);
     std::vector<const int32_t *> lips(ns, nullptr);
-    std::vector<int32_t> maps(5 * (ns + 1), 0);
+    std::vector<int32_t> maps(7 * (ns + 1), 0);
     int32_t *mp = maps.data(), *mc = mp + (ns + 1), *mg = mc + (ns + 1), *mtp = mg + (ns + 1), *mts = mtp + (ns + 1);
+    int32_t *msc = mts + (ns + 1), *msg = msc + (ns + 1);
     for (int s = 0; s < ns; ++s) {
         HostSys &hs = h->sys[s];
         SysDev d{};
@@ -228,6 +235,8 @@ rbc_status refresh_tables(rbc_ctx *h) {
         mg[s + 1] = mg[s] + (hs.live ? (hs.gcap + BLOCK - 1) / BLOCK : 0);
         mtp[s + 1] = mtp[s] + (hs.live ? hs.ntile_p : 0);
         mts[s + 1] = mts[s] + (hs.live ? hs.ntile_s : 0);
+        msc[s + 1] = msc[s] + (k + SCAN_TILE - 1) / SCAN_TILE;
+        msg[s + 1] = msg[s] + (hs.live ? (hs.gcap + SCAN_TILE - 1) / SCAN_TILE : 0);
     }
     HIPCHK(hipMemcpyAsync(h->d_sys, tab.data(), sizeof(SysDev) * ns, hipMemcpyHostToDevice, h->st));
     HIPCHK(hipMemcpyAsync(h->d_maps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice, h->st));
@@ -240,12 +249,16 @@ rbc_status refresh_tables(rbc_ctx *h) {
     L.maps.g = h->d_maps + 2 * (ns + 1);
     L.maps.tp = h->d_maps + 3 * (ns + 1);
     L.maps.ts = h->d_maps + 4 * (ns + 1);
+    L.maps.sc = h->d_maps + 5 * (ns + 1);
+    L.maps.sg = h->d_maps + 6 * (ns + 1);
     L.maps.nsys = ns;
     L.nblk_p = mp[ns];
     L.nblk_c = mc[ns];
     L.nblk_g = mg[ns];
     L.nblk_tp = mtp[ns];
     L.nblk_ts = mts[ns];
+    L.nblk_sc = msc[ns];
+    L.nblk_sg = msg[ns];
     L.nsys = ns;
     L.prm = h->dprm;
     L.st = h->st;
@@ -315,6 +328,8 @@ rbc_status read_errors(rbc_ctx *h, const SysScal *sc) {
 }
 
 rbc_status sync_and_check(rbc_ctx *h) {
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return fail(h, RBC_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(le));
     HIPCHK(hipMemcpyAsync(h->h_ring, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
     return read_errors(h, h->h_ring);
@@ -550,7 +565,7 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(&h->d_sys, sizeof(SysDev) * max_slots) == hipSuccess &&
               hipMalloc(&h->d_sc, sizeof(SysScal) * max_slots) == hipSuccess &&
-              hipMalloc(&h->d_maps, sizeof(int32_t) * 5 * (max_slots + 1)) == hipSuccess &&
+              hipMalloc(&h->d_maps, sizeof(int32_t) * 7 * (max_slots + 1)) == hipSuccess &&
               hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
               hipHostMalloc((void **)&h->h_ring, sizeof(SysScal) * MAX_SLOTS * RING, hipHostMallocDefault) == hipSuccess;
     for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->ring_ev[q], hipEventDisableTiming) == hipSuccess;
@@ -828,6 +843,39 @@ rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_
             hipEventCreate(&h->te[q]);
         }
     }
+    return RBC_OK;
+}
+
+rbc_status rbc_debug_array(rbc_handle h, int32_t which, int64_t cap, void *out, int64_t *bytes) {
+    if (!h || !bytes || cap < 0 || (cap > 0 && !out)) return RBC_ERR_INVALID_ARG;
+    HostSys &hs = h->sys[0];
+    if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    rbc_status r = sync_and_check(h);
+    if (r != RBC_OK && r != RBC_ERR_CAPACITY) return r;
+    const SysDev &d = hs.dev;
+    const SysScal &sc = h->h_ring[0];
+    const void *src = nullptr;
+    int64_t nb = 0;
+    int32_t total = 0;
+    switch (which) {
+        case 0: src = d.owner; nb = 4 * hs.n; break;
+        case 1: src = d.cstart; nb = 4 * (int64_t)(hs.k + 1); break;
+        case 2: src = d.ccount; nb = 4 * (int64_t)hs.k; break;
+        case 3: src = d.cnbr_start; nb = 4 * (int64_t)(hs.k + 1); break;
+        case 4:
+            HIPCHK(hipMemcpy(&total, d.cnbr_start + hs.k, 4, hipMemcpyDeviceToHost));
+            src = d.cnbr; nb = 4 * (int64_t)std::min(std::max(total, 0), hs.cnbr_cap); break;
+        case 5: src = d.gstart; nb = 4 * (int64_t)(sc.gtot + 1); break;
+        case 6: src = d.gseed; nb = 4 * (int64_t)hs.k; break;
+        case 7: src = d.seed; nb = sizeof(D4) * (int64_t)hs.k; break;
+        case 8: src = d.nlk; nb = 4 * (int64_t)hs.nchunk; break;
+        case 9: src = d.scount; nb = 4 * ((hs.n + BLOCK - 1) / BLOCK); break;
+        case 10: src = d.gid; nb = 4 * hs.n; break;
+        case 11: src = d.tsum; nb = 4 * (int64_t)(std::max((hs.k + SCAN_TILE - 1) / SCAN_TILE, (hs.gcap + SCAN_TILE - 1) / SCAN_TILE) + 2); break;
+        default: return fail(h, RBC_ERR_INVALID_ARG, "unknown array");
+    }
+    *bytes = nb;
+    if (cap > 0 && nb > 0) HIPCHK(hipMemcpy(out, src, std::min(cap, nb), hipMemcpyDeviceToHost));
     return RBC_OK;
 }
 

@@ -14,6 +14,11 @@ constexpr int SORT_IPT = 16;          // items per thread in the radix sort
 constexpr int SORT_TILE = BLOCK * SORT_IPT;
 constexpr int MAX_SLOTS = 256;
 constexpr int CNBR_ROW_MAX = 2048;      // cell pairs per cell before the build reports overflow
+constexpr int SMAX = 1024;             // neighbours staged in LDS per 256-particle block
+constexpr int CANDMAX = 2048;          // candidate cells (cell-pair entries) per block while staging
+constexpr int SSMAX = 4096;            // particles in a block's candidate cells while staging
+constexpr int SCAN_TILE = 2048;        // elements per block in the segmented scans
+constexpr int BRED = 8;                // doubles of per-block partial results
 
 // error bits in SysScal::err
 constexpr int ERR_NLIST = 1;          // a particle had more than MAXNB list neighbours
@@ -67,6 +72,10 @@ struct SysDev {
     double *epart;                                  // per-chunk energy partials (nchunk x 9)
     int32_t *pairs;                                 // scratch for exporting the pair set
     int64_t pairs_cap;
+    int32_t *stage, *scount;                        // per 256-particle block: staged slots (SMAX), count (-1: none)
+    int32_t *blkrows;                               // per block: largest list row count of the last build
+    double *bred;                                   // per particle block: BRED partials (stats, bounding box)
+    int32_t *tsum;                                  // segmented-scan tile sums
     SysScal *sc;
 };
 
@@ -89,6 +98,8 @@ struct Maps {
     const int32_t *g;      // seed-grid cell blocks
     const int32_t *tp;     // particle sort tiles
     const int32_t *ts;     // seed sort tiles
+    const int32_t *sc;     // scan tiles over cells
+    const int32_t *sg;     // scan tiles over seed-grid cells
     int32_t nsys;
 };
 
@@ -153,14 +164,14 @@ namespace rbc {
 struct LaunchCtx {
     const SysDev *S;         // device array of systems
     Maps maps;
-    int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts;   // totals over systems
+    int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts, nblk_sc, nblk_sg;   // totals over systems
     int32_t nsys;
     DevParams prm;
     hipStream_t st;
 };
 
 // step kernels
-void launch_kick_drift(const LaunchCtx &L, double dt);
+void launch_kick_drift(const LaunchCtx &L, double dt);   // includes the per-system statistics reduction
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt);
 void launch_reduce_energy(const LaunchCtx &L);
 void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count);

@@ -25,7 +25,7 @@ FUNCTIONS = [
     "rbc_get_pairs", "rbc_energy", "rbc_stats", "rbc_get_cells", "rbc_force_timing", "rbc_sync", "rbc_destroy",
     "rbc_status_string", "rbc_last_error", "rbc_ensemble_create", "rbc_ensemble_footprint", "rbc_ensemble_admit",
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
-    "rbc_ensemble_info",
+    "rbc_ensemble_info", "rbc_debug_array",
 ]
 
 
@@ -52,6 +52,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1701_02059_amd.build.build()")
+        # torch bundles its own HIP runtime under the same soname; load and initialise it
+        # first so that librbc binds to that single runtime in this process
+        import torch
+        torch.cuda.is_available()
         L = C.CDLL(LIB_PATH)
         vp, dp, ip, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
         h = C.c_void_p
@@ -78,6 +82,7 @@ def lib():
             "rbc_ensemble_energy": [h, C.c_int32, dp],
             "rbc_ensemble_retire": [h, C.c_int32],
             "rbc_ensemble_info": [h, i64p],
+            "rbc_debug_array": [h, C.c_int32, C.c_int64, vp, i64p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -218,6 +223,16 @@ class Context:
         _check(self._h, lib().rbc_get_cells(self._h, owner.ctypes.data_as(C.POINTER(C.c_int32)),
                                             seeds.ctypes.data_as(C.POINTER(C.c_double))))
         return owner, seeds
+
+    def debug_array(self, which: int) -> np.ndarray:
+        nb = C.c_int64(0)
+        _check(self._h, lib().rbc_debug_array(self._h, int(which), 0, None, C.byref(nb)))
+        dt = np.float64 if which == 7 else np.int32
+        out = np.zeros(max(1, nb.value // np.dtype(dt).itemsize), dtype=dt)
+        _check(self._h, lib().rbc_debug_array(self._h, int(which), nb.value, out.ctypes.data_as(C.c_void_p),
+                                              C.byref(nb)))
+        out = out[: nb.value // np.dtype(dt).itemsize]
+        return out.reshape(-1, 4) if which == 7 else out
 
     def force_timing(self, enable: bool = True):
         avg = C.c_double(0.0)

@@ -303,3 +303,30 @@ def test_nonfinite_state_is_reported(R, mp, patch):
         c.step(2, 0.01)
     assert ei.value.status == R.RBC_ERR_NONFINITE
     c.close()
+
+
+def _dense_cloud(n_side=14, spacing=1.36, seed=11):
+    """Jittered cubic lattice of lipids (3D, density ~0.4): neighbour unions of a
+    256-particle block exceed the LDS stage, so the global-gather path is used."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(n_side) * spacing
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    x = x + rng.normal(0, 0.05, size=x.shape)
+    nrm = rng.normal(size=x.shape)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    N = x.shape[0]
+    return I.System("cloud", x, nrm, np.zeros(N, np.int32), np.zeros((N, 3)), np.zeros((N, 3)),
+                    np.zeros((0, 2), np.int32), np.zeros(0), np.zeros(3), np.zeros(3, np.int32))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dense_3d_cloud_unstaged_blocks(R, mp, prec):
+    s = _dense_cloud()
+    p = O.params_for(s, mp)
+    F0, T0, U0, W0 = O.forces(p, s)
+    c = _ctx(R, mp, s, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
+    F, T = (to_np(t) for t in c.forces())
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    assert rel_err(F, F0) < tol and rel_err(T, T0) < tol
+    assert np.array_equal(c.get_pairs(), O.pairs(p, s.x, s.type))
+    c.close()
