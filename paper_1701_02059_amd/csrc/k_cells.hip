@@ -579,7 +579,12 @@ __global__ __launch_bounds__(256) void k_sort_scan(const SysDev *Sd, int kind) {
     }
     int tot;
     int base = block_excl_scan(run, s_w, tot);
-    for (int t = 0; t < ntile; ++t) S.hist[t * 256 + d] += base;
+    for (int t0 = 0; t0 < ntile; t0 += B) {
+        int c[B];
+        for (int q = 0; q < B; ++q) c[q] = (t0 + q < ntile) ? S.hist[(t0 + q) * 256 + d] : 0;
+        for (int q = 0; q < B; ++q)
+            if (t0 + q < ntile) S.hist[(t0 + q) * 256 + d] = c[q] + base;
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_sort_scatter(const SysDev *Sd, Maps L_maps, int kind, int pass) {
@@ -1002,9 +1007,9 @@ __device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v) {
 // Pass 2: the union of all partners of the block is staged: the cell-pair entries
 // of the block's (consecutive) cells are sorted and deduplicated in LDS, partners
 // are marked in a bitmap over those cells' particles, a prefix popcount numbers
-// them, the block's stage list receives their slots and every list entry is
-// rewritten as its index in the stage list.  Blocks whose union does not fit keep
-// global slots (stage count -1).
+// them, the block's stage list receives their slots and a 16-bit copy of every
+// list holds stage indices (0xffff pads).  Blocks whose union does not fit use
+// the global-slot lists (stage count -1).
 __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
@@ -1137,15 +1142,21 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
                         ++r;
                     }
                 }
-                if (valid)
-                    for (int r = 0; r < mycnt; ++r) {
-                        const int j = col[r * CHUNK];
-                        const int B = S.owner[j];
-                        const int pos = lds_lower_bound(s_cand, nsc, B);
-                        const int sidx = s_ofs[pos] + (j - S.cstart[B]);
-                        const int w = sidx >> 5;
-                        col[r * CHUNK] = s_wpre[w] + __popc(s_bits[w] & ((1u << (sidx & 31)) - 1u));
+                if (chunk_ok) {
+                    uint16_t *col16 = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
+                    for (int r = 0; r < rows; ++r) {
+                        int local = 0xffff;
+                        if (valid && r < mycnt) {
+                            const int j = col[r * CHUNK];
+                            const int B = S.owner[j];
+                            const int pos = lds_lower_bound(s_cand, nsc, B);
+                            const int sidx = s_ofs[pos] + (j - S.cstart[B]);
+                            const int w = sidx >> 5;
+                            local = s_wpre[w] + __popc(s_bits[w] & ((1u << (sidx & 31)) - 1u));
+                        }
+                        col16[r * CHUNK] = (uint16_t)local;
                     }
+                }
                 if (tid == 0) S.scount[lb] = staged;
             }
         }
@@ -1164,7 +1175,11 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
     int i = lb * BLOCK + threadIdx.x;
-    if (i < S.n) S.xb[i] = S.pos[i];
+    if (i < S.n) {
+        S.xb[i] = S.pos[i];
+        const D4 o = S.ori[i];
+        S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, 0.0f};
+    }
 }
 
 __global__ __launch_bounds__(256) void k_finish_sys(const SysDev *Sd, int nsys) {

@@ -41,104 +41,67 @@ __device__ __forceinline__ T ipow(T c, int e) {
 // ------------------------------------------------------------------ pair laws
 
 // Lipid-lipid orientation-dependent law; d = x_i - x_j.  Adds the force and torque
-// on i and returns U (with dU/dr, dU/da and the gradient projection written out).
-template <class T>
+// on i and returns U.  FAST: the default constants zeta = 4 and sin(theta0) = 0
+// folded in at compile time (same arithmetic with the zero terms removed).
+template <class T, bool FAST>
 __device__ __forceinline__ T lipid_pair(const DevParams &P, T dx, T dy, T dz, T nix, T niy, T niz, T njx, T njy,
-                                        T njz, T &fx, T &fy, T &fz, T &tx, T &ty, T &tz);
-
-template <>
-__device__ __forceinline__ float lipid_pair<float>(const DevParams &P, float dx, float dy, float dz, float nix,
-                                                   float niy, float niz, float njx, float njy, float njz, float &fx,
-                                                   float &fy, float &fz, float &tx, float &ty, float &tz) {
-    const float eps = (float)P.eps, mu = (float)P.mu, st0 = (float)P.st0, rmin = (float)P.r_min;
-    const float rc = (float)P.rc_lipid;
-    const float inv_w = 1.0f / (rc - rmin);
-    float r2 = dx * dx + dy * dy + dz * dz;
-    float rinv = __builtin_amdgcn_rsqf(r2);
-    float r = r2 * rinv;
-    float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-    float s = nix * ex + niy * ey + niz * ez;
-    float t = njx * ex + njy * ey + njz * ez;
-    float c = nix * njx + niy * njy + niz * njz;
-    float a = c - s * t + st0 * (t - s) - st0 * st0;
-    float phi = 1.0f + mu * (a - 1.0f);
-    float U, dUdr, dUda;
+                                        T njz, T &fx, T &fy, T &fz, T &tx, T &ty, T &tz) {
+    const T eps = (T)P.eps, mu = (T)P.mu, st0 = FAST ? (T)0 : (T)P.st0, rmin = (T)P.r_min;
+    T r2 = dx * dx + dy * dy + dz * dz;
+    T rinv, r;
+    if constexpr (sizeof(T) == 4) {
+        rinv = __builtin_amdgcn_rsqf(r2);
+        r = r2 * rinv;
+    } else {
+        r = sqrt(r2);
+        rinv = (T)1 / r;
+    }
+    const T ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+    const T s = nix * ex + niy * ey + niz * ez;
+    const T t = njx * ex + njy * ey + njz * ez;
+    const T c = nix * njx + niy * njy + niz * njz;
+    T a = c - s * t;
+    if (!FAST) a += st0 * (t - s) - st0 * st0;
+    const T phi = (T)1 + mu * (a - (T)1);
+    T U, dUdr, dUda;
     if (r < rmin) {
-        float q = rmin * rmin * rinv * rinv;
-        U = eps * (q * q - 2.0f * q) + (1.0f - phi) * eps;
-        dUdr = 4.0f * eps * (q - q * q) * rinv;
+        const T q = (rmin * rinv) * (rmin * rinv);
+        U = eps * (q * q - (T)2 * q) + ((T)1 - phi) * eps;
+        dUdr = (T)4 * eps * (q - q * q) * rinv;
         dUda = -mu * eps;
     } else {
-        // x = (pi/2) u: the hardware sine / cosine take revolutions, x / 2pi = u / 4
-        float u = (r - rmin) * inv_w;
-        float sx = __builtin_amdgcn_sinf(0.25f * u);
-        float cx = __builtin_amdgcn_cosf(0.25f * u);
-        float c2 = cx * cx;
-        float cz1 = ipow(c2, P.zeta - 1);        // cos^(2 zeta - 2)
-        float uA = -eps * cz1 * c2;
+        T sx, cx;
+        const T u = (r - rmin) * (T)P.inv_w;              // (r - r_min) / (r_c - r_min)
+        if constexpr (sizeof(T) == 4) {
+            // x = (pi/2) u; the hardware sine and cosine take revolutions: x / 2pi = u / 4
+            sx = __builtin_amdgcn_sinf((T)0.25 * u);
+            cx = __builtin_amdgcn_cosf((T)0.25 * u);
+        } else {
+            sincos((T)0.5 * (T)M_PI * u, &sx, &cx);
+        }
+        const T c2 = cx * cx;
+        T cz1;                                            // cos^(2 zeta - 2)
+        if (FAST) cz1 = c2 * c2 * c2;
+        else cz1 = ipow(c2, P.zeta - 1);
+        const T uA = -eps * cz1 * c2;
         U = uA * phi;
-        dUdr = phi * eps * (float)P.zeta * 3.14159265358979f * inv_w * sx * cz1 * cx;
+        dUdr = phi * (T)P.dudr_k * sx * cz1 * cx;         // phi eps zeta pi / (r_c - r_min) sin x cos^(2 zeta - 1) x
         dUda = mu * uA;
     }
-    float gx = -t * nix - s * njx + st0 * (njx - nix);
-    float gy = -t * niy - s * njy + st0 * (njy - niy);
-    float gz = -t * niz - s * njz + st0 * (njz - niz);
-    float proj = gx * ex + gy * ey + gz * ez;
-    float k = dUda * rinv;
+    T gx = -t * nix - s * njx, gy = -t * niy - s * njy, gz = -t * niz - s * njz;
+    if (!FAST) {
+        gx += st0 * (njx - nix);
+        gy += st0 * (njy - niy);
+        gz += st0 * (njz - niz);
+    }
+    const T proj = gx * ex + gy * ey + gz * ez;
+    const T k = dUda * rinv;
     fx -= dUdr * ex + k * (gx - proj * ex);
     fy -= dUdr * ey + k * (gy - proj * ey);
     fz -= dUdr * ez + k * (gz - proj * ez);
     // torque on i: n_i x g_i with g_i = -dU/da (n_j - (t + sin th0) e)
-    float b = t + st0;
-    float wx = -dUda * (njx - b * ex), wy = -dUda * (njy - b * ey), wz = -dUda * (njz - b * ez);
-    tx += niy * wz - niz * wy;
-    ty += niz * wx - nix * wz;
-    tz += nix * wy - niy * wx;
-    return U;
-}
-
-template <>
-__device__ __forceinline__ double lipid_pair<double>(const DevParams &P, double dx, double dy, double dz, double nix,
-                                                     double niy, double niz, double njx, double njy, double njz,
-                                                     double &fx, double &fy, double &fz, double &tx, double &ty,
-                                                     double &tz) {
-    const double eps = P.eps, mu = P.mu, st0 = P.st0, rmin = P.r_min, rc = P.rc_lipid;
-    double r2 = dx * dx + dy * dy + dz * dz;
-    double r = sqrt(r2);
-    double rinv = 1.0 / r;
-    double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-    double s = nix * ex + niy * ey + niz * ez;
-    double t = njx * ex + njy * ey + njz * ez;
-    double c = nix * njx + niy * njy + niz * njz;
-    double a = c - s * t + st0 * (t - s) - st0 * st0;
-    double phi = 1.0 + mu * (a - 1.0);
-    double U, dUdr, dUda;
-    if (r < rmin) {
-        double q = (rmin * rinv) * (rmin * rinv);
-        U = eps * (q * q - 2.0 * q) + (1.0 - phi) * eps;
-        dUdr = 4.0 * eps * (q - q * q) * rinv;
-        dUda = -mu * eps;
-    } else {
-        double x = 0.5 * M_PI * (r - rmin) / (rc - rmin);
-        double sx, cx;
-        sincos(x, &sx, &cx);
-        double c2 = cx * cx;
-        double cz1 = ipow(c2, P.zeta - 1);
-        double uA = -eps * cz1 * c2;
-        U = uA * phi;
-        dUdr = phi * eps * (double)P.zeta * M_PI / (rc - rmin) * sx * cz1 * cx;
-        dUda = mu * uA;
-    }
-    double gx = -t * nix - s * njx + st0 * (njx - nix);
-    double gy = -t * niy - s * njy + st0 * (njy - niy);
-    double gz = -t * niz - s * njz + st0 * (njz - niz);
-    double proj = gx * ex + gy * ey + gz * ez;
-    double k = dUda * rinv;
-    fx -= dUdr * ex + k * (gx - proj * ex);
-    fy -= dUdr * ey + k * (gy - proj * ey);
-    fz -= dUdr * ez + k * (gz - proj * ez);
-    double b = t + st0;
-    double wx = -dUda * (njx - b * ex), wy = -dUda * (njy - b * ey), wz = -dUda * (njz - b * ez);
+    const T bb = t + st0;
+    const T wx = -dUda * (njx - bb * ex), wy = -dUda * (njy - bb * ey), wz = -dUda * (njz - bb * ez);
     tx += niy * wz - niz * wy;
     ty += niz * wx - nix * wz;
     tz += nix * wy - niy * wx;
@@ -149,11 +112,14 @@ __device__ __forceinline__ double lipid_pair<double>(const DevParams &P, double 
 template <class T>
 __device__ __forceinline__ T wca_pair(const DevParams &P, T dx, T dy, T dz, T &fx, T &fy, T &fz) {
     T r2 = dx * dx + dy * dy + dz * dz;
-    T sr2 = (T)P.wca_sig2 / r2;
+    T r2inv;
+    if constexpr (sizeof(T) == 4) r2inv = __builtin_amdgcn_rcpf(r2);
+    else r2inv = (T)1 / r2;
+    T sr2 = (T)P.wca_sig2 * r2inv;
     T sr6 = sr2 * sr2 * sr2;
     T e = (T)P.wca_eps;
     T U = (T)4 * e * (sr6 * sr6 - sr6) + e;
-    T f = (T)24 * e * ((T)2 * sr6 * sr6 - sr6) / r2;
+    T f = (T)24 * e * ((T)2 * sr6 * sr6 - sr6) * r2inv;
     fx += f * dx;
     fy += f * dy;
     fz += f * dz;
@@ -162,31 +128,28 @@ __device__ __forceinline__ T wca_pair(const DevParams &P, T dx, T dy, T dz, T &f
 
 // ------------------------------------------------------------------ force kernel
 
+// LDS stage per 256-particle block (structure of arrays): FP64 positions, and either
+// FP32 orientations with the type in w (mixed) or FP64 orientations and a type byte.
 template <int MIXED>
-struct Staged;
-template <>
-struct Staged<1> {
-    using P = D4;          // raw FP64 position, type in w (the separation is formed in FP64)
-    using N = float4;      // orientation (FP32)
-};
-template <>
-struct Staged<0> {
-    using P = D4;          // raw FP64 position, type in w
-    using N = D4;          // FP64 orientation
+struct StageBytes {
+    static constexpr int value = MIXED ? SMAX * (3 * 8 + 16) : SMAX * (6 * 8 + 1);
 };
 
 // One workgroup per 256 consecutive cell-sorted particles.  The block's partners
 // (its stage list) are read once from HBM into LDS; lane i then walks column i of
-// its chunk's list, whose entries index the LDS stage.  Every candidate takes the
-// exact FP64 neighbour test on FP64 positions in both modes; mixed mode rounds the
-// separation and orientations to FP32 for the pair law.
-template <int MIXED, int ENERGY, int KICK>
+// its chunk's 16-bit list of stage indices.  Every candidate takes the exact FP64
+// neighbour test on FP64 positions in both modes; mixed mode rounds the
+// separation and uses FP32 orientations for the pair law.
+template <int MIXED, int ENERGY, int KICK, int FAST>
 __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     using T = typename std::conditional<MIXED, float, double>::type;
-    using SP = typename Staged<MIXED>::P;
-    using SN = typename Staged<MIXED>::N;
-    __shared__ SP s_p[SMAX];
-    __shared__ SN s_n[SMAX];
+    __shared__ __align__(16) unsigned char s_raw[StageBytes<MIXED>::value];
+    double *s_x = reinterpret_cast<double *>(s_raw);
+    double *s_y = s_x + SMAX;
+    double *s_z = s_y + SMAX;
+    F4 *s_n4 = reinterpret_cast<F4 *>(s_z + SMAX);                // mixed
+    double *s_nx = s_z + SMAX, *s_ny = s_nx + SMAX, *s_nz = s_ny + SMAX;   // FP64
+    unsigned char *s_t = reinterpret_cast<unsigned char *>(s_nz + SMAX);   // FP64
     const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
     const SysDev &S = Sd[s];
     const int lb = blockIdx.x - L_maps.p[s];
@@ -199,13 +162,18 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     for (int q = tid; q < scnt; q += BLOCK) {
         const int slot = S.stage[(size_t)lb * SMAX + q];
         const D4 p = S.pos[slot];
-        const D4 o = S.ori[slot];
+        s_x[q] = p.x;
+        s_y[q] = p.y;
+        s_z[q] = p.z;
         if constexpr (MIXED) {
-            s_p[q] = p;
-            s_n[q] = make_float4((float)o.x, (float)o.y, (float)o.z, 0.0f);
+            const F4 o = S.ori32[slot];
+            s_n4[q] = F4{o.x, o.y, o.z, (float)p.w};
         } else {
-            s_p[q] = p;
-            s_n[q] = o;
+            const D4 o = S.ori[slot];
+            s_nx[q] = o.x;
+            s_ny[q] = o.y;
+            s_nz[q] = o.z;
+            s_t[q] = (unsigned char)p.w;
         }
     }
     __syncthreads();
@@ -217,60 +185,54 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
     double U = 0.0, W = 0.0;
     const int rows = min(S.nlk[chunk], MAXNB);
-    const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
-    if (scnt >= 0) {
-        if constexpr (MIXED) {
-            for (int r = 0; r < rows; ++r) {
-                const int e = valid ? col[r * CHUNK] : -1;
-                if (e < 0 || e >= scnt) continue;
-                const D4 pj = s_p[e];
-                const int tj = (int)pj.w;
-                double dx, dy, dz;
-                const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
-                if (!(d2 < P.rc2[ti][tj])) continue;
-                float ax = 0.f, ay = 0.f, az = 0.f, u;
-                if ((ti | tj) == 0) {
-                    const float4 nj = s_n[e];
-                    u = lipid_pair<float>(P, (float)dx, (float)dy, (float)dz, nix, niy, niz, nj.x, nj.y, nj.z, ax, ay,
-                                          az, tx, ty, tz);
-                } else {
-                    u = wca_pair<float>(P, (float)dx, (float)dy, (float)dz, ax, ay, az);
-                }
-                fx += ax;
-                fy += ay;
-                fz += az;
-                if (ENERGY) {
-                    U += 0.5 * (double)u;
-                    W += 0.5 * (dx * (double)ax + dy * (double)ay + dz * (double)az);
-                }
+    // cutoff row of this particle's type, selected by the partner's type without
+    // dynamic indexing; the periodic min-image only where the system has periodic axes
+    const double rcA = P.rc2[ti][0], rcB = P.rc2[ti][1], rcC = P.rc2[ti][2];
+    const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
+    auto staged_rows = [&](auto per_tag) {
+        constexpr bool PER = decltype(per_tag)::value;
+        const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
+        for (int r = 0; r < rows; ++r) {
+            const int e = valid ? (int)col[r * CHUNK] : 0xffff;
+            if (e >= scnt) continue;
+            int tj;
+            T njx, njy, njz;
+            if constexpr (MIXED) {
+                const F4 nj = s_n4[e];
+                tj = (int)nj.w;
+                njx = nj.x; njy = nj.y; njz = nj.z;
+            } else {
+                tj = s_t[e];
+                njx = s_nx[e]; njy = s_ny[e]; njz = s_nz[e];
             }
-        } else {
-            for (int r = 0; r < rows; ++r) {
-                const int e = valid ? col[r * CHUNK] : -1;
-                if (e < 0 || e >= scnt) continue;
-                const D4 pj = s_p[e];
-                const int tj = (int)pj.w;
-                double dx, dy, dz;
-                const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
-                if (!(d2 < P.rc2[ti][tj])) continue;
-                double ax = 0, ay = 0, az = 0, u;
-                if ((ti | tj) == 0) {
-                    const D4 nj = s_n[e];
-                    u = lipid_pair<double>(P, dx, dy, dz, nix, niy, niz, nj.x, nj.y, nj.z, ax, ay, az, tx, ty, tz);
-                } else {
-                    u = wca_pair<double>(P, dx, dy, dz, ax, ay, az);
-                }
-                fx += ax;
-                fy += ay;
-                fz += az;
-                if (ENERGY) {
-                    U += 0.5 * u;
-                    W += 0.5 * (dx * ax + dy * ay + dz * az);
-                }
+            double dx, dy, dz, d2;
+            if constexpr (PER) {
+                d2 = dist2_exact(S, pi.x, pi.y, pi.z, s_x[e], s_y[e], s_z[e], dx, dy, dz);
+            } else {
+                d2 = dist2_open(pi.x, pi.y, pi.z, s_x[e], s_y[e], s_z[e], dx, dy, dz);
+            }
+            const double rc2 = tj == 0 ? rcA : (tj == 1 ? rcB : rcC);
+            if (!(d2 < rc2)) continue;
+            T ax = 0, ay = 0, az = 0, u;
+            if ((ti | tj) == 0)
+                u = lipid_pair<T, FAST>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, njx, njy, njz, ax, ay, az, tx, ty, tz);
+            else
+                u = wca_pair<T>(P, (T)dx, (T)dy, (T)dz, ax, ay, az);
+            fx += ax;
+            fy += ay;
+            fz += az;
+            if (ENERGY) {
+                U += 0.5 * (double)u;
+                W += 0.5 * (dx * (double)ax + dy * (double)ay + dz * (double)az);
             }
         }
+    };
+    if (scnt >= 0) {
+        if (periodic) staged_rows(std::true_type{});
+        else staged_rows(std::false_type{});
     } else {
-        // block whose partners did not fit the stage: entries are global slots
+        // block whose partners did not fit the stage: the lists hold global slots
+        const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
         for (int r = 0; r < rows; ++r) {
             const int j = valid ? col[r * CHUNK] : -1;
             if (j < 0 || j >= S.n) continue;
@@ -283,8 +245,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
             T u;
             if ((ti | tj) == 0) {
                 const D4 nj = S.ori[j];
-                u = lipid_pair<T>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, (T)nj.x, (T)nj.y, (T)nj.z, ax, ay, az, tx,
-                                  ty, tz);
+                u = lipid_pair<T, FAST>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, (T)nj.x, (T)nj.y, (T)nj.z, ax, ay, az,
+                                        tx, ty, tz);
             } else {
                 u = wca_pair<T>(P, (T)dx, (T)dy, (T)dz, ax, ay, az);
             }
@@ -364,7 +326,13 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
 
 template <int MIXED, int ENERGY, int KICK>
 static void launch_force_t(const LaunchCtx &L, double dt) {
-    hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK>), dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm, dt);
+    const bool fast = L.prm.zeta == 4 && L.prm.st0 == 0.0;
+    if (fast)
+        hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 1>), dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
+                           dt);
+    else
+        hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 0>), dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
+                           dt);
 }
 
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt) {
@@ -426,6 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
             if (nn > 0.0) { n.x /= nn; n.y /= nn; n.z /= nn; }
             S.angv[i] = w;
             S.ori[i] = n;
+            S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
         }
         const D4 b = S.xb[i];
         const double ddx = p.x - b.x, ddy = p.y - b.y, ddz = p.z - b.z;
@@ -536,9 +505,10 @@ void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, in
 // ------------------------------------------------------------------ neighbour-set export
 
 // Pairs (gid_i < gid_j) of the list that pass the exact FP64 test, appended in any
-// order (one atomic per wavefront).  Staged entries are mapped back to slots.
+// order (one atomic per wavefront).
 __device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, int e) {
-    return scnt >= 0 ? S.stage[(size_t)blk * SMAX + e] : e;
+    (void)S; (void)blk; (void)scnt;
+    return e;                      // the 32-bit lists always hold slots
 }
 
 __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {

@@ -153,6 +153,8 @@ void make_dev_params(rbc_ctx *h) {
     d.inv_inertia = 1.0 / p.inertia;
     d.cell_search = search;
     d.zeta = (int32_t)p.zeta;
+    d.inv_w = 1.0 / (p.rc[0][0] - p.r_min);
+    d.dudr_k = p.eps * p.zeta * M_PI / (p.rc[0][0] - p.r_min);
 }
 
 // Sizes of one system and (with base != null) its device layout.
@@ -176,6 +178,8 @@ size_t layout(HostSys &s, char *base) {
     d.gstart = c.take<int32_t>(s.gcap + 1); d.gcount = c.take<int32_t>(s.gcap);
     d.gseed = c.take<int32_t>(k); d.sgcell = c.take<int32_t>(k);
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
+    d.nl16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK);
+    d.ori32 = c.take<F4>(n);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
     d.epart = c.take<double>((size_t)s.nchunk * 9);
     const int64_t nblkp = (n + BLOCK - 1) / BLOCK;

@@ -30,6 +30,10 @@ struct alignas(16) D4 {
     double x, y, z, w;
 };
 
+struct alignas(16) F4 {
+    float x, y, z, w;
+};
+
 // Per-system scalars living in device memory.
 struct alignas(256) SysScal {
     unsigned long long maxdisp2;      // bits of the largest |x - x_build|^2 since the last build
@@ -67,6 +71,8 @@ struct SysDev {
     int32_t *cnbr_start, *cnbr;                     // full cell-pair CSR (k+1, cnbr_cap)
     int32_t *gstart, *gcount, *gseed, *sgcell;      // seed grid (gcap+1, gcap, k, k)
     int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
+    uint16_t *nl16;                                 // the same lists as stage indices (staged blocks)
+    F4 *ori32;                                      // FP32 copy of the orientations (mixed-mode staging)
     int32_t *bstart, *bpart;                        // bonds by caller id (n+1, 2 nbond)
     double *br0;
     double *epart;                                  // per-chunk energy partials (nchunk x 9)
@@ -87,6 +93,8 @@ struct DevParams {
     double inv_mass[3];
     double inv_inertia;
     double cell_search;    // largest rc + 2 skin (cell-pair test slack)
+    double inv_w;          // 1 / (r_c - r_min)
+    double dudr_k;         // eps * zeta * pi / (r_c - r_min)
     int32_t zeta;
     int32_t pad;
 };
@@ -134,6 +142,21 @@ __device__ __forceinline__ double dist2_exact(const SysDev &S, double xi, double
     dx = minimg1(xi - xj, S.per[0], S.box[0]);
     dy = minimg1(yi - yj, S.per[1], S.box[1]);
     dz = minimg1(zi - zj, S.per[2], S.box[2]);
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double s = xx + yy;
+    return s + zz;
+}
+
+// The same squared distance for a system without periodic axes (identical
+// operations: the min-image is the identity on open axes).
+__device__ __forceinline__ double dist2_open(double xi, double yi, double zi, double xj, double yj, double zj,
+                                             double &dx, double &dy, double &dz) {
+#pragma clang fp contract(off)
+    dx = xi - xj;
+    dy = yi - yj;
+    dz = zi - zj;
     double xx = dx * dx;
     double yy = dy * dy;
     double zz = dz * dz;

@@ -330,3 +330,19 @@ def test_dense_3d_cloud_unstaged_blocks(R, mp, prec):
     assert rel_err(F, F0) < tol and rel_err(T, T0) < tol
     assert np.array_equal(c.get_pairs(), O.pairs(p, s.x, s.type))
     c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_forces_nondefault_constants(R, prec, ves):
+    """Generic pair-law path: spontaneous-curvature angle, zeta = 3, mu = 2.5."""
+    from paper_1701_02059_amd.inputs import ModelParams
+    mp2 = ModelParams(sin_theta0=0.1, zeta=3.0, mu=2.5)
+    sub = ves.subset(np.arange(0, 30000))
+    p = O.params_for(sub, mp2)
+    F0, T0, U0, W0 = O.forces(p, sub)
+    c = _ctx(R, mp2, sub, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
+    F, T, E = (to_np(t) for t in c.forces(energy=True))
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    assert rel_err(F, F0) < tol and rel_err(T, T0) < tol
+    assert E[0] == pytest.approx(U0, rel=tol)
+    c.close()
