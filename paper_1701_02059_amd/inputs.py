@@ -325,14 +325,18 @@ def biconcave_cell(nL: int = 3_600_000, nJ: int = 16_000, seed: int = 0, kT: flo
 
     The surface is scaled (sigma per micrometre) so that each lipid covers LIPID_AREA.
     Junctions use the same sampling, offset inward along the normal, triangulated
-    through the equal-area map to the unit sphere; beads sit on straight chords.
+    through the equal-area map to the unit sphere.  Beads start at even fractions
+    of the straight chord between their junctions and are then moved along the
+    local surface normal (that of the nearest lipid site) to the same depth under
+    the sheet as the junctions: on the strongly curved rim a bare chord would cut
+    into the lipid layer.
     """
     params = params or ModelParams()
     rng = np.random.default_rng(seed)
     t_tab, A_tab = evans_fung_area_table()
     scale = math.sqrt(nL * LIPID_AREA / A_tab[-1])
-    lip, nrm, _ = _ef_points(nL, t_tab, A_tab, scale)
-    lip = lip + rng.normal(0.0, jitter, size=(nL, 3))
+    site, nrm, _ = _ef_points(nL, t_tab, A_tab, scale)
+    lip = site + rng.normal(0.0, jitter, size=(nL, 3))
     jp, jn, jsph = _ef_points(nJ, t_tab, A_tab, scale)
     jpos = jp - ANCHOR_DEPTH * jn
     edges = _hull_edges(jsph)
@@ -341,11 +345,21 @@ def biconcave_cell(nL: int = 3_600_000, nJ: int = 16_000, seed: int = 0, kT: flo
         return a[:, None, :] + k[None, :, None] * (b - a)[:, None, :]
 
     beads, chain_bonds = _chains(jpos, edges, nL, nJ, beads_fn)
+    beads = _to_depth(beads, site, nrm, ANCHOR_DEPTH)
     anchors = _anchor_bonds(jpos, lip, nL)
     s = _assemble(f"rbc{nL + nJ + beads.shape[0]}", lip, nrm, jpos, beads, chain_bonds, anchors, rng, kT,
                   params, np.zeros(3), np.zeros(3, dtype=np.int32))
     s.scale = scale
     return s
+
+
+def _to_depth(p: np.ndarray, site: np.ndarray, nrm: np.ndarray, depth: float) -> np.ndarray:
+    """Move points along the normal of their nearest surface site to `depth` below it."""
+    from scipy.spatial import cKDTree
+    _, idx = cKDTree(site).query(p)
+    x0, n0 = site[idx], nrm[idx]
+    h = np.sum((p - x0) * n0, axis=1)
+    return p - (h + depth)[:, None] * n0
 
 
 # --------------------------------------------------------------------------- named workloads
