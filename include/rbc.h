@@ -90,7 +90,8 @@ rbc_status rbc_create(const rbc_params *params, void *hip_stream, rbc_handle *ou
 /* Load a system (sync).  [device] x, nrm, v, w: n x 3; type: n; bonds: nbond x 2
  * particle ids; r0: nbond rest lengths.  [host] box[3] lengths and periodic[3]
  * flags (1 = periodic axis; box ignored on open axes).  Periodic lengths must
- * exceed twice the largest cutoff plus skin.  n = 0 clears the context.
+ * exceed twice the largest cutoff plus skin.  0 <= n <= 2^29; n = 0 clears the
+ * context.
  * Builds the initial Voronoi cells (params.lloyd_iters k-means iterations). */
 rbc_status rbc_set_system(rbc_handle h, int64_t n, const double *x, const double *nrm,
                           const int32_t *type, const double *v, const double *w,

@@ -560,31 +560,26 @@ __global__ __launch_bounds__(BLOCK) void k_sort_hist(const SysDev *Sd, Maps L_ma
     S.hist[tile * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
+// Column scan of the tile histograms: one block per (system, digit) turns the
+// digit's per-tile counts into exclusive tile offsets within the digit and leaves
+// the digit's total after the last tile row (the scatter adds the digit bases).
 __global__ __launch_bounds__(256) void k_sort_scan(const SysDev *Sd, int kind) {
-    const SysDev &S = Sd[blockIdx.x];
+    const SysDev &S = Sd[blockIdx.x >> 8];
     if (!S.sc->rebuild) return;
+    const int d = blockIdx.x & 255;
     const int cnt = kind ? S.k : S.n;
     const int ntile = (cnt + SORT_TILE - 1) / SORT_TILE;
     __shared__ int s_w[16];
-    const int d = threadIdx.x;
-    constexpr int B = 16;            // tiles per batch: independent loads in flight
-    int run = 0;
-    for (int t0 = 0; t0 < ntile; t0 += B) {
-        int c[B];
-        for (int q = 0; q < B; ++q) c[q] = (t0 + q < ntile) ? S.hist[(t0 + q) * 256 + d] : 0;
-        for (int q = 0; q < B; ++q) {
-            if (t0 + q < ntile) S.hist[(t0 + q) * 256 + d] = run;
-            run += c[q];
-        }
+    int carry = 0;
+    for (int t0 = 0; t0 < ntile; t0 += 256) {
+        const int t = t0 + (int)threadIdx.x;
+        const int v = t < ntile ? S.hist[t * 256 + d] : 0;
+        int tot;
+        const int ex = block_excl_scan(v, s_w, tot);
+        if (t < ntile) S.hist[t * 256 + d] = carry + ex;
+        carry += tot;
     }
-    int tot;
-    int base = block_excl_scan(run, s_w, tot);
-    for (int t0 = 0; t0 < ntile; t0 += B) {
-        int c[B];
-        for (int q = 0; q < B; ++q) c[q] = (t0 + q < ntile) ? S.hist[(t0 + q) * 256 + d] : 0;
-        for (int q = 0; q < B; ++q)
-            if (t0 + q < ntile) S.hist[(t0 + q) * 256 + d] = c[q] + base;
-    }
+    if (threadIdx.x == 0) S.hist[ntile * 256 + d] = carry;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_sort_scatter(const SysDev *Sd, Maps L_maps, int kind, int pass) {
@@ -601,8 +596,14 @@ __global__ __launch_bounds__(BLOCK) void k_sort_scatter(const SysDev *Sd, Maps L
     const int shift = 8 * pass;
     __shared__ int s_base[256];
     __shared__ int s_cnt[BLOCK / WAVE][256];
+    __shared__ int s_w[16];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    s_base[tid] = S.hist[tile * 256 + tid];
+    {
+        const int ntile = (cnt + SORT_TILE - 1) / SORT_TILE;
+        int tot;
+        const int digit_base = block_excl_scan(S.hist[ntile * 256 + tid], s_w, tot);
+        s_base[tid] = S.hist[tile * 256 + tid] + digit_base;
+    }
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int r = 0; r < SORT_IPT; ++r) {
         for (int q = tid; q < (BLOCK / WAVE) * 256; q += BLOCK) s_cnt[q >> 8][q & 255] = 0;
@@ -641,7 +642,7 @@ static void sort_segments(const LaunchCtx &L, int kind, int key_bits) {
     int nblk = kind ? L.nblk_ts : L.nblk_tp;
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(BLOCK), 0, L.st, L.S, L.maps, kind, p);
-        hipLaunchKernelGGL(k_sort_scan, dim3(L.nsys), dim3(256), 0, L.st, L.S, kind);
+        hipLaunchKernelGGL(k_sort_scan, dim3(L.nsys * 256), dim3(256), 0, L.st, L.S, kind);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(BLOCK), 0, L.st, L.S, L.maps, kind, p);
     }
 }
@@ -1000,25 +1001,43 @@ __device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v) {
     return lo;
 }
 
+// Last candidate cell whose particle offset is <= u (offsets of empty cells repeat).
+__device__ __forceinline__ int union_cell(const int *ofs, int nsc, int u) {
+    int lo = 0, hi = nsc;
+    while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (ofs[m] <= u) lo = m; else hi = m;
+    }
+    return lo;
+}
+
 // One block per 256 consecutive cell-sorted particles (four 64-particle chunks).
+// Candidates: the cell-pair entries of the block's (consecutive) cells, sorted
+// and deduplicated in LDS; their particles form the block's candidate union.
 // Pass 1: each lane collects every partner within the list radius (rc + 2 skin of
 // the pair's types) by scanning the particles of every cell paired with its cell;
-// column `lane` of the chunk's ELL block holds them, padded with -1.
-// Pass 2: the union of all partners of the block is staged: the cell-pair entries
-// of the block's (consecutive) cells are sorted and deduplicated in LDS, partners
-// are marked in a bitmap over those cells' particles, a prefix popcount numbers
-// them, the block's stage list receives their slots and a 16-bit copy of every
-// list holds stage indices (0xffff pads).  Blocks whose union does not fit use
-// the global-slot lists (stage count -1).
+// column `lane` of the chunk's ELL block holds them.  When the union fits in LDS
+// its positions are staged there as FP32 offsets from the block's first particle
+// (with slot and type packed in w) and the test runs in FP32 against the list
+// radius widened by 1e-3 sigma, which bounds the offsets' rounding (offsets are
+// limited to 4096 sigma), so the list stays a superset of the FP64 one; the force
+// kernel applies the exact FP64 test to every entry.  Otherwise the test runs on
+// FP64 positions from global memory.
+// Pass 2: partners are marked in a bitmap over the union, a prefix popcount
+// numbers them, the block's stage list receives their slots and the 16-bit lists
+// hold stage indices (0xffff pads).  Blocks whose partners do not fit the stage
+// keep 32-bit lists of global slots (stage count -1).
 __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
     __shared__ int s_cand[CANDMAX];
     __shared__ int s_ofs[CANDMAX + 1];
+    __shared__ int s_qpos[CANDMAX];
     __shared__ unsigned s_bits[SSMAX / 32];
     __shared__ int s_wpre[SSMAX / 32 + 1];
+    __shared__ F4 s_u[USTAGE];
     __shared__ int s_w[16];
-    __shared__ int s_flag, s_rows;
+    __shared__ int s_flag, s_rows, s_big;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int chunk = lb * (BLOCK / WAVE) + wv;
     const bool chunk_ok = chunk < S.nchunk;
@@ -1029,10 +1048,119 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         if (tid == 0) { S.scount[lb] = 0; S.blkrows[lb] = 0; }
         return;
     }
+    if (tid == 0) { s_flag = 0; s_rows = 0; s_big = 0; }
+    for (int w = tid; w < SSMAX / 32; w += BLOCK) s_bits[w] = 0u;
+    __syncthreads();
+    // ---- candidate cells, their particle offsets, and the union position of every cell-pair entry
+    const int first = lb * BLOCK;
+    const int last = min(S.n - 1, first + BLOCK - 1);
+    const int c0 = S.owner[first], c1 = S.owner[last];
+    const int q0 = S.cnbr_start[c0];
+    const int ncand = S.cnbr_start[c1 + 1] - q0;
+    const bool have_union = !(ncand <= 0 || ncand > CANDMAX || c1 < c0);
+    int nsc = 0, ss = 0;
+    if (have_union) {
+        int pw = 1;
+        while (pw < ncand) pw <<= 1;
+        for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? S.cnbr[q0 + q] : INT_MAX;
+        __syncthreads();
+        for (int kk = 2; kk <= pw; kk <<= 1)
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int t = tid; t < pw; t += BLOCK) {
+                    int ixj = t ^ jj;
+                    if (ixj > t) {
+                        int va = s_cand[t], vb = s_cand[ixj];
+                        bool up = (t & kk) == 0;
+                        if ((va > vb) == up) { s_cand[t] = vb; s_cand[ixj] = va; }
+                    }
+                }
+                __syncthreads();
+            }
+        // deduplicate in place
+        int vals[CANDMAX / BLOCK], fl[CANDMAX / BLOCK], loc = 0;
+        for (int q = 0; q < CANDMAX / BLOCK; ++q) {
+            const int idx = tid * (CANDMAX / BLOCK) + q;
+            vals[q] = idx < pw ? s_cand[idx] : INT_MAX;
+            const int prev = (idx > 0 && idx < pw) ? s_cand[idx - 1] : INT_MIN;
+            fl[q] = (idx < ncand && (idx == 0 || vals[q] != prev)) ? 1 : 0;
+            loc += fl[q];
+        }
+        int p = block_excl_scan(loc, s_w, nsc);
+        for (int q = 0; q < CANDMAX / BLOCK; ++q)
+            if (fl[q]) s_cand[p++] = vals[q];
+        __syncthreads();
+        for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = S.ccount[s_cand[q]];
+        for (int q = tid; q < ncand; q += BLOCK) s_qpos[q] = lds_lower_bound(s_cand, nsc, S.cnbr[q0 + q]);
+        __syncthreads();
+        ss = block_scan_lds(s_ofs, nsc, s_w);
+        if (tid == 0) s_ofs[nsc] = ss;
+        __syncthreads();
+    }
+    // ---- stage the union as FP32 offsets when it fits
+    bool staged = have_union && ss <= USTAGE;
+    const D4 ref = S.pos[first];
+    const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
+    if (staged) {
+        float big = 0.0f;
+        for (int u = tid; u < ss; u += BLOCK) {
+            const int c = union_cell(s_ofs, nsc + 1, u);
+            const int slot = S.cstart[s_cand[c]] + (u - s_ofs[c]);
+            const D4 pj = S.pos[slot];
+            const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
+            const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
+            const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
+            s_u[u] = F4{ox, oy, oz, __int_as_float((slot << 2) | ((int)pj.w & 3))};
+            big = fmaxf(big, fmaxf(fabsf(ox), fmaxf(fabsf(oy), fabsf(oz))));
+        }
+        if (!(big <= LIST_EXTENT)) s_big = 1;       // also catches non-finite offsets
+        __syncthreads();
+        staged = s_big == 0;
+    }
     // ---- pass 1
     int cnt = 0;
     int32_t *col = S.nl + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
-    if (valid) {
+    uint16_t *col16 = S.nl16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
+    if (valid && staged) {
+        // entries are union indices (< USTAGE) in the 16-bit lists until pass 2
+        const D4 pi = S.pos[i];
+        const int ti = (int)pi.w;
+        const int A = S.owner[i];
+        const float oix = (float)minimg1(pi.x - ref.x, S.per[0], S.box[0]);
+        const float oiy = (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]);
+        const float oiz = (float)minimg1(pi.z - ref.z, S.per[2], S.box[2]);
+        const float rlA = P.rl2f[ti][0], rlB = P.rl2f[ti][1], rlC = P.rl2f[ti][2];
+        const int self = s_ofs[lds_lower_bound(s_cand, nsc, A)] + (i - S.cstart[A]);
+        const float Lx = S.per[0] ? (float)S.box[0] : 0.0f, Ly = S.per[1] ? (float)S.box[1] : 0.0f,
+                    Lz = S.per[2] ? (float)S.box[2] : 0.0f;
+        const float iLx = S.per[0] ? 1.0f / Lx : 0.0f, iLy = S.per[1] ? 1.0f / Ly : 0.0f,
+                    iLz = S.per[2] ? 1.0f / Lz : 0.0f;
+        const int qa = S.cnbr_start[A] - q0, qb = S.cnbr_start[A + 1] - q0;
+        auto scan_cells = [&](auto per_tag) {
+            constexpr bool PER = decltype(per_tag)::value;
+            for (int q = qa; q < qb; ++q) {
+                const int pos = s_qpos[q];
+                const int ue = s_ofs[pos + 1];
+                for (int u = s_ofs[pos]; u < ue; ++u) {
+                    const F4 c = s_u[u];
+                    float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
+                    if constexpr (PER) {
+                        dx -= Lx * rintf(dx * iLx);
+                        dy -= Ly * rintf(dy * iLy);
+                        dz -= Lz * rintf(dz * iLz);
+                    }
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    const int tj = __float_as_int(c.w) & 3;
+                    const float rl = tj == 0 ? rlA : (tj == 1 ? rlB : rlC);
+                    if (d2 < rl && u != self) {
+                        if (cnt < MAXNB) col16[cnt * CHUNK] = (uint16_t)u;
+                        ++cnt;
+                    }
+                }
+            }
+        };
+        if (periodic) scan_cells(std::true_type{});
+        else scan_cells(std::false_type{});
+    } else if (valid) {
         D4 pi = S.pos[i];
         int ti = (int)pi.w;
         int A = S.owner[i];
@@ -1057,112 +1185,84 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         rows = MAXNB;
     }
     const int mycnt = min(cnt, MAXNB);
-    if (chunk_ok) {
-        for (int r = mycnt; r < rows; ++r) col[r * CHUNK] = -1;
-        if (lane == 0) S.nlk[chunk] = rows;
-    }
-    if (tid == 0) { s_flag = 0; s_rows = 0; }
-    __syncthreads();
+    if (chunk_ok && lane == 0) S.nlk[chunk] = rows;
     if (lane == 0) atomicMax(&s_rows, rows);
-    // ---- pass 2: candidate cells = the contiguous cell-pair slice of the block's cells
-    const int first = lb * BLOCK;
-    const int last = min(S.n - 1, first + BLOCK - 1);
-    const int c0 = S.owner[first], c1 = S.owner[last];
-    const int q0 = S.cnbr_start[c0];
-    const int ncand = S.cnbr_start[c1 + 1] - q0;
-    bool overflow = (ncand <= 0 || ncand > CANDMAX || c1 < c0);
-    int nsc = 0;
-    if (!overflow) {
-        int pw = 1;
-        while (pw < ncand) pw <<= 1;
-        for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? S.cnbr[q0 + q] : INT_MAX;
-        __syncthreads();
-        for (int kk = 2; kk <= pw; kk <<= 1)
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int t = tid; t < pw; t += BLOCK) {
-                    int ixj = t ^ jj;
-                    if (ixj > t) {
-                        int va = s_cand[t], vb = s_cand[ixj];
-                        bool up = (t & kk) == 0;
-                        if ((va > vb) == up) { s_cand[t] = vb; s_cand[ixj] = va; }
-                    }
-                }
-                __syncthreads();
+    // ---- pass 2: mark partners in the union, number them, write the stage list
+    const int nwords = staged ? (USTAGE / 32) : (SSMAX / 32);
+    bool stage_ok = have_union && (staged || ss <= SSMAX);
+    if (stage_ok && valid) {
+        for (int r = 0; r < mycnt; ++r) {
+            int u;
+            if (staged) {
+                u = col16[r * CHUNK];
+            } else {
+                const int j = col[r * CHUNK];
+                const int B = S.owner[j];
+                const int pos = lds_lower_bound(s_cand, nsc, B);
+                if (pos >= nsc || s_cand[pos] != B) { s_flag = 1; continue; }
+                u = s_ofs[pos] + (j - S.cstart[B]);
             }
-        // deduplicate in place
-        int vals[8], fl[8], loc = 0;
-        for (int q = 0; q < 8; ++q) {
-            const int idx = tid * 8 + q;
-            vals[q] = idx < pw ? s_cand[idx] : INT_MAX;
-            const int prev = (idx > 0 && idx < pw) ? s_cand[idx - 1] : INT_MIN;
-            fl[q] = (idx < ncand && (idx == 0 || vals[q] != prev)) ? 1 : 0;
-            loc += fl[q];
-        }
-        int p = block_excl_scan(loc, s_w, nsc);
-        for (int q = 0; q < 8; ++q)
-            if (fl[q]) s_cand[p++] = vals[q];
-        __syncthreads();
-        // particle offsets of the candidate cells
-        for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = S.ccount[s_cand[q]];
-        __syncthreads();
-        const int ss = block_scan_lds(s_ofs, nsc, s_w);
-        if (tid == 0) s_ofs[nsc] = ss;
-        for (int w = tid; w < SSMAX / 32; w += BLOCK) s_bits[w] = 0u;
-        __syncthreads();
-        overflow = ss > SSMAX;
-        if (!overflow) {
-            if (valid)
-                for (int r = 0; r < mycnt; ++r) {
-                    const int j = col[r * CHUNK];
-                    const int B = S.owner[j];
-                    const int pos = lds_lower_bound(s_cand, nsc, B);
-                    if (pos >= nsc || s_cand[pos] != B) { s_flag = 1; continue; }
-                    const int sidx = s_ofs[pos] + (j - S.cstart[B]);
-                    atomicOr(&s_bits[sidx >> 5], 1u << (sidx & 31));
-                }
-            __syncthreads();
-            for (int w = tid; w < SSMAX / 32; w += BLOCK) s_wpre[w] = __popc(s_bits[w]);
-            __syncthreads();
-            const int staged = block_scan_lds(s_wpre, SSMAX / 32, s_w);
-            overflow = staged > SMAX || s_flag != 0;
-            if (!overflow) {
-                for (int w = tid; w < SSMAX / 32; w += BLOCK) {
-                    unsigned bits = s_bits[w];
-                    int r = s_wpre[w];
-                    while (bits) {
-                        const int b = __ffs(bits) - 1;
-                        bits &= bits - 1u;
-                        const int sidx = w * 32 + b;
-                        int lo = 0, hi = nsc;                 // last cell with offset <= sidx
-                        while (hi - lo > 1) {
-                            int m = (lo + hi) >> 1;
-                            if (s_ofs[m] <= sidx) lo = m; else hi = m;
-                        }
-                        S.stage[(size_t)lb * SMAX + r] = S.cstart[s_cand[lo]] + (sidx - s_ofs[lo]);
-                        ++r;
-                    }
-                }
-                if (chunk_ok) {
-                    uint16_t *col16 = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
-                    for (int r = 0; r < rows; ++r) {
-                        int local = 0xffff;
-                        if (valid && r < mycnt) {
-                            const int j = col[r * CHUNK];
-                            const int B = S.owner[j];
-                            const int pos = lds_lower_bound(s_cand, nsc, B);
-                            const int sidx = s_ofs[pos] + (j - S.cstart[B]);
-                            const int w = sidx >> 5;
-                            local = s_wpre[w] + __popc(s_bits[w] & ((1u << (sidx & 31)) - 1u));
-                        }
-                        col16[r * CHUNK] = (uint16_t)local;
-                    }
-                }
-                if (tid == 0) S.scount[lb] = staged;
-            }
+            atomicOr(&s_bits[u >> 5], 1u << (u & 31));
         }
     }
-    if (overflow && tid == 0) S.scount[lb] = -1;     // entries keep global slots
-    if (tid == 0) S.blkrows[lb] = s_rows;
+    __syncthreads();
+    int nstaged = 0;
+    if (stage_ok) {
+        for (int w = tid; w < nwords; w += BLOCK) s_wpre[w] = __popc(s_bits[w]);
+        __syncthreads();
+        nstaged = block_scan_lds(s_wpre, nwords, s_w);
+        stage_ok = nstaged <= SMAX && s_flag == 0;
+    }
+    if (stage_ok) {
+        for (int w = tid; w < nwords; w += BLOCK) {
+            unsigned bits = s_bits[w];
+            int r = s_wpre[w];
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                const int u = w * 32 + b;
+                int slot;
+                if (staged) {
+                    slot = __float_as_int(s_u[u].w) >> 2;
+                } else {
+                    const int c = union_cell(s_ofs, nsc + 1, u);
+                    slot = S.cstart[s_cand[c]] + (u - s_ofs[c]);
+                }
+                S.stage[(size_t)lb * SMAX + r] = slot;
+                ++r;
+            }
+        }
+        if (chunk_ok) {
+            for (int r = 0; r < rows; ++r) {
+                int local = 0xffff;
+                if (valid && r < mycnt) {
+                    int u;
+                    if (staged) {
+                        u = col16[r * CHUNK];
+                    } else {
+                        const int j = col[r * CHUNK];
+                        const int B = S.owner[j];
+                        u = s_ofs[lds_lower_bound(s_cand, nsc, B)] + (j - S.cstart[B]);
+                    }
+                    const int w = u >> 5;
+                    local = s_wpre[w] + __popc(s_bits[w] & ((1u << (u & 31)) - 1u));
+                }
+                col16[r * CHUNK] = (uint16_t)local;
+            }
+        }
+    } else if (chunk_ok) {
+        // unstaged block: the 32-bit lists hold global slots, padded with -1
+        for (int r = 0; r < rows; ++r) {
+            int j = -1;
+            if (valid && r < mycnt) j = staged ? (__float_as_int(s_u[col16[r * CHUNK]].w) >> 2) : col[r * CHUNK];
+            col[r * CHUNK] = j;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        S.scount[lb] = stage_ok ? nstaged : -1;
+        S.blkrows[lb] = s_rows;
+    }
 }
 
 void launch_nlist(const LaunchCtx &L) {

@@ -506,9 +506,15 @@ void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, in
 
 // Pairs (gid_i < gid_j) of the list that pass the exact FP64 test, appended in any
 // order (one atomic per wavefront).
-__device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, int e) {
-    (void)S; (void)blk; (void)scnt;
-    return e;                      // the 32-bit lists always hold slots
+// Staged blocks keep stage indices in the 16-bit lists (0xffff pads); the others
+// keep global slots in the 32-bit lists (-1 pads).
+__device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, int chunk, int lane, int r) {
+    const size_t at = (size_t)chunk * MAXNB * CHUNK + (size_t)r * CHUNK + lane;
+    if (scnt >= 0) {
+        const int e = S.nl16[at];
+        return e < scnt ? S.stage[(size_t)blk * SMAX + e] : -1;
+    }
+    return S.nl[at];
 }
 
 __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
@@ -518,14 +524,12 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
     const int chunk = i / CHUNK, lane = i % CHUNK, blk = i / BLOCK;
     D4 pi = {0, 0, 0, 0};
     int ti = 0, gi = 0, rows = 0, scnt = -1;
-    const int32_t *col = nullptr;
     if (valid) {
         pi = S.pos[i];
         ti = (int)pi.w;
         gi = S.gid[i];
         rows = min(S.nlk[chunk], MAXNB);
         scnt = S.scount[blk];
-        col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
     }
     int mine = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -544,9 +548,7 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
         }
         int k = 0;
         for (int r = 0; r < rows; ++r) {
-            const int e = col[r * CHUNK];
-            if (e < 0) continue;
-            const int j = entry_slot(S, blk, scnt, e);
+            const int j = entry_slot(S, blk, scnt, chunk, lane, r);
             if (j < 0 || j >= S.n) continue;
             const int gj = S.gid[j];
             if (gj <= gi) continue;

@@ -139,6 +139,7 @@ void make_dev_params(rbc_ctx *h) {
             d.rc2[a][b] = p.rc[a][b] * p.rc[a][b];
             double rl = p.rc[a][b] + 2.0 * p.skin;
             d.rl2[a][b] = rl * rl * (1.0 + 1e-12);
+            d.rl2f[a][b] = std::nextafter((float)((rl + 1e-3) * (rl + 1e-3)), INFINITY);
             search = std::max(search, rl);
         }
     d.rc_lipid = p.rc[0][0];
@@ -170,7 +171,7 @@ size_t layout(HostSys &s, char *base) {
     d.owner = c.take<int32_t>(n);
     d.key = c.take<uint64_t>(n); d.key2 = c.take<uint64_t>(n);
     d.val = c.take<uint32_t>(n); d.val2 = c.take<uint32_t>(n);
-    d.hist = c.take<int32_t>((size_t)256 * std::max(s.ntile_p, s.ntile_s));
+    d.hist = c.take<int32_t>((size_t)256 * (std::max(s.ntile_p, s.ntile_s) + 1));   // + digit totals
     d.seed = c.take<D4>(k); d.seed2 = c.take<D4>(k);
     d.cstart = c.take<int32_t>(k + 1); d.ccount = c.take<int32_t>(k); d.cstart2 = c.take<int32_t>(k + 1);
     d.ccount2 = c.take<int32_t>(k); d.cmap = c.take<int32_t>(k);
@@ -439,7 +440,7 @@ size_t footprint(const rbc_ctx *h, int64_t n, int64_t nlip, int64_t nbond) {
 rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const double *nrm, const int32_t *type,
                  const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
                  const double *box, const int32_t *periodic) {
-    if (n < 0 || n > (1ll << 30)) return fail(h, RBC_ERR_INVALID_ARG, "n out of range");
+    if (n < 0 || n > (1ll << 29)) return fail(h, RBC_ERR_INVALID_ARG, "n out of range (at most 2^29 particles)");
     if (n > 0 && (!x || !nrm || !type || !v || !w)) return fail(h, RBC_ERR_INVALID_ARG, "NULL state array");
     if (nbond < 0 || (nbond > 0 && (!bonds || !r0))) return fail(h, RBC_ERR_INVALID_ARG, "bad bond arrays");
     if (!box || !periodic) return fail(h, RBC_ERR_INVALID_ARG, "box and periodic are required");

@@ -15,8 +15,10 @@ constexpr int SORT_TILE = BLOCK * SORT_IPT;
 constexpr int MAX_SLOTS = 256;
 constexpr int CNBR_ROW_MAX = 2048;      // cell pairs per cell before the build reports overflow
 constexpr int SMAX = 1024;             // neighbours staged in LDS per 256-particle block
-constexpr int CANDMAX = 2048;          // candidate cells (cell-pair entries) per block while staging
+constexpr int CANDMAX = 1024;          // candidate cells (cell-pair entries) per block while staging
 constexpr int SSMAX = 4096;            // particles in a block's candidate cells while staging
+constexpr int USTAGE = 2048;           // candidate particles staged in LDS while building a block's lists
+constexpr float LIST_EXTENT = 4096.0f; // largest FP32 offset (sigma) allowed in that staging
 constexpr int SCAN_TILE = 2048;        // elements per block in the segmented scans
 constexpr int BRED = 8;                // doubles of per-block partial results
 
@@ -89,6 +91,7 @@ struct SysDev {
 struct DevParams {
     double rc2[3][3];      // fl(rc*rc): exact neighbour test
     double rl2[3][3];      // (rc + 2 skin)^2 with a small relative margin: list radius
+    float rl2f[3][3];      // (rc + 2 skin + 1e-3)^2 rounded up: list radius for FP32 offsets
     double rc_lipid, r_min, eps, mu, st0, wca_eps, wca_sig2, k_bond;
     double inv_mass[3];
     double inv_inertia;
