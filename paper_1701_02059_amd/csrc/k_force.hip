@@ -126,6 +126,43 @@ __device__ __forceinline__ T wca_pair(const DevParams &P, T dx, T dy, T dz, T &f
     return U;
 }
 
+// ------------------------------------------------------------------ integrator pieces
+
+// Free linear-rotor drift: n rotated about omega by |omega| dt (Rodrigues), then
+// renormalised.
+__device__ __forceinline__ D4 rotor_drift(D4 n, const D4 &w, double dt) {
+    const double wn = sqrt(w.x * w.x + w.y * w.y + w.z * w.z);
+    if (wn > 0.0) {
+        const double kx = w.x / wn, ky = w.y / wn, kz = w.z / wn;
+        double sn, cs;
+        sincos(wn * dt, &sn, &cs);
+        const double kn = kx * n.x + ky * n.y + kz * n.z;
+        const double cx = ky * n.z - kz * n.y, cy = kz * n.x - kx * n.z, cz = kx * n.y - ky * n.x;
+        const double ox = n.x * cs + cx * sn + kx * kn * (1.0 - cs);
+        const double oy = n.y * cs + cy * sn + ky * kn * (1.0 - cs);
+        const double oz = n.z * cs + cz * sn + kz * kn * (1.0 - cs);
+        n.x = ox; n.y = oy; n.z = oz;
+    }
+    const double nn = sqrt(n.x * n.x + n.y * n.y + n.z * n.z);
+    if (nn > 0.0) { n.x /= nn; n.y /= nn; n.z /= nn; }
+    return n;
+}
+
+// Per-wavefront drift statistics: the largest |x - x_build|^2 and |v|^2 of the
+// wave's particles go to the block's partial slots 2w and 2w+1; a non-finite
+// state raises the system's error bit.
+__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, double disp2, double v2, bool bad) {
+    disp2 = wave_maxd(disp2);
+    v2 = wave_maxd(v2);
+    const unsigned long long anybad = __ballot(bad);
+    if (lane_id_f() == 0) {
+        const int w = (threadIdx.x >> 6) & 3;
+        S.bred[(size_t)blk * BRED + 2 * w] = disp2;
+        S.bred[(size_t)blk * BRED + 2 * w + 1] = v2;
+        if (anybad) atomicOr(&S.sc->err, ERR_NONFINITE);
+    }
+}
+
 // ------------------------------------------------------------------ force kernel
 
 // LDS stage per 256-particle block (structure of arrays): FP64 positions, and either
@@ -140,6 +177,10 @@ struct StageBytes {
 // its chunk's 16-bit list of stage indices.  Every candidate takes the exact FP64
 // neighbour test on FP64 positions in both modes; mixed mode rounds the
 // separation and uses FP32 orientations for the pair law.
+// KICK: 0 stores F and tau; 1 also applies the closing half-kick of the step;
+// 2 applies the closing half-kick and then, with the same force, the opening
+// half-kick and drift of the next step (positions and orientations go to the
+// second buffers, which the stats kernel then swaps in), without storing F, tau.
 template <int MIXED, int ENERGY, int KICK, int FAST>
 __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -261,6 +302,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     }
     double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
     D4 v = {0.0, 0.0, 0.0, 0.0}, w = {0.0, 0.0, 0.0, 0.0};
+    double disp2 = 0.0, vmax2 = 0.0;
+    bool bad = false;
     const D4 Tq = {(double)tx, (double)ty, (double)tz, 0.0};
     if (valid) {
         // bonds of this particle (CSR by caller id), FP64 in both modes
@@ -281,25 +324,55 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
                 W += 0.5 * f * d2;
             }
         }
-        S.frc[i] = D4{Fx, Fy, Fz, 0.0};
-        S.trq[i] = Tq;
+        if (KICK != 2) {
+            S.frc[i] = D4{Fx, Fy, Fz, 0.0};
+            S.trq[i] = Tq;
+        }
         v = S.vel[i];
         w = S.angv[i];
         if (KICK) {
             const double h = 0.5 * dt * P.inv_mass[ti];
+            const double hw = 0.5 * dt * P.inv_inertia;
             v.x += h * Fx;
             v.y += h * Fy;
             v.z += h * Fz;
-            S.vel[i] = v;
             if (ti == 0) {
-                const double hw = 0.5 * dt * P.inv_inertia;
                 w.x += hw * Tq.x;
                 w.y += hw * Tq.y;
                 w.z += hw * Tq.z;
-                S.angv[i] = w;
+            }
+            if (KICK == 1) {
+                S.vel[i] = v;
+                if (ti == 0) S.angv[i] = w;
+            } else {
+                D4 vn = v, wn = w, xn = pi;
+                vn.x += h * Fx;
+                vn.y += h * Fy;
+                vn.z += h * Fz;
+                xn.x += dt * vn.x;
+                xn.y += dt * vn.y;
+                xn.z += dt * vn.z;
+                S.vel[i] = vn;
+                S.pos2[i] = xn;
+                D4 on = ni;
+                if (ti == 0) {
+                    wn.x += hw * Tq.x;
+                    wn.y += hw * Tq.y;
+                    wn.z += hw * Tq.z;
+                    S.angv[i] = wn;
+                    on = rotor_drift(ni, wn, dt);
+                }
+                S.ori2[i] = on;
+                S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
+                const D4 b = S.xb[i];
+                const double ddx = xn.x - b.x, ddy = xn.y - b.y, ddz = xn.z - b.z;
+                disp2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                vmax2 = vn.x * vn.x + vn.y * vn.y + vn.z * vn.z;
+                bad = !isfinite(xn.x + xn.y + xn.z + vn.x + vn.y + vn.z);
             }
         }
     }
+    if (KICK == 2) drift_stats(S, lb, disp2, vmax2, bad);
     if (ENERGY) {
         // per-chunk partials of U, W, KE, sum F and sum (r x F + tau), reduced across
         // the wavefront in a fixed butterfly (deterministic)
@@ -336,6 +409,11 @@ static void launch_force_t(const LaunchCtx &L, double dt) {
 }
 
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt) {
+    if (kick == 2) {
+        if (mixed) launch_force_t<1, 0, 2>(L, dt);
+        else launch_force_t<0, 0, 2>(L, dt);
+        return;
+    }
     const int key = (mixed ? 4 : 0) | (energy ? 2 : 0) | (kick ? 1 : 0);
     switch (key) {
         case 0: launch_force_t<0, 0, 0>(L, dt); break;
@@ -357,7 +435,8 @@ void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
     const SysDev &S = Sd[s];
-    const int i = (blockIdx.x - L_maps.p[s]) * BLOCK + threadIdx.x;
+    const int lb = blockIdx.x - L_maps.p[s];
+    const int i = lb * BLOCK + threadIdx.x;
     double disp2 = 0.0, v2 = 0.0;
     bool bad = false;
     if (i < S.n) {
@@ -373,25 +452,13 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
         S.vel[i] = v;
         S.pos[i] = p;
         if (t == 0) {
-            D4 w = S.angv[i], tq = S.trq[i], n = S.ori[i];
+            D4 w = S.angv[i];
+            const D4 tq = S.trq[i];
             const double hw = 0.5 * dt * P.inv_inertia;
             w.x += hw * tq.x;
             w.y += hw * tq.y;
             w.z += hw * tq.z;
-            const double wn = sqrt(w.x * w.x + w.y * w.y + w.z * w.z);
-            if (wn > 0.0) {
-                const double kx = w.x / wn, ky = w.y / wn, kz = w.z / wn;
-                double sn, cs;
-                sincos(wn * dt, &sn, &cs);
-                const double kn = kx * n.x + ky * n.y + kz * n.z;
-                const double cx = ky * n.z - kz * n.y, cy = kz * n.x - kx * n.z, cz = kx * n.y - ky * n.x;
-                const double ox = n.x * cs + cx * sn + kx * kn * (1.0 - cs);
-                const double oy = n.y * cs + cy * sn + ky * kn * (1.0 - cs);
-                const double oz = n.z * cs + cz * sn + kz * kn * (1.0 - cs);
-                n.x = ox; n.y = oy; n.z = oz;
-            }
-            const double nn = sqrt(n.x * n.x + n.y * n.y + n.z * n.z);
-            if (nn > 0.0) { n.x /= nn; n.y /= nn; n.z /= nn; }
+            const D4 n = rotor_drift(S.ori[i], w, dt);
             S.angv[i] = w;
             S.ori[i] = n;
             S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
@@ -402,50 +469,57 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
         v2 = v.x * v.x + v.y * v.y + v.z * v.z;
         bad = !isfinite(p.x + p.y + p.z + v.x + v.y + v.z);
     }
-    disp2 = wave_maxd(disp2);
-    v2 = wave_maxd(v2);
-    const unsigned long long anybad = __ballot(bad);
-    __shared__ double s_m[2][BLOCK / WAVE];
-    if (lane_id_f() == 0) {
-        s_m[0][threadIdx.x >> 6] = disp2;
-        s_m[1][threadIdx.x >> 6] = v2;
-        if (anybad) atomicOr(&S.sc->err, ERR_NONFINITE);
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        double m = s_m[threadIdx.x][0];
-        for (int q = 1; q < BLOCK / WAVE; ++q) m = fmax(m, s_m[threadIdx.x][q]);
-        S.bred[(size_t)(blockIdx.x - L_maps.p[s]) * BRED + threadIdx.x] = m;
-    }
+    drift_stats(S, lb, disp2, v2, bad);
 }
 
 // Largest displacement since the last build and largest drift speed, per system,
-// from the kick-drift block partials.
-__global__ __launch_bounds__(256) void k_stats_reduce(const SysDev *Sd, int nsys) {
-    const SysDev &S = Sd[blockIdx.x];
-    const int nblk = (S.n + BLOCK - 1) / BLOCK;
+// from the per-wavefront (displacement, speed) partials of the drift, which form
+// one pair per 64-particle chunk.  STATS_BLOCKS blocks per system fold their share
+// with an unsigned atomic max on the bits (non-negative doubles order like their
+// bit patterns).  swap: the drift wrote the second position / orientation buffers,
+// which become the current ones.
+constexpr int STATS_BLOCKS = 16;
+
+__global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int swap) {
+    SysDev &S = Sd[blockIdx.x / STATS_BLOCKS];
+    const int part = blockIdx.x % STATS_BLOCKS;
+    const int per = (S.nchunk + STATS_BLOCKS - 1) / STATS_BLOCKS;
+    const int c0 = part * per, c1 = min(S.nchunk, c0 + per);
+    const double2 *dv = reinterpret_cast<const double2 *>(S.bred);
     double d = 0.0, v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        d = fmax(d, S.bred[(size_t)b * BRED]);
-        v = fmax(v, S.bred[(size_t)b * BRED + 1]);
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+        const double2 x = dv[c];
+        d = fmax(d, x.x);
+        v = fmax(v, x.y);
     }
     d = wave_maxd(d);
     v = wave_maxd(v);
     __shared__ double s_m[2][4];
     if ((threadIdx.x & 63) == 0) { s_m[0][threadIdx.x >> 6] = d; s_m[1][threadIdx.x >> 6] = v; }
     __syncthreads();
-    if (threadIdx.x == 0 && nblk > 0) {
+    if (threadIdx.x == 0 && S.n > 0) {
         d = fmax(fmax(s_m[0][0], s_m[0][1]), fmax(s_m[0][2], s_m[0][3]));
         v = fmax(fmax(s_m[1][0], s_m[1][1]), fmax(s_m[1][2], s_m[1][3]));
         SysScal *sc = S.sc;
-        if (dbits(d) > sc->maxdisp2) sc->maxdisp2 = dbits(d);
-        if (dbits(v) > sc->maxv2) sc->maxv2 = dbits(v);
+        if (c1 > c0) {
+            atomicMax(&sc->maxdisp2, dbits(d));
+            atomicMax(&sc->maxv2, dbits(v));
+        }
+        if (swap && part == 0) {
+            D4 *t = S.pos; S.pos = S.pos2; S.pos2 = t;
+            t = S.ori; S.ori = S.ori2; S.ori2 = t;
+            F4 *f = S.ori32; S.ori32 = S.ori32b; S.ori32b = f;
+        }
     }
 }
 
 void launch_kick_drift(const LaunchCtx &L, double dt) {
     hipLaunchKernelGGL(k_kick_drift, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm, dt);
-    hipLaunchKernelGGL(k_stats_reduce, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(L.nsys * STATS_BLOCKS), dim3(256), 0, L.st, L.Sw, L.nsys, 0);
+}
+
+void launch_drift_stats_swap(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_stats_reduce, dim3(L.nsys * STATS_BLOCKS), dim3(256), 0, L.st, L.Sw, L.nsys, 1);
 }
 
 // ------------------------------------------------------------------ energy reduction

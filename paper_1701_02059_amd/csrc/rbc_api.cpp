@@ -181,6 +181,7 @@ size_t layout(HostSys &s, char *base) {
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
     d.nl16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK);
     d.ori32 = c.take<F4>(n);
+    d.ori32b = c.take<F4>(n);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
     d.epart = c.take<double>((size_t)s.nchunk * 9);
     const int64_t nblkp = (n + BLOCK - 1) / BLOCK;
@@ -249,6 +250,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
     HIPCHK(hipStreamSynchronize(h->st));   // host staging vectors go out of scope
     LaunchCtx &L = h->L;
     L.S = h->d_sys;
+    L.Sw = h->d_sys;
     L.maps.p = h->d_maps;
     L.maps.c = h->d_maps + (ns + 1);
     L.maps.g = h->d_maps + 2 * (ns + 1);
@@ -369,15 +371,30 @@ rbc_status ensure_forces(rbc_ctx *h) {
     return RBC_OK;
 }
 
+// The drift of every step but the first is fused into the previous step's force
+// kernel, which wrote the second position / orientation buffers; the stats kernel
+// swaps them in on the device, and the host mirror follows.
+void swap_drift_buffers(rbc_ctx *h) {
+    launch_drift_stats_swap(h->L);
+    for (auto &hs : h->sys)
+        if (hs.live) {
+            std::swap(hs.dev.pos, hs.dev.pos2);
+            std::swap(hs.dev.ori, hs.dev.ori2);
+            std::swap(hs.dev.ori32, hs.dev.ori32b);
+        }
+}
+
 // The time-step loop over every live system.
 rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     if (!any_live(h)) return RBC_OK;
+    if (nsteps <= 0) return RBC_OK;
     ensure_forces(h);
     const double skin = h->prm.skin;
     const int64_t K = h->prm.update_every;
     rbc_status out = RBC_OK;
+    launch_kick_drift(h->L, dt);
     for (int64_t st = 0; st < nsteps; ++st) {
-        launch_kick_drift(h->L, dt);
+        const bool last = st + 1 == nsteps;
         const int slot = (int)(h->ring_pos % RING);
         h->ring_pos++;
         SysScal *ring = h->h_ring + (size_t)slot * MAX_SLOTS;
@@ -400,7 +417,8 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             if (need) which.push_back(s);
         }
         run_update(h, which, 0);
-        force_launch(h, 0, 1, dt);
+        force_launch(h, 0, last ? 1 : 2, dt);
+        if (!last) swap_drift_buffers(h);
         // while the force runs, read this step's kick-drift statistics
         hipEventSynchronize(h->ring_ev[slot]);
         for (int s = 0; s < h->nsys; ++s) {

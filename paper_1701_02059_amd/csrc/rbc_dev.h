@@ -75,6 +75,7 @@ struct SysDev {
     int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
     uint16_t *nl16;                                 // the same lists as stage indices (staged blocks)
     F4 *ori32;                                      // FP32 copy of the orientations (mixed-mode staging)
+    F4 *ori32b;                                     // its second buffer (fused drift target; pos2 / ori2 likewise)
     int32_t *bstart, *bpart;                        // bonds by caller id (n+1, 2 nbond)
     double *br0;
     double *epart;                                  // per-chunk energy partials (nchunk x 9)
@@ -189,6 +190,7 @@ namespace rbc {
 
 struct LaunchCtx {
     const SysDev *S;         // device array of systems
+    SysDev *Sw;              // the same array, for the kernel that swaps the drift buffers
     Maps maps;
     int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts, nblk_sc, nblk_sg;   // totals over systems
     int32_t nsys;
@@ -198,6 +200,7 @@ struct LaunchCtx {
 
 // step kernels
 void launch_kick_drift(const LaunchCtx &L, double dt);   // includes the per-system statistics reduction
+void launch_drift_stats_swap(const LaunchCtx &L);         // statistics of a fused drift, then buffer swap
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt);
 void launch_reduce_energy(const LaunchCtx &L);
 void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count);
