@@ -201,13 +201,13 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     const bool valid = i < S.n;
     const int scnt = S.scount[lb];
     for (int q = tid; q < scnt; q += BLOCK) {
-        const int slot = S.stage[(size_t)lb * SMAX + q];
-        const D4 p = S.pos[slot];
+        const int slot = ldg(S.stage + (size_t)lb * SMAX + q);
+        const D4 p = ldg(S.pos + slot);
         s_x[q] = p.x;
         s_y[q] = p.y;
         s_z[q] = p.z;
         if constexpr (MIXED) {
-            const F4 o = S.ori32[slot];
+            const F4 o = ldg(S.ori32 + slot);
             s_n4[q] = F4{o.x, o.y, o.z, (float)p.w};
         } else {
             const D4 o = S.ori[slot];
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     }
     __syncthreads();
     if (chunk >= S.nchunk) return;
-    const D4 pi = valid ? S.pos[i] : D4{0.0, 0.0, 0.0, 0.0};
-    const D4 ni = valid ? S.ori[i] : D4{0.0, 0.0, 0.0, 0.0};
+    const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
+    const D4 ni = valid ? ldg(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
     const int ti = (int)pi.w;
     const T nix = (T)ni.x, niy = (T)ni.y, niz = (T)ni.z;
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
@@ -233,8 +233,10 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     auto staged_rows = [&](auto per_tag) {
         constexpr bool PER = decltype(per_tag)::value;
         const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
+        int e_next = (valid && rows > 0) ? (int)ldg(col) : 0xffff;
         for (int r = 0; r < rows; ++r) {
-            const int e = valid ? (int)col[r * CHUNK] : 0xffff;
+            const int e = e_next;                       // next row's entry is in flight meanwhile
+            e_next = (valid && r + 1 < rows) ? (int)ldg(col + (r + 1) * CHUNK) : 0xffff;
             if (e >= scnt) continue;
             int tj;
             T njx, njy, njz;

@@ -176,6 +176,23 @@ __device__ __forceinline__ double wrap_coord(double v, int per, double L) {
     return w;
 }
 
+// Loads through the global address space (the descriptor table holds generic
+// pointers, which would otherwise compile to flat loads that also wait on LDS).
+template <class T>
+__device__ __forceinline__ T ldg(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+__device__ __forceinline__ D4 ldg(const D4 *p) {
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    const v4d v = *(const __attribute__((address_space(1))) v4d *)p;
+    return D4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ F4 ldg(const F4 *p) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f v = *(const __attribute__((address_space(1))) v4f *)p;
+    return F4{v.x, v.y, v.z, v.w};
+}
+
 __device__ __forceinline__ unsigned long long dbits(double v) {
     return (unsigned long long)__double_as_longlong(v);
 }
