@@ -422,6 +422,12 @@ __global__ void k_grid_sortcells(const SysDev *Sd, Maps L_maps) {
         while (j >= b && S.gseed[j] > v) { S.gseed[j + 1] = S.gseed[j]; --j; }
         S.gseed[j + 1] = v;
     }
+    // centroid positions in grid order, seed index in w (one load per candidate in the E-step)
+    for (int q = b; q < e; ++q) {
+        const int sd = S.gseed[q];
+        const D4 c = S.seed[sd];
+        S.gpos[q] = D4{c.x, c.y, c.z, (double)sd};
+    }
 }
 
 void launch_grid_build(const LaunchCtx &L) {
@@ -489,9 +495,10 @@ __device__ int nearest_seed(const SysDev &S, const SysScal *sc, double xi, doubl
                     int gz = cc[2] + oz;
                     if (S.per[2]) gz = (gz % sc->gdim[2] + sc->gdim[2]) % sc->gdim[2];
                     int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
-                    for (int q = S.gstart[g]; q < S.gstart[g + 1]; ++q) {
-                        int sd = S.gseed[q];
-                        D4 c = S.seed[sd];
+                    const int qe = ldg(S.gstart + g + 1);
+                    for (int q = ldg(S.gstart + g); q < qe; ++q) {
+                        const D4 c = ldg(S.gpos + q);
+                        const int sd = (int)c.w;
                         double d2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
                         if (d2 < bestd2 || (d2 == bestd2 && sd < best)) { bestd2 = d2; best = sd; }
                     }
@@ -860,7 +867,6 @@ __global__ void k_cell_bounds(const SysDev *Sd, Maps L_maps) {
     SYS_FROM(c);
     if (!S.sc->rebuild) return;
     int c = lb * BLOCK + threadIdx.x;
-    if (c >= S.k) return;
     double R = 0.0;
     if (c < S.k) {
         D4 sd = S.seed[c];
@@ -911,9 +917,10 @@ __device__ int cell_query(const SysDev &S, const SysScal *sc, int A, double sear
             for (int gz0 = lo[2]; gz0 <= hi[2]; ++gz0) {
                 int gz = S.per[2] ? ((gz0 % sc->gdim[2]) + sc->gdim[2]) % sc->gdim[2] : gz0;
                 int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
-                for (int q = S.gstart[g]; q < S.gstart[g + 1]; ++q) {
-                    int B = S.gseed[q];
-                    D4 cb = S.seed[B];
+                const int qe = ldg(S.gstart + g + 1);
+                for (int q = ldg(S.gstart + g); q < qe; ++q) {
+                    const int B = ldg(S.gseed + q);
+                    const D4 cb = ldg(S.seed + B);
                     double d = sqrt(dist2_exact(S, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, dx, dy, dz));
                     if (d <= Ra + cb.w + search + 1e-9) {
                         if (mode && cnt < cap) out[cnt] = B;
@@ -1036,6 +1043,7 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
     __shared__ unsigned s_bits[SSMAX / 32];
     __shared__ int s_wpre[SSMAX / 32 + 1];
     __shared__ F4 s_u[USTAGE];
+    __shared__ F4 s_cb[CULLMAX];
     __shared__ int s_w[16];
     __shared__ int s_flag, s_rows, s_big;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1062,7 +1070,7 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
     if (have_union) {
         int pw = 1;
         while (pw < ncand) pw <<= 1;
-        for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? S.cnbr[q0 + q] : INT_MAX;
+        for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? ldg(S.cnbr + q0 + q) : INT_MAX;
         __syncthreads();
         for (int kk = 2; kk <= pw; kk <<= 1)
             for (int jj = kk >> 1; jj > 0; jj >>= 1) {
@@ -1089,23 +1097,34 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         for (int q = 0; q < CANDMAX / BLOCK; ++q)
             if (fl[q]) s_cand[p++] = vals[q];
         __syncthreads();
-        for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = S.ccount[s_cand[q]];
-        for (int q = tid; q < ncand; q += BLOCK) s_qpos[q] = lds_lower_bound(s_cand, nsc, S.cnbr[q0 + q]);
+        for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = ldg(S.ccount + s_cand[q]);
+        for (int q = tid; q < ncand; q += BLOCK) s_qpos[q] = lds_lower_bound(s_cand, nsc, ldg(S.cnbr + q0 + q));
         __syncthreads();
         ss = block_scan_lds(s_ofs, nsc, s_w);
         if (tid == 0) s_ofs[nsc] = ss;
         __syncthreads();
     }
-    // ---- stage the union as FP32 offsets when it fits
+    // ---- stage the union as FP32 offsets when it fits, with the candidate cells'
+    // centroids and radii (widened by 2e-3 sigma for the offsets' rounding)
     bool staged = have_union && ss <= USTAGE;
-    const D4 ref = S.pos[first];
+    const bool cull = nsc <= CULLMAX;
+    const D4 ref = ldg(S.pos + first);
     const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
     if (staged) {
         float big = 0.0f;
+        if (cull)
+            for (int q = tid; q < nsc; q += BLOCK) {
+                const D4 c = ldg(S.seed + s_cand[q]);
+                const float ox = (float)minimg1(c.x - ref.x, S.per[0], S.box[0]);
+                const float oy = (float)minimg1(c.y - ref.y, S.per[1], S.box[1]);
+                const float oz = (float)minimg1(c.z - ref.z, S.per[2], S.box[2]);
+                s_cb[q] = F4{ox, oy, oz, (float)c.w + 2e-3f};
+                big = fmaxf(big, fmaxf(fabsf(ox), fmaxf(fabsf(oy), fabsf(oz))));
+            }
         for (int u = tid; u < ss; u += BLOCK) {
             const int c = union_cell(s_ofs, nsc + 1, u);
-            const int slot = S.cstart[s_cand[c]] + (u - s_ofs[c]);
-            const D4 pj = S.pos[slot];
+            const int slot = ldg(S.cstart + s_cand[c]) + (u - s_ofs[c]);
+            const D4 pj = ldg(S.pos + slot);
             const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
             const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
             const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
@@ -1129,6 +1148,7 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         const float oiy = (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]);
         const float oiz = (float)minimg1(pi.z - ref.z, S.per[2], S.box[2]);
         const float rlA = P.rl2f[ti][0], rlB = P.rl2f[ti][1], rlC = P.rl2f[ti][2];
+        const float rlmax = P.rlmaxf[ti];
         const int self = s_ofs[lds_lower_bound(s_cand, nsc, A)] + (i - S.cstart[A]);
         const float Lx = S.per[0] ? (float)S.box[0] : 0.0f, Ly = S.per[1] ? (float)S.box[1] : 0.0f,
                     Lz = S.per[2] ? (float)S.box[2] : 0.0f;
@@ -1139,6 +1159,18 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
             constexpr bool PER = decltype(per_tag)::value;
             for (int q = qa; q < qb; ++q) {
                 const int pos = s_qpos[q];
+                if (cull) {
+                    // skip cells whose bounding sphere lies beyond the list radius
+                    const F4 cb = s_cb[pos];
+                    float dx = cb.x - oix, dy = cb.y - oiy, dz = cb.z - oiz;
+                    if constexpr (PER) {
+                        dx -= Lx * rintf(dx * iLx);
+                        dy -= Ly * rintf(dy * iLy);
+                        dz -= Lz * rintf(dz * iLz);
+                    }
+                    const float rr = cb.w + rlmax;
+                    if (dx * dx + dy * dy + dz * dz > rr * rr) continue;
+                }
                 const int ue = s_ofs[pos + 1];
                 for (int u = s_ofs[pos]; u < ue; ++u) {
                     const F4 c = s_u[u];
@@ -1152,8 +1184,9 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
                     const int tj = __float_as_int(c.w) & 3;
                     const float rl = tj == 0 ? rlA : (tj == 1 ? rlB : rlC);
                     if (d2 < rl && u != self) {
-                        if (cnt < MAXNB) col16[cnt * CHUNK] = (uint16_t)u;
+                        if (cnt < MAXNB) stg(col16 + cnt * CHUNK, (uint16_t)u);
                         ++cnt;
+                        atomicOr(&s_bits[u >> 5], 1u << (u & 31));     // partner of the block
                     }
                 }
             }
@@ -1165,15 +1198,15 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         int ti = (int)pi.w;
         int A = S.owner[i];
         for (int q = S.cnbr_start[A]; q < S.cnbr_start[A + 1]; ++q) {
-            int B = S.cnbr[q];
-            int b = S.cstart[B], e = b + S.ccount[B];
+            int B = ldg(S.cnbr + q);
+            int b = ldg(S.cstart + B), e = b + ldg(S.ccount + B);
             for (int j = b; j < e; ++j) {
                 if (j == i) continue;
-                D4 pj = S.pos[j];
+                D4 pj = ldg(S.pos + j);
                 double dx, dy, dz;
                 double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
                 if (d2 < P.rl2[ti][(int)pj.w]) {
-                    if (cnt < MAXNB) col[cnt * CHUNK] = j;
+                    if (cnt < MAXNB) stg(col + cnt * CHUNK, (int32_t)j);
                     ++cnt;
                 }
             }
@@ -1190,13 +1223,11 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
     // ---- pass 2: mark partners in the union, number them, write the stage list
     const int nwords = staged ? (USTAGE / 32) : (SSMAX / 32);
     bool stage_ok = have_union && (staged || ss <= SSMAX);
-    if (stage_ok && valid) {
+    if (stage_ok && valid && !staged) {            // staged blocks marked their partners in pass 1
         for (int r = 0; r < mycnt; ++r) {
             int u;
-            if (staged) {
-                u = col16[r * CHUNK];
-            } else {
-                const int j = col[r * CHUNK];
+            {
+                const int j = ldg(col + r * CHUNK);
                 const int B = S.owner[j];
                 const int pos = lds_lower_bound(s_cand, nsc, B);
                 if (pos >= nsc || s_cand[pos] != B) { s_flag = 1; continue; }
@@ -1226,36 +1257,52 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
                     slot = __float_as_int(s_u[u].w) >> 2;
                 } else {
                     const int c = union_cell(s_ofs, nsc + 1, u);
-                    slot = S.cstart[s_cand[c]] + (u - s_ofs[c]);
+                    slot = ldg(S.cstart + s_cand[c]) + (u - s_ofs[c]);
                 }
-                S.stage[(size_t)lb * SMAX + r] = slot;
+                stg(S.stage + (size_t)lb * SMAX + r, (int32_t)slot);
                 ++r;
             }
         }
-        if (chunk_ok) {
+        if (chunk_ok && staged) {
+            // union index -> stage index, eight rows per batch of loads
+            for (int r0 = 0; r0 < rows; r0 += 8) {
+                int u8[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    u8[q] = (valid && r0 + q < mycnt) ? (int)ldg(col16 + (r0 + q) * CHUNK) : -1;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (r0 + q >= rows) break;
+                    int local = 0xffff;
+                    if (u8[q] >= 0) {
+                        const int w = u8[q] >> 5;
+                        local = s_wpre[w] + __popc(s_bits[w] & ((1u << (u8[q] & 31)) - 1u));
+                    }
+                    stg(col16 + (r0 + q) * CHUNK, (uint16_t)local);
+                }
+            }
+        } else if (chunk_ok) {
             for (int r = 0; r < rows; ++r) {
                 int local = 0xffff;
                 if (valid && r < mycnt) {
                     int u;
-                    if (staged) {
-                        u = col16[r * CHUNK];
-                    } else {
-                        const int j = col[r * CHUNK];
+                    {
+                        const int j = ldg(col + r * CHUNK);
                         const int B = S.owner[j];
                         u = s_ofs[lds_lower_bound(s_cand, nsc, B)] + (j - S.cstart[B]);
                     }
                     const int w = u >> 5;
                     local = s_wpre[w] + __popc(s_bits[w] & ((1u << (u & 31)) - 1u));
                 }
-                col16[r * CHUNK] = (uint16_t)local;
+                stg(col16 + r * CHUNK, (uint16_t)local);
             }
         }
     } else if (chunk_ok) {
         // unstaged block: the 32-bit lists hold global slots, padded with -1
         for (int r = 0; r < rows; ++r) {
             int j = -1;
-            if (valid && r < mycnt) j = staged ? (__float_as_int(s_u[col16[r * CHUNK]].w) >> 2) : col[r * CHUNK];
-            col[r * CHUNK] = j;
+            if (valid && r < mycnt) j = staged ? (__float_as_int(s_u[ldg(col16 + r * CHUNK)].w) >> 2) : ldg(col + r * CHUNK);
+            stg(col + r * CHUNK, (int32_t)j);
         }
     }
     __syncthreads();

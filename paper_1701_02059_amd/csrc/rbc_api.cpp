@@ -7,6 +7,9 @@
 // step of lookahead: after each kick-drift the per-system displacement statistics
 // are copied to pinned memory, and while the force kernel of step s runs the
 // host decides which systems need a cell update before the force of step s+1.
+// With graphs enabled (the default for ensembles) the fixed launch sequences of
+// a step -- the force kernel with its fused drift, and the whole cell update --
+// are captured once per system table and time step and replayed as HIP graphs.
 #include "../../include/rbc.h"
 #include "rbc_dev.h"
 
@@ -77,6 +80,12 @@ struct rbc_ctx {
     int sticky = RBC_OK;
     std::string err;
     int64_t ens_steps = 0;
+    // captured launch sequences (replayed while the system table and dt are unchanged)
+    bool graphs = false;
+    int64_t table_version = 0;
+    int64_t graph_version = -1;
+    double graph_dt = 0.0;
+    hipGraphExec_t g_step = nullptr, g_last = nullptr, g_upd = nullptr;
     // force-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tb, te;
@@ -134,6 +143,11 @@ void make_dev_params(rbc_ctx *h) {
     const rbc_params &p = h->prm;
     DevParams &d = h->dprm;
     double search = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double m = 0.0;
+        for (int b = 0; b < 3; ++b) m = std::max(m, p.rc[a][b] + 2.0 * p.skin + 1e-3);
+        d.rlmaxf[a] = std::nextafter((float)m, INFINITY);
+    }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             d.rc2[a][b] = p.rc[a][b] * p.rc[a][b];
@@ -178,6 +192,7 @@ size_t layout(HostSys &s, char *base) {
     d.cnbr_start = c.take<int32_t>(k + 1); d.cnbr = c.take<int32_t>(s.cnbr_cap);
     d.gstart = c.take<int32_t>(s.gcap + 1); d.gcount = c.take<int32_t>(s.gcap);
     d.gseed = c.take<int32_t>(k); d.sgcell = c.take<int32_t>(k);
+    d.gpos = c.take<D4>(k);
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
     d.nl16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK);
     d.ori32 = c.take<F4>(n);
@@ -248,6 +263,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
     HIPCHK(hipMemcpyAsync(h->d_maps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice, h->st));
     HIPCHK(hipMemcpyAsync(h->d_lip, lips.data(), sizeof(void *) * ns, hipMemcpyHostToDevice, h->st));
     HIPCHK(hipStreamSynchronize(h->st));   // host staging vectors go out of scope
+    h->table_version++;
     LaunchCtx &L = h->L;
     L.S = h->d_sys;
     L.Sw = h->d_sys;
@@ -278,6 +294,8 @@ bool any_live(const rbc_ctx *h) {
     return false;
 }
 
+void update_body(rbc_ctx *h, int bits, int lloyd);
+
 // Run the cell update for the systems in `mask`.  lloyd > 0: seed from lipids and
 // run that many k-means iterations first.
 void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
@@ -290,7 +308,21 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
     }
     const LaunchCtx &L = h->L;
     launch_set_rebuild(L, m);
-    const int bits = key_bits(kmax);
+    if (lloyd == 0 && h->graphs && h->g_upd && h->graph_version == h->table_version) {
+        hipGraphLaunch(h->g_upd, h->st);
+    } else {
+        update_body(h, key_bits(kmax), lloyd);
+    }
+    for (int s : which) {
+        HostSys &hs = h->sys[s];
+        hs.updates++;
+        hs.steps_since = 0;
+    }
+}
+
+// The cell-update launches for the systems whose rebuild flag is set.
+void update_body(rbc_ctx *h, int bits, int lloyd) {
+    const LaunchCtx &L = h->L;
     auto estep_msteps = [&](int iters) {
         for (int it = 0; it < iters; ++it) {
             if (it > 0) launch_grid_build(L);
@@ -315,11 +347,6 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
     launch_cell_pairs(L);
     launch_nlist(L);
     launch_finish_update(L);
-    for (int s : which) {
-        HostSys &hs = h->sys[s];
-        hs.updates++;
-        hs.steps_since = 0;
-    }
 }
 
 rbc_status read_errors(rbc_ctx *h, const SysScal *sc) {
@@ -371,11 +398,59 @@ rbc_status ensure_forces(rbc_ctx *h) {
     return RBC_OK;
 }
 
+void drop_graphs(rbc_ctx *h) {
+    for (hipGraphExec_t *g : {&h->g_step, &h->g_last, &h->g_upd})
+        if (*g) {
+            hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
+    h->graph_version = -1;
+}
+
+template <class F>
+hipGraphExec_t capture(rbc_ctx *h, F body) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    if (hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    body();
+    if (hipStreamEndCapture(h->st, &g) != hipSuccess || !g) return nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+    hipGraphDestroy(g);
+    return ex;
+}
+
+// Capture the step and update sequences for the current table and dt.  The sort
+// in the captured update takes as many radix passes as the largest live system
+// needs.  Returns false (eager launches are used) if capture fails.
+bool ensure_graphs(rbc_ctx *h, double dt) {
+    if (h->graph_version == h->table_version && h->graph_dt == dt && h->g_step && h->g_last && h->g_upd) return true;
+    drop_graphs(h);
+    const int mixed = h->prm.precision == RBC_MIXED;
+    int32_t kmax = 1;
+    for (const auto &hs : h->sys)
+        if (hs.live) kmax = std::max(kmax, hs.k);
+    const int bits = key_bits(kmax);
+    h->g_step = capture(h, [&] {
+        launch_force(h->L, mixed, 0, 2, dt);
+        launch_drift_stats_swap(h->L);
+    });
+    h->g_last = capture(h, [&] { launch_force(h->L, mixed, 0, 1, dt); });
+    h->g_upd = capture(h, [&] { update_body(h, bits, 0); });
+    if (!(h->g_step && h->g_last && h->g_upd)) {
+        drop_graphs(h);
+        hipGetLastError();
+        return false;
+    }
+    h->graph_version = h->table_version;
+    h->graph_dt = dt;
+    return true;
+}
+
 // The drift of every step but the first is fused into the previous step's force
 // kernel, which wrote the second position / orientation buffers; the stats kernel
 // swaps them in on the device, and the host mirror follows.
-void swap_drift_buffers(rbc_ctx *h) {
-    launch_drift_stats_swap(h->L);
+void swap_drift_buffers(rbc_ctx *h, bool launch) {
+    if (launch) launch_drift_stats_swap(h->L);
     for (auto &hs : h->sys)
         if (hs.live) {
             std::swap(hs.dev.pos, hs.dev.pos2);
@@ -388,6 +463,7 @@ void swap_drift_buffers(rbc_ctx *h) {
 rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     if (!any_live(h)) return RBC_OK;
     if (nsteps <= 0) return RBC_OK;
+    const bool graphs = h->graphs && !h->timing && ensure_graphs(h, dt);
     ensure_forces(h);
     const double skin = h->prm.skin;
     const int64_t K = h->prm.update_every;
@@ -417,8 +493,13 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             if (need) which.push_back(s);
         }
         run_update(h, which, 0);
-        force_launch(h, 0, last ? 1 : 2, dt);
-        if (!last) swap_drift_buffers(h);
+        if (graphs) {
+            hipGraphLaunch(last ? h->g_last : h->g_step, h->st);
+            if (!last) swap_drift_buffers(h, false);
+        } else {
+            force_launch(h, 0, last ? 1 : 2, dt);
+            if (!last) swap_drift_buffers(h, true);
+        }
         // while the force runs, read this step's kick-drift statistics
         hipEventSynchronize(h->ring_ev[slot]);
         for (int s = 0; s < h->nsys; ++s) {
@@ -580,6 +661,7 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
     h->max_slots = max_slots;
     h->budget = budget;
     h->ensemble = ensemble;
+    h->graphs = ensemble;
     h->sys.resize(max_slots);
     h->user = (hipStream_t)stream;
     hipGetDevice(&h->device);
@@ -637,6 +719,7 @@ rbc_status rbc_ensemble_create(const rbc_params *params, void *hip_stream, int32
 rbc_status rbc_destroy(rbc_handle h) {
     if (!h) return RBC_ERR_INVALID_ARG;
     if (h->st) hipStreamSynchronize(h->st);
+    drop_graphs(h);
     for (int s = 0; s < (int)h->sys.size(); ++s) {
         if (h->sys[s].mem) hipFree(h->sys[s].mem);
         if (h->sys[s].pairs_mem) hipFree(h->sys[s].pairs_mem);
@@ -719,6 +802,14 @@ rbc_status rbc_step(rbc_handle h, int64_t nsteps, double dt) {
 }
 
 rbc_status rbc_ensemble_step(rbc_handle h, int64_t nsteps, double dt) { return rbc_step(h, nsteps, dt); }
+
+rbc_status rbc_set_graphs(rbc_handle h, int32_t enable) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(h->st) != hipSuccess) return fail(h, RBC_ERR_HIP, "stream synchronisation failed");
+    h->graphs = enable != 0;
+    if (!h->graphs) drop_graphs(h);
+    return RBC_OK;
+}
 
 static rbc_status state_slot(rbc_handle h, int32_t slot, double *x, double *nrm, double *v, double *w) {
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");

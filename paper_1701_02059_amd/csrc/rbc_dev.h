@@ -19,6 +19,7 @@ constexpr int CANDMAX = 1024;          // candidate cells (cell-pair entries) pe
 constexpr int SSMAX = 4096;            // particles in a block's candidate cells while staging
 constexpr int USTAGE = 2048;           // candidate particles staged in LDS while building a block's lists
 constexpr float LIST_EXTENT = 4096.0f; // largest FP32 offset (sigma) allowed in that staging
+constexpr int CULLMAX = 256;           // candidate cells whose bounding spheres are staged for culling
 constexpr int SCAN_TILE = 2048;        // elements per block in the segmented scans
 constexpr int BRED = 8;                // doubles of per-block partial results
 
@@ -72,6 +73,7 @@ struct SysDev {
     int32_t *cstart, *ccount, *cstart2, *ccount2, *cmap;
     int32_t *cnbr_start, *cnbr;                     // full cell-pair CSR (k+1, cnbr_cap)
     int32_t *gstart, *gcount, *gseed, *sgcell;      // seed grid (gcap+1, gcap, k, k)
+    D4 *gpos;                                       // centroids in grid order, w = seed index (k)
     int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
     uint16_t *nl16;                                 // the same lists as stage indices (staged blocks)
     F4 *ori32;                                      // FP32 copy of the orientations (mixed-mode staging)
@@ -93,6 +95,7 @@ struct DevParams {
     double rc2[3][3];      // fl(rc*rc): exact neighbour test
     double rl2[3][3];      // (rc + 2 skin)^2 with a small relative margin: list radius
     float rl2f[3][3];      // (rc + 2 skin + 1e-3)^2 rounded up: list radius for FP32 offsets
+    float rlmaxf[3];       // largest list radius (+ 1e-3) of a particle type, rounded up
     double rc_lipid, r_min, eps, mu, st0, wca_eps, wca_sig2, k_bond;
     double inv_mass[3];
     double inv_inertia;
@@ -181,6 +184,10 @@ __device__ __forceinline__ double wrap_coord(double v, int per, double L) {
 template <class T>
 __device__ __forceinline__ T ldg(const T *p) {
     return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void stg(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
 }
 __device__ __forceinline__ D4 ldg(const D4 *p) {
     typedef double v4d __attribute__((ext_vector_type(4)));

@@ -25,7 +25,7 @@ FUNCTIONS = [
     "rbc_get_pairs", "rbc_energy", "rbc_stats", "rbc_get_cells", "rbc_force_timing", "rbc_sync", "rbc_destroy",
     "rbc_status_string", "rbc_last_error", "rbc_ensemble_create", "rbc_ensemble_footprint", "rbc_ensemble_admit",
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
-    "rbc_ensemble_info", "rbc_debug_array",
+    "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs",
 ]
 
 
@@ -83,6 +83,7 @@ def lib():
             "rbc_ensemble_retire": [h, C.c_int32],
             "rbc_ensemble_info": [h, i64p],
             "rbc_debug_array": [h, C.c_int32, C.c_int64, vp, i64p],
+            "rbc_set_graphs": [h, C.c_int32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -234,6 +235,9 @@ class Context:
         out = out[: nb.value // np.dtype(dt).itemsize]
         return out.reshape(-1, 4) if which == 7 else out
 
+    def set_graphs(self, enable: bool = True):
+        _check(self._h, lib().rbc_set_graphs(self._h, int(bool(enable))))
+
     def force_timing(self, enable: bool = True):
         avg = C.c_double(0.0)
         cnt = C.c_int64(0)
@@ -286,6 +290,9 @@ class Ensemble:
 
     def step(self, nsteps: int, dt: float):
         _check(self._h, lib().rbc_ensemble_step(self._h, int(nsteps), float(dt)))
+
+    def set_graphs(self, enable: bool = True):
+        _check(self._h, lib().rbc_set_graphs(self._h, int(bool(enable))))
 
     def get_state(self, slot: int):
         import torch

@@ -242,6 +242,36 @@ def test_ensemble_alone_equals_mix(R, mp):
         assert np.array_equal(a, b)
 
 
+def test_ensemble_graph_replay_matches_eager(R, mp):
+    """Captured step / update graphs, replayed many times with eager work (energy,
+    state copies) between the replays and recaptured after admissions and
+    retirements, give the same trajectories bit for bit as direct launches."""
+    systems = [I.build_request({"kind": "patch", "nL": 2500, "seed": 11}),
+               I.build_request({"kind": "vesicle", "nL": 5000, "seed": 12}),
+               I.build_request({"kind": "vesicle", "nL": 2000, "seed": 13})]
+    runs = []
+    for graphs in (True, False):
+        e = R.Ensemble(mp, R.RBC_MIXED, max_slots=4)
+        e.set_graphs(graphs)
+        a = e.admit(systems[0])
+        b = e.admit(systems[1])
+        out = []
+        for chunk in range(6):
+            e.step(10, 0.01)
+            out.append(e.energy(a))
+            if chunk == 2:
+                c = e.admit(systems[2])
+            if chunk == 4:
+                out += [to_np(t) for t in e.get_state(b)]
+                e.retire(b)
+        out += [to_np(t) for t in e.get_state(a)] + [to_np(t) for t in e.get_state(c)]
+        out.append(e.info()["steps"])
+        e.close()
+        runs.append(out)
+    for x, y in zip(*runs):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
 def test_ensemble_budget_admission(R, mp):
     s = I.build_request({"kind": "vesicle", "nL": 4000, "seed": 5})
     probe = R.Ensemble(mp, R.RBC_MIXED, max_slots=2)
