@@ -688,31 +688,68 @@ __global__ void k_commit(const SysDev *Sd, Maps L_maps, int mode) {
     S.owner[j] = mode ? (int)S.val[j] : (int)S.key[j];
 }
 
-void launch_gather_particles(const LaunchCtx &L) {
+// The gathered state becomes current by swapping the buffer pointers of the
+// rebuilding systems in the descriptor table (each update swaps twice, so the
+// host's copy of the table stays valid); only the id maps and owners are written.
+__global__ void k_swap_state(SysDev *Sd, int nsys) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    SysDev &S = Sd[s];
+    if (S.n <= 0 || !S.sc->rebuild) return;
+    D4 *t;
+    t = S.pos; S.pos = S.pos2; S.pos2 = t;
+    t = S.vel; S.vel = S.vel2; S.vel2 = t;
+    t = S.ori; S.ori = S.ori2; S.ori2 = t;
+    t = S.angv; S.angv = S.angv2; S.angv2 = t;
+    int32_t *g = S.gid; S.gid = S.gid2; S.gid2 = g;
+}
+
+__global__ void k_commit_ids(const SysDev *Sd, Maps L_maps, int mode) {
+    SYS_FROM(p);
+    if (!S.sc->rebuild) return;
+    int j = lb * BLOCK + threadIdx.x;
+    if (j >= S.n) return;
+    S.slot[S.gid[j]] = j;
+    S.owner[j] = mode ? (int)S.val[j] : (int)S.key[j];
+}
+
+static void swap_and_commit(const LaunchCtx &L, int mode) {
+    hipLaunchKernelGGL(k_swap_state, dim3((L.nsys + 63) / 64), dim3(64), 0, L.st, L.Sw, L.nsys);
+    hipLaunchKernelGGL(k_commit_ids, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, mode);
+}
+
+void launch_gather_particles(const LaunchCtx &L, int swap) {
     hipLaunchKernelGGL(k_gather, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_commit, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, 0);
+    if (swap) swap_and_commit(L, 0);
+    else hipLaunchKernelGGL(k_commit, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, 0);
 }
 
 // ------------------------------------------------------------------ cell ranges
 
-__global__ void k_cell_clear(const SysDev *Sd, Maps L_maps) {
-    SYS_FROM(c);
-    if (!S.sc->rebuild) return;
-    int c = lb * BLOCK + threadIdx.x;
-    if (c < S.k) S.ccount[c] = 0;
-}
-
-__global__ void k_cell_count(const SysDev *Sd, Maps L_maps) {
+// Cell ranges from the owners, which the sort left in ascending order: where the
+// owner changes between slots j-1 and j, every cell in between starts at j.
+__global__ void k_cell_starts(const SysDev *Sd, Maps L_maps) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
-    int i = lb * BLOCK + threadIdx.x;
-    if (i < S.n) atomicAdd(&S.ccount[S.owner[i]], 1);
+    const int j = lb * BLOCK + threadIdx.x;
+    if (j >= S.n) return;
+    const int o = S.owner[j];
+    const int prev = j > 0 ? S.owner[j - 1] : -1;
+    for (int c = prev + 1; c <= o; ++c) S.cstart[c] = j;
+    if (j == S.n - 1)
+        for (int c = o + 1; c <= S.k; ++c) S.cstart[c] = S.n;
+}
+
+__global__ void k_cell_counts(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    const int c = lb * BLOCK + threadIdx.x;
+    if (c < S.k) S.ccount[c] = S.cstart[c + 1] - S.cstart[c];
 }
 
 void launch_cell_ranges(const LaunchCtx &L) {
-    hipLaunchKernelGGL(k_cell_clear, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_cell_count, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    launch_scan(L, 2);
+    hipLaunchKernelGGL(k_cell_starts, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_cell_counts, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
 }
 
 // ------------------------------------------------------------------ M-step
@@ -857,7 +894,7 @@ __global__ void k_cell_commit(const SysDev *Sd, Maps L_maps) {
 
 void launch_block_permute(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_block_permute, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_commit, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, 1);
+    swap_and_commit(L, 1);
     hipLaunchKernelGGL(k_cell_commit, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
 }
 

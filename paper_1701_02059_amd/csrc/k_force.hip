@@ -38,6 +38,13 @@ __device__ __forceinline__ T ipow(T c, int e) {
     return r;
 }
 
+// One of three FP64 cutoffs by partner type, as bit selects (no branches).
+__device__ __forceinline__ double sel_cut(int t, double a, double b, double c) {
+    long long r = (t == 1) ? __double_as_longlong(b) : __double_as_longlong(c);
+    r = (t == 0) ? __double_as_longlong(a) : r;
+    return __longlong_as_double(r);
+}
+
 // ------------------------------------------------------------------ pair laws
 
 // Lipid-lipid orientation-dependent law; d = x_i - x_j.  Adds the force and torque
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
             } else {
                 d2 = dist2_open(pi.x, pi.y, pi.z, s_x[e], s_y[e], s_z[e], dx, dy, dz);
             }
-            const double rc2 = tj == 0 ? rcA : (tj == 1 ? rcB : rcC);
+            const double rc2 = sel_cut(tj, rcA, rcB, rcC);
             if (!(d2 < rc2)) continue;
             T ax = 0, ay = 0, az = 0, u;
             if ((ti | tj) == 0)

@@ -328,7 +328,7 @@ void update_body(rbc_ctx *h, int bits, int lloyd) {
             if (it > 0) launch_grid_build(L);
             launch_assign(L, 1);
             launch_sort_particles(L, bits);
-            launch_gather_particles(L);
+            launch_gather_particles(L, it == iters - 1);   // the update swaps buffers exactly twice
             launch_cell_ranges(L);
             launch_mstep(L);
         }

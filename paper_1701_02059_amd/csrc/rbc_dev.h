@@ -236,7 +236,7 @@ void launch_init_seeds(const LaunchCtx &L, const int32_t *const *lipids);
 void launch_grid_build(const LaunchCtx &L);
 void launch_assign(const LaunchCtx &L, int warm);
 void launch_sort_particles(const LaunchCtx &L, int key_bits);
-void launch_gather_particles(const LaunchCtx &L);
+void launch_gather_particles(const LaunchCtx &L, int swap);   // swap: make the gathered buffers current
 void launch_cell_ranges(const LaunchCtx &L);
 void launch_mstep(const LaunchCtx &L);
 void launch_morton_sort_seeds(const LaunchCtx &L);
