@@ -1071,7 +1071,7 @@ __device__ __forceinline__ int union_cell(const int *ofs, int nsc, int u) {
 // numbers them, the block's stage list receives their slots and the 16-bit lists
 // hold stage indices (0xffff pads).  Blocks whose partners do not fit the stage
 // keep 32-bit lists of global slots (stage count -1).
-__global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
     __shared__ int s_cand[CANDMAX];
@@ -1185,7 +1185,9 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         const float oiy = (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]);
         const float oiz = (float)minimg1(pi.z - ref.z, S.per[2], S.box[2]);
         const float rlA = P.rl2f[ti][0], rlB = P.rl2f[ti][1], rlC = P.rl2f[ti][2];
+        const float rf = P.rf2f[ti];
         const float rlmax = P.rlmaxf[ti];
+        int nb = 0;                                      // entries beyond rc + skin, kept at the top
         const int self = s_ofs[lds_lower_bound(s_cand, nsc, A)] + (i - S.cstart[A]);
         const float Lx = S.per[0] ? (float)S.box[0] : 0.0f, Ly = S.per[1] ? (float)S.box[1] : 0.0f,
                     Lz = S.per[2] ? (float)S.box[2] : 0.0f;
@@ -1221,7 +1223,14 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
                     const int tj = __float_as_int(c.w) & 3;
                     const float rl = tj == 0 ? rlA : (tj == 1 ? rlB : rlC);
                     if (d2 < rl && u != self) {
-                        if (cnt < MAXNB) stg(col16 + cnt * CHUNK, (uint16_t)u);
+                        // partners that can come within rc before the next update first,
+                        // the outer shell after them (the force loop's later rows then
+                        // rarely hold a pair in range)
+                        if (cnt < MAXNB) {
+                            const int row = d2 < rf ? cnt - nb : MAXNB - 1 - nb;
+                            stg(col16 + row * CHUNK, (uint16_t)u);
+                        }
+                        if (!(d2 < rf)) ++nb;
                         ++cnt;
                         atomicOr(&s_bits[u >> 5], 1u << (u & 31));     // partner of the block
                     }
@@ -1230,6 +1239,12 @@ __global__ __launch_bounds__(BLOCK) void k_nlist(const SysDev *Sd, Maps L_maps, 
         };
         if (periodic) scan_cells(std::true_type{});
         else scan_cells(std::false_type{});
+        // close the gap: the outer entries follow the inner ones
+        const int nin = min(cnt, MAXNB) - min(nb, MAXNB);
+        const int nout = min(cnt, MAXNB) - nin;
+        if (nin + nout < MAXNB)
+            for (int q = 0; q < nout; ++q)
+                stg(col16 + (nin + q) * CHUNK, ldg(col16 + (MAXNB - nout + q) * CHUNK));
     } else if (valid) {
         D4 pi = S.pos[i];
         int ti = (int)pi.w;

@@ -147,6 +147,8 @@ void make_dev_params(rbc_ctx *h) {
         double m = 0.0;
         for (int b = 0; b < 3; ++b) m = std::max(m, p.rc[a][b] + 2.0 * p.skin + 1e-3);
         d.rlmaxf[a] = std::nextafter((float)m, INFINITY);
+        const double f = m - 1e-3 - p.skin;
+        d.rf2f[a] = (float)(f * f);
     }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {

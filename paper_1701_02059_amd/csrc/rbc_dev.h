@@ -96,6 +96,7 @@ struct DevParams {
     double rl2[3][3];      // (rc + 2 skin)^2 with a small relative margin: list radius
     float rl2f[3][3];      // (rc + 2 skin + 1e-3)^2 rounded up: list radius for FP32 offsets
     float rlmaxf[3];       // largest list radius (+ 1e-3) of a particle type, rounded up
+    float rf2f[3];         // (largest rc of the type + skin)^2: list entries inside come first
     double rc_lipid, r_min, eps, mu, st0, wca_eps, wca_sig2, k_bond;
     double inv_mass[3];
     double inv_inertia;

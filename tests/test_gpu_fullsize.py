@@ -27,6 +27,7 @@ pytestmark = pytest.mark.gpu
 DT = 0.01
 FP64_TOL = 1e-10
 MIXED_TOL = 1e-5
+SKIN = 0.5          # the benchmark's Verlet skin for the whole-cell workload
 
 
 @pytest.fixture(scope="module")
@@ -61,6 +62,7 @@ def _state(ctx, system):
 
 
 def test_rbc4m_pairs_and_sampled_forces_mixed(R, mp, cell):
+    mp = dataclasses.replace(mp, skin=SKIN)
     c = R.Context(mp, R.RBC_MIXED)
     c.set_system(cell)
     c.step(40, DT)
@@ -85,6 +87,7 @@ def test_rbc4m_pairs_and_sampled_forces_mixed(R, mp, cell):
 
 
 def test_rbc4m_sampled_forces_fp64(R, mp, cell):
+    mp = dataclasses.replace(mp, skin=SKIN)
     c = R.Context(mp, R.RBC_FP64)
     c.set_system(cell)
     c.step(12, DT)
