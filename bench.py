@@ -27,16 +27,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 DT = 0.01
-# Algorithmic work per force launch (operation counts of the pair laws as
-# written: add/sub/mul 1 flop each, FMA 2, sqrt/rsqrt/sin/cos/div 1).
+# Algorithmic work of the timed force kernel, which also applies the closing
+# half-kick, the next opening half-kick and the drift.  Flops: operation counts
+# of the pair laws as written, once per unordered pair (add/sub/mul 1, FMA 2,
+# sqrt/rsqrt/sin/cos/div 1).
 FLOPS_LIPID_PAIR = 147      # per unordered lipid pair: F_i, F_j, tau_i, tau_j, U, W and the distance test
 FLOPS_WCA_PAIR = 37         # per unordered pair with a protein bead
 FLOPS_BOND = 28             # per bond
-BYTES_MIXED = 56            # per particle: 32 B position/type + orientation in, 24 B force + torque out
-BYTES_FP64 = 112            # per particle in FP64
+# Bytes: the state read and written once per step.  Lipid: read x (24) + type (1) + FP32 n
+# for the partner stage (12) + v, omega, n (72); write x, v, n, omega (96) + FP32 n (12).
+# Protein bead: read x (24) + type (1) + v (24); write x, v (48).
+BYTES_LIPID_STEP = 217
+BYTES_PROTEIN_STEP = 97
 PEAK_FP32 = 157.3           # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
 PEAK_FP64 = 78.6            # TFLOP/s, MI355X FP64 vector
 PEAK_HBM = 8000.0           # GB/s
+# HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
+# skin 0.5: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
+# plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
+FORCE_TRAFFIC = {"sources_sha256": "13688b1deb76fe8d", "bytes": 2571021312,
+                 "fetch_kib": 979613, "write_kib": 551537}
+KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
+                  "paper_1701_02059_amd/csrc/rbc_dev.h")
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -79,12 +100,11 @@ def timed_run(R, mp, system, precision, steps, warmup, label):
     return ctx, out
 
 
-def cpu_baseline(system, mp):
-    """FP64 oracle on this host: velocity-Verlet steps of the full cell (difference of a
-    3-step and a 1-step run, so the initial force evaluation is not counted)."""
+def _oracle_steps(system, mp, threads):
+    """Seconds per velocity-Verlet step of the FP64 oracle: a 3-step run minus a 1-step
+    run, so the initial force evaluation is not counted."""
     from oracle import oracle as O
     p = O.params_for(system, mp)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     t0 = time.perf_counter()
     O.vv_run(p, system, DT, 1, nthreads=threads)
     t1 = time.perf_counter()
@@ -93,9 +113,23 @@ def cpu_baseline(system, mp):
     per_step = ((t2 - t1) - (t1 - t0)) / 2.0
     if per_step <= 0:
         per_step = (t2 - t1) / 4.0
+    return per_step, t2 - t0
+
+
+def cpu_baseline(system, mp):
+    """The FP64 oracle on this host, on all cores (the full cell) and on one core (the
+    499,952-particle cell), in particle-steps/s."""
+    from paper_1701_02059_amd import inputs as I
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    per_step, spent = _oracle_steps(system, mp, threads)
+    small = I.config("rbc500k")
+    per1, spent1 = _oracle_steps(small, mp, 1)
     return {"value": system.N / per_step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"2 velocity-Verlet steps of the full {system.N:,}-particle cell (3-step minus 1-step run, "
-                      f"{(t2 - t0):.1f} s of CPU work)", "seconds_per_step": per_step}
+                      f"{spent:.1f} s of CPU work)", "seconds_per_step": per_step,
+            "one_core": {"value": small.N / per1, "unit": "particle-steps/s", "cores": 1,
+                         "sample": f"2 steps of the {small.N:,}-particle cell (3-step minus 1-step run, "
+                                   f"{spent1:.1f} s)"}}
 
 
 def serving_run(R, mp, count, rate, steps, saturated=False):
@@ -155,17 +189,28 @@ def main():
     n_bond = int(system.bonds.shape[0])
     ctx.close()
     flops = FLOPS_LIPID_PAIR * n_ll + FLOPS_WCA_PAIR * n_wca + FLOPS_BOND * n_bond
+    n_lip = int(np.sum(system.type == 0))
+    bytes_alg = BYTES_LIPID_STEP * n_lip + BYTES_PROTEIN_STEP * (system.N - n_lip)
     t_force = mixed["force_ms"] * 1e-3
-    achieved = flops / t_force / 1e12
-    bytes_alg = BYTES_MIXED * system.N
-    t_roof = max(flops / (PEAK_FP32 * 1e12), bytes_alg / (PEAK_HBM * 1e9))
-    bound = "alu" if flops / (PEAK_FP32 * 1e12) >= bytes_alg / (PEAK_HBM * 1e9) else "hbm"
-    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32, 4), "traffic": None,
-            "kernel": "k_force<mixed,kick> (pair force + bonds + half-kick)",
+    t_flop = flops / (PEAK_FP32 * 1e12)
+    t_byte = bytes_alg / (PEAK_HBM * 1e9)
+    if t_byte >= t_flop:
+        bound, achieved, peak, unit = "hbm", bytes_alg / t_force / 1e9, PEAK_HBM, "GB/s"
+    else:
+        bound, achieved, peak, unit = "alu", flops / t_force / 1e12, PEAK_FP32, "TFLOP/s"
+    digest = kernel_sources_digest()
+    traffic = FORCE_TRAFFIC["bytes"] if (FORCE_TRAFFIC["sources_sha256"] == digest and
+                                        args.workload == "rbc4m" and args.skin == 0.5) else None
+    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "traffic": traffic,
+            "kernel": "k_force<mixed, fused kick-drift-kick> (pair forces, bonds, integration)",
             "flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_alg,
+            "pair_flops_tflops": round(flops / t_force / 1e12, 3),
+            "pair_flops_frac_of_fp32_peak": round(flops / t_force / 1e12 / PEAK_FP32, 4),
             "avg_launch_us": round(mixed["force_ms"] * 1e3, 2), "launches_timed": mixed["force_launches"],
-            "roofline_time_us": round(t_roof * 1e6, 2), "time_frac": round(t_roof / t_force, 4),
+            "roofline_time_us": round(max(t_flop, t_byte) * 1e6, 2),
+            "time_frac": round(max(t_flop, t_byte) / t_force, 4),
+            "traffic_sources_sha256": digest,
             "lipid_pairs": n_ll, "wca_pairs": n_wca, "bonds": n_bond}
     log(f"[roofline] {roof}")
 
@@ -183,7 +228,9 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = serving_run(R, mp, args.serving_requests, 20.0, args.serving_steps)
+        smp = I.ModelParams()
+        serving = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps)
+        serving["saturated"] = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps, saturated=True)
 
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20

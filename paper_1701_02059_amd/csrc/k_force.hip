@@ -140,9 +140,18 @@ __device__ __forceinline__ T wca_pair(const DevParams &P, T dx, T dy, T dz, T &f
 __device__ __forceinline__ D4 rotor_drift(D4 n, const D4 &w, double dt) {
     const double wn = sqrt(w.x * w.x + w.y * w.y + w.z * w.z);
     if (wn > 0.0) {
-        const double kx = w.x / wn, ky = w.y / wn, kz = w.z / wn;
+        const double iw = 1.0 / wn;
+        const double kx = w.x * iw, ky = w.y * iw, kz = w.z * iw;
+        const double a = wn * dt;
         double sn, cs;
-        sincos(wn * dt, &sn, &cs);
+        if (a < 0.05) {
+            // Taylor series; the first omitted terms are below 1e-18 relative here
+            const double a2 = a * a;
+            sn = a * (1.0 - a2 / 6.0 * (1.0 - a2 / 20.0 * (1.0 - a2 / 42.0 * (1.0 - a2 / 72.0))));
+            cs = 1.0 - a2 / 2.0 * (1.0 - a2 / 12.0 * (1.0 - a2 / 30.0 * (1.0 - a2 / 56.0 * (1.0 - a2 / 90.0))));
+        } else {
+            sincos(a, &sn, &cs);
+        }
         const double kn = kx * n.x + ky * n.y + kz * n.z;
         const double cx = ky * n.z - kz * n.y, cy = kz * n.x - kx * n.z, cz = kx * n.y - ky * n.x;
         const double ox = n.x * cs + cx * sn + kx * kn * (1.0 - cs);
@@ -151,7 +160,10 @@ __device__ __forceinline__ D4 rotor_drift(D4 n, const D4 &w, double dt) {
         n.x = ox; n.y = oy; n.z = oz;
     }
     const double nn = sqrt(n.x * n.x + n.y * n.y + n.z * n.z);
-    if (nn > 0.0) { n.x /= nn; n.y /= nn; n.z /= nn; }
+    if (nn > 0.0) {
+        const double in = 1.0 / nn;
+        n.x *= in; n.y *= in; n.z *= in;
+    }
     return n;
 }
 
