@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=500)
     ap.add_argument("--skin", type=float, default=0.5,
                     help="Verlet skin (sigma); 0.5 is the measured optimum for the membrane workloads")
+    ap.add_argument("--cell-target", type=int, default=16, help="mean lipids per Voronoi cell")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -179,7 +180,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     R.lib()
-    mp = I.ModelParams(skin=args.skin)
+    mp = I.ModelParams(skin=args.skin, cell_target=args.cell_target)
     t0 = time.perf_counter()
     system = I.config(args.workload)
     log(f"[gen] {args.workload}: N={system.N:,} {system.counts()} in {time.perf_counter() - t0:.1f} s")

@@ -251,27 +251,47 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
     auto staged_rows = [&](auto per_tag) {
         constexpr bool PER = decltype(per_tag)::value;
+        // Software pipeline: the list entry of row r+2 is fetched from global memory and
+        // the stage record of row r+1 from LDS while row r is evaluated.
         const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
-        int e_next = (valid && rows > 0) ? (int)ldg(col) : 0xffff;
-        for (int r = 0; r < rows; ++r) {
-            const int e = e_next;                       // next row's entry is in flight meanwhile
-            e_next = (valid && r + 1 < rows) ? (int)ldg(col + (r + 1) * CHUNK) : 0xffff;
-            if (e >= scnt) continue;
-            int tj;
-            T njx, njy, njz;
+        int e_cur = (valid && rows > 0) ? (int)ldg(col) : 0xffff;
+        int e_nxt = (valid && rows > 1) ? (int)ldg(col + CHUNK) : 0xffff;
+        struct Rec {
+            double x, y, z;
+            T nx, ny, nz;
+            int t;
+        };
+        auto fetch = [&](int e) {
+            const int q = e < scnt ? e : 0;             // in-bounds dummy for padding entries
+            Rec c;
+            c.x = s_x[q];
+            c.y = s_y[q];
+            c.z = s_z[q];
             if constexpr (MIXED) {
-                const F4 nj = s_n4[e];
-                tj = (int)nj.w;
-                njx = nj.x; njy = nj.y; njz = nj.z;
+                const F4 nj = s_n4[q];
+                c.nx = nj.x; c.ny = nj.y; c.nz = nj.z;
+                c.t = (int)nj.w;
             } else {
-                tj = s_t[e];
-                njx = s_nx[e]; njy = s_ny[e]; njz = s_nz[e];
+                c.nx = s_nx[q]; c.ny = s_ny[q]; c.nz = s_nz[q];
+                c.t = s_t[q];
             }
+            return c;
+        };
+        Rec rec = fetch(e_cur);
+        for (int r = 0; r < rows; ++r) {
+            const int e = e_cur;
+            const Rec c = rec;
+            e_cur = e_nxt;
+            e_nxt = (valid && r + 2 < rows) ? (int)ldg(col + (r + 2) * CHUNK) : 0xffff;
+            rec = fetch(e_cur);
+            if (e >= scnt) continue;
+            const int tj = c.t;
+            const T njx = c.nx, njy = c.ny, njz = c.nz;
             double dx, dy, dz, d2;
             if constexpr (PER) {
-                d2 = dist2_exact(S, pi.x, pi.y, pi.z, s_x[e], s_y[e], s_z[e], dx, dy, dz);
+                d2 = dist2_exact(S, pi.x, pi.y, pi.z, c.x, c.y, c.z, dx, dy, dz);
             } else {
-                d2 = dist2_open(pi.x, pi.y, pi.z, s_x[e], s_y[e], s_z[e], dx, dy, dz);
+                d2 = dist2_open(pi.x, pi.y, pi.z, c.x, c.y, c.z, dx, dy, dz);
             }
             const double rc2 = sel_cut(tj, rcA, rcB, rcC);
             if (!(d2 < rc2)) continue;
