@@ -1045,6 +1045,13 @@ __device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v) {
     return lo;
 }
 
+// One of three FP32 radii by partner type, as integer selects (no branches).
+__device__ __forceinline__ float sel3f(int t, float a, float b, float c) {
+    int r = (t == 1) ? __float_as_int(b) : __float_as_int(c);
+    r = (t == 0) ? __float_as_int(a) : r;
+    return __int_as_float(r);
+}
+
 // Last candidate cell whose particle offset is <= u (offsets of empty cells repeat).
 __device__ __forceinline__ int union_cell(const int *ofs, int nsc, int u) {
     int lo = 0, hi = nsc;
@@ -1211,8 +1218,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     if (dx * dx + dy * dy + dz * dz > rr * rr) continue;
                 }
                 const int ue = s_ofs[pos + 1];
-                for (int u = s_ofs[pos]; u < ue; ++u) {
-                    const F4 c = s_u[u];
+                int u = s_ofs[pos];
+                F4 c_next = s_u[min(u, USTAGE - 1)];
+                for (; u < ue; ++u) {
+                    const F4 c = c_next;
+                    c_next = s_u[min(u + 1, ue - 1)];          // next candidate in flight meanwhile
                     float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
                     if constexpr (PER) {
                         dx -= Lx * rintf(dx * iLx);
@@ -1221,7 +1231,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     }
                     const float d2 = dx * dx + dy * dy + dz * dz;
                     const int tj = __float_as_int(c.w) & 3;
-                    const float rl = tj == 0 ? rlA : (tj == 1 ? rlB : rlC);
+                    const float rl = sel3f(tj, rlA, rlB, rlC);
                     if (d2 < rl && u != self) {
                         // partners that can come within rc before the next update first,
                         // the outer shell after them (the force loop's later rows then
