@@ -140,11 +140,13 @@ rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds);
  * when timing is enabled), and the number of launches timed. */
 rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_t *launches);
 
-/* Replay the step's fixed launch sequences (the force kernel with its fused drift,
- * and the cell update) as HIP graphs captured once per system table and time step
- * (enable = 1), or launch every kernel directly (0).  Results are identical either
- * way.  Default: on for ensembles, off for single-system contexts.  Graphs are not
- * used while force timing is enabled.  Synchronises the library stream. */
+/* Replay the step's fixed launch sequence (the force kernel with its fused drift
+ * and the drift statistics) as a HIP graph captured once per system table and time
+ * step (enable = 1), or launch every kernel directly (0).  Cell updates always
+ * launch directly, with grids covering only the systems that rebuild.  Results are
+ * identical either way.  Default: on for ensembles, off for single-system contexts.
+ * Graphs are not used while force timing is enabled.  Synchronises the library
+ * stream. */
 rbc_status rbc_set_graphs(rbc_handle h, int32_t enable);
 
 /* Internal cell-list arrays of the single system, for inspection and tests (sync).

@@ -1417,6 +1417,36 @@ void launch_finish_update(const LaunchCtx &L) {
 
 // ------------------------------------------------------------------ entry points used by the runtime
 
+// Block maps restricted to the systems that rebuild (the others get no blocks), so
+// an update launches only the rebuilding systems' blocks.  The block counts per
+// system match the full maps built on the host; one block of MAX_SLOTS threads.
+__global__ __launch_bounds__(MAX_SLOTS) void k_restrict_maps(const SysDev *Sd, int nsys, int32_t *out) {
+    __shared__ int s_w[16];
+    const int s = threadIdx.x;
+    int cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (s < nsys) {
+        const SysDev &S = Sd[s];
+        if (S.n > 0 && S.sc->rebuild) {
+            cnt[0] = (S.n + BLOCK - 1) / BLOCK;
+            cnt[1] = (S.k + BLOCK - 1) / BLOCK;
+            cnt[2] = (S.gcap + BLOCK - 1) / BLOCK;
+            cnt[3] = S.ntile_p;
+            cnt[4] = S.ntile_s;
+            cnt[5] = (S.k + SCAN_TILE - 1) / SCAN_TILE;
+            cnt[6] = (S.gcap + SCAN_TILE - 1) / SCAN_TILE;
+        }
+    }
+    for (int m = 0; m < 7; ++m) {
+        int tot;
+        const int ex = block_excl_scan(cnt[m], s_w, tot);
+        if (s <= nsys) out[m * (nsys + 1) + s] = ex;     // entry nsys receives the total
+    }
+}
+
+void launch_restrict_maps(const LaunchCtx &L, int32_t *out) {
+    hipLaunchKernelGGL(k_restrict_maps, dim3(1), dim3(MAX_SLOTS), 0, L.st, L.S, L.nsys, out);
+}
+
 void launch_set_rebuild(const LaunchCtx &L, const unsigned long long m[4]) {
     hipLaunchKernelGGL(k_set_rebuild, dim3((L.nsys + 63) / 64), dim3(64), 0, L.st, L.S, L.nsys, m[0], m[1], m[2],
                        m[3]);

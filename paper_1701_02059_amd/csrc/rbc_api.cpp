@@ -7,9 +7,10 @@
 // step of lookahead: after each kick-drift the per-system displacement statistics
 // are copied to pinned memory, and while the force kernel of step s runs the
 // host decides which systems need a cell update before the force of step s+1.
-// With graphs enabled (the default for ensembles) the fixed launch sequences of
-// a step -- the force kernel with its fused drift, and the whole cell update --
-// are captured once per system table and time step and replayed as HIP graphs.
+// With graphs enabled (the default for ensembles) the fixed launch sequence of a
+// step -- the force kernel with its fused drift and the drift statistics -- is
+// captured once per system table and time step and replayed as a HIP graph; cell
+// updates launch only the blocks of the systems that rebuild.
 #include "../../include/rbc.h"
 #include "rbc_dev.h"
 
@@ -70,6 +71,7 @@ struct rbc_ctx {
     SysDev *d_sys = nullptr;
     SysScal *d_sc = nullptr;
     int32_t *d_maps = nullptr;
+    int32_t *d_umaps = nullptr;       // block maps of the systems in the running cell update
     const int32_t **d_lip = nullptr;
     SysScal *h_ring = nullptr;
     hipEvent_t ring_ev[RING] = {};
@@ -85,7 +87,7 @@ struct rbc_ctx {
     int64_t table_version = 0;
     int64_t graph_version = -1;
     double graph_dt = 0.0;
-    hipGraphExec_t g_step = nullptr, g_last = nullptr, g_upd = nullptr;
+    hipGraphExec_t g_step = nullptr, g_last = nullptr;
     // force-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tb, te;
@@ -296,7 +298,7 @@ bool any_live(const rbc_ctx *h) {
     return false;
 }
 
-void update_body(rbc_ctx *h, int bits, int lloyd);
+void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd);
 
 // Run the cell update for the systems in `mask`.  lloyd > 0: seed from lipids and
 // run that many k-means iterations first.
@@ -310,11 +312,30 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
     }
     const LaunchCtx &L = h->L;
     launch_set_rebuild(L, m);
-    if (lloyd == 0 && h->graphs && h->g_upd && h->graph_version == h->table_version) {
-        hipGraphLaunch(h->g_upd, h->st);
-    } else {
-        update_body(h, key_bits(kmax), lloyd);
+    // launch only the rebuilding systems' blocks: the device builds their prefix maps
+    // from the rebuild flags, the host sums the same block counts for the grid sizes
+    launch_restrict_maps(L, h->d_umaps);
+    LaunchCtx U = L;
+    const int ns = h->nsys;
+    U.maps.p = h->d_umaps;
+    U.maps.c = h->d_umaps + (ns + 1);
+    U.maps.g = h->d_umaps + 2 * (ns + 1);
+    U.maps.tp = h->d_umaps + 3 * (ns + 1);
+    U.maps.ts = h->d_umaps + 4 * (ns + 1);
+    U.maps.sc = h->d_umaps + 5 * (ns + 1);
+    U.maps.sg = h->d_umaps + 6 * (ns + 1);
+    U.nblk_p = U.nblk_c = U.nblk_g = U.nblk_tp = U.nblk_ts = U.nblk_sc = U.nblk_sg = 0;
+    for (int s : which) {
+        const HostSys &hs = h->sys[s];
+        U.nblk_p += (int32_t)((hs.n + BLOCK - 1) / BLOCK);
+        U.nblk_c += (hs.k + BLOCK - 1) / BLOCK;
+        U.nblk_g += (hs.gcap + BLOCK - 1) / BLOCK;
+        U.nblk_tp += hs.ntile_p;
+        U.nblk_ts += hs.ntile_s;
+        U.nblk_sc += (hs.k + SCAN_TILE - 1) / SCAN_TILE;
+        U.nblk_sg += (hs.gcap + SCAN_TILE - 1) / SCAN_TILE;
     }
+    update_body(h, U, key_bits(kmax), lloyd);
     for (int s : which) {
         HostSys &hs = h->sys[s];
         hs.updates++;
@@ -322,9 +343,9 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
     }
 }
 
-// The cell-update launches for the systems whose rebuild flag is set.
-void update_body(rbc_ctx *h, int bits, int lloyd) {
-    const LaunchCtx &L = h->L;
+// The cell-update launches for the systems whose rebuild flag is set (L carries
+// block maps restricted to them).
+void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd) {
     auto estep_msteps = [&](int iters) {
         for (int it = 0; it < iters; ++it) {
             if (it > 0) launch_grid_build(L);
@@ -401,7 +422,7 @@ rbc_status ensure_forces(rbc_ctx *h) {
 }
 
 void drop_graphs(rbc_ctx *h) {
-    for (hipGraphExec_t *g : {&h->g_step, &h->g_last, &h->g_upd})
+    for (hipGraphExec_t *g : {&h->g_step, &h->g_last})
         if (*g) {
             hipGraphExecDestroy(*g);
             *g = nullptr;
@@ -421,24 +442,18 @@ hipGraphExec_t capture(rbc_ctx *h, F body) {
     return ex;
 }
 
-// Capture the step and update sequences for the current table and dt.  The sort
-// in the captured update takes as many radix passes as the largest live system
-// needs.  Returns false (eager launches are used) if capture fails.
+// Capture the step sequences for the current table and dt.  Returns false (eager
+// launches are used) if capture fails.
 bool ensure_graphs(rbc_ctx *h, double dt) {
-    if (h->graph_version == h->table_version && h->graph_dt == dt && h->g_step && h->g_last && h->g_upd) return true;
+    if (h->graph_version == h->table_version && h->graph_dt == dt && h->g_step && h->g_last) return true;
     drop_graphs(h);
     const int mixed = h->prm.precision == RBC_MIXED;
-    int32_t kmax = 1;
-    for (const auto &hs : h->sys)
-        if (hs.live) kmax = std::max(kmax, hs.k);
-    const int bits = key_bits(kmax);
     h->g_step = capture(h, [&] {
         launch_force(h->L, mixed, 0, 2, dt);
         launch_drift_stats_swap(h->L);
     });
     h->g_last = capture(h, [&] { launch_force(h->L, mixed, 0, 1, dt); });
-    h->g_upd = capture(h, [&] { update_body(h, bits, 0); });
-    if (!(h->g_step && h->g_last && h->g_upd)) {
+    if (!(h->g_step && h->g_last)) {
         drop_graphs(h);
         hipGetLastError();
         return false;
@@ -673,6 +688,7 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipMalloc(&h->d_sys, sizeof(SysDev) * max_slots) == hipSuccess &&
               hipMalloc(&h->d_sc, sizeof(SysScal) * max_slots) == hipSuccess &&
               hipMalloc(&h->d_maps, sizeof(int32_t) * 7 * (max_slots + 1)) == hipSuccess &&
+              hipMalloc(&h->d_umaps, sizeof(int32_t) * 7 * (MAX_SLOTS + 1)) == hipSuccess &&
               hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
               hipHostMalloc((void **)&h->h_ring, sizeof(SysScal) * MAX_SLOTS * RING, hipHostMallocDefault) == hipSuccess;
     for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->ring_ev[q], hipEventDisableTiming) == hipSuccess;
@@ -732,6 +748,7 @@ rbc_status rbc_destroy(rbc_handle h) {
     if (h->d_sys) hipFree(h->d_sys);
     if (h->d_sc) hipFree(h->d_sc);
     if (h->d_maps) hipFree(h->d_maps);
+    if (h->d_umaps) hipFree(h->d_umaps);
     if (h->d_lip) hipFree(h->d_lip);
     if (h->h_ring) hipHostFree(h->h_ring);
     if (h->ev_in) hipEventDestroy(h->ev_in);

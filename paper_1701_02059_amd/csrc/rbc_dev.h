@@ -233,6 +233,7 @@ void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, in
 void launch_export_pairs(const LaunchCtx &L, int sys, int count);
 // cell update kernels (each predicated on SysScal::rebuild)
 void launch_set_rebuild(const LaunchCtx &L, const unsigned long long m[4]);
+void launch_restrict_maps(const LaunchCtx &L, int32_t *out);   // 7 x (nsys+1) prefix maps of the rebuilding systems
 void launch_init_seeds(const LaunchCtx &L, const int32_t *const *lipids);
 void launch_grid_build(const LaunchCtx &L);
 void launch_assign(const LaunchCtx &L, int warm);
