@@ -1218,11 +1218,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     if (dx * dx + dy * dy + dz * dz > rr * rr) continue;
                 }
                 const int ue = s_ofs[pos + 1];
-                int u = s_ofs[pos];
-                F4 c_next = s_u[min(u, USTAGE - 1)];
-                for (; u < ue; ++u) {
-                    const F4 c = c_next;
-                    c_next = s_u[min(u + 1, ue - 1)];          // next candidate in flight meanwhile
+                auto test = [&](const F4 &c, int u) {
                     float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
                     if constexpr (PER) {
                         dx -= Lx * rintf(dx * iLx);
@@ -1244,7 +1240,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                         ++cnt;
                         atomicOr(&s_bits[u >> 5], 1u << (u & 31));     // partner of the block
                     }
+                };
+                int u = s_ofs[pos];
+                for (; u + 1 < ue; u += 2) {                      // two candidates per trip
+                    const F4 c0 = s_u[u], c1 = s_u[u + 1];
+                    test(c0, u);
+                    test(c1, u + 1);
                 }
+                if (u < ue) test(s_u[u], u);
             }
         };
         if (periodic) scan_cells(std::true_type{});

@@ -84,7 +84,19 @@ __device__ __forceinline__ T lipid_pair(const DevParams &P, T dx, T dy, T dz, T 
             sx = __builtin_amdgcn_sinf((T)0.25 * u);
             cx = __builtin_amdgcn_cosf((T)0.25 * u);
         } else {
-            sincos((T)0.5 * (T)M_PI * u, &sx, &cx);
+            // x = (pi/2) u lies in [0, pi/2): Taylor series of the half angle (terms
+            // through h^16; the first omitted one is below 1e-16 relative), then the
+            // double-angle formulas
+            const double h = 0.25 * M_PI * u, h2 = h * h;
+            // nested factors 1 - h^2/(k(k+1)), multiplied by compile-time reciprocals
+            const double sh = h * (1.0 - h2 * (1.0 / 6.0) * (1.0 - h2 * (1.0 / 20.0) * (1.0 - h2 * (1.0 / 42.0) *
+                              (1.0 - h2 * (1.0 / 72.0) * (1.0 - h2 * (1.0 / 110.0) * (1.0 - h2 * (1.0 / 156.0) *
+                              (1.0 - h2 * (1.0 / 210.0))))))));
+            const double ch = 1.0 - h2 * 0.5 * (1.0 - h2 * (1.0 / 12.0) * (1.0 - h2 * (1.0 / 30.0) *
+                              (1.0 - h2 * (1.0 / 56.0) * (1.0 - h2 * (1.0 / 90.0) * (1.0 - h2 * (1.0 / 132.0) *
+                              (1.0 - h2 * (1.0 / 182.0) * (1.0 - h2 * (1.0 / 240.0))))))));
+            sx = 2.0 * sh * ch;
+            cx = (ch - sh) * (ch + sh);
         }
         const T c2 = cx * cx;
         T cz1;                                            // cos^(2 zeta - 2)
@@ -147,8 +159,10 @@ __device__ __forceinline__ D4 rotor_drift(D4 n, const D4 &w, double dt) {
         if (a < 0.05) {
             // Taylor series; the first omitted terms are below 1e-18 relative here
             const double a2 = a * a;
-            sn = a * (1.0 - a2 / 6.0 * (1.0 - a2 / 20.0 * (1.0 - a2 / 42.0 * (1.0 - a2 / 72.0))));
-            cs = 1.0 - a2 / 2.0 * (1.0 - a2 / 12.0 * (1.0 - a2 / 30.0 * (1.0 - a2 / 56.0 * (1.0 - a2 / 90.0))));
+            sn = a * (1.0 - a2 * (1.0 / 6.0) * (1.0 - a2 * (1.0 / 20.0) * (1.0 - a2 * (1.0 / 42.0) *
+                 (1.0 - a2 * (1.0 / 72.0)))));
+            cs = 1.0 - a2 * 0.5 * (1.0 - a2 * (1.0 / 12.0) * (1.0 - a2 * (1.0 / 30.0) * (1.0 - a2 * (1.0 / 56.0) *
+                 (1.0 - a2 * (1.0 / 90.0)))));
         } else {
             sincos(a, &sn, &cs);
         }
