@@ -553,6 +553,8 @@ size_t footprint(const rbc_ctx *h, int64_t n, int64_t nlip, int64_t nbond) {
     return layout(tmp, nullptr);
 }
 
+void release(rbc_ctx *h, int32_t slot);
+
 rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const double *nrm, const int32_t *type,
                  const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
                  const double *box, const int32_t *periodic) {
@@ -567,7 +569,9 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
             return fail(h, RBC_ERR_INVALID_ARG, "periodic box length must exceed twice the largest cutoff plus skin");
     }
     HostSys &hs = h->sys[slot];
-    // type histogram and bond topology are needed on the host
+    // type histogram and bond topology are needed on the host: wait for the caller's
+    // stream, which may still be producing the input arrays
+    HIPCHK(hipStreamSynchronize(h->user));
     std::vector<int32_t> ht(n);
     std::vector<int32_t> hb(2 * nbond);
     std::vector<double> hr(nbond);
@@ -648,7 +652,15 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
         hs.updates = 1;
         h->forces_valid = false;
     }
-    return sync_and_check(h);
+    rbc_status st = sync_and_check(h);
+    if (st != RBC_OK) {
+        // the initial cell build failed (capacity, non-finite input): the slot is not admitted
+        const std::string why = h->err;
+        release(h, slot);
+        h->err = why;
+        if (h->d_sc) hipMemset(h->d_sc + slot, 0, sizeof(SysScal));
+    }
+    return st;
 }
 
 void release(rbc_ctx *h, int32_t slot) {

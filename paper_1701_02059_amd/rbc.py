@@ -256,6 +256,7 @@ class Ensemble:
         self.params = make_params(mp, precision)
         _check(None, lib().rbc_ensemble_create(C.byref(self.params), _stream_ptr(), int(max_slots), int(hbm_budget),
                                                C.byref(self._h)))
+        self.max_slots = int(max_slots)
         self.sizes = {}
 
     def close(self):
@@ -277,13 +278,18 @@ class Ensemble:
         return out.value
 
     def admit(self, system) -> Optional[int]:
-        """Slot index, or None when no slot or budget is free."""
+        """Slot index, or None when no slot or budget is free.  A system that cannot be
+        admitted at all (for example, its lists overflow the per-particle capacity)
+        raises RbcError."""
         u = _Uploaded(system)
         slot = C.c_int32(-1)
         st = lib().rbc_ensemble_admit(self._h, u.n, _dev(u.x), _dev(u.nrm), _dev(u.type), _dev(u.v), _dev(u.w),
                                       u.nbond, _dev(u.bonds), _dev(u.r0), u.box, u.per, C.byref(slot))
         if st == RBC_ERR_CAPACITY:
-            return None
+            info = self.info()
+            if info["live"] >= self.max_slots or (
+                    info["budget"] > 0 and info["bytes"] + self.footprint(system) > info["budget"]):
+                return None
         _check(self._h, st)
         self.sizes[slot.value] = u.n
         return slot.value

@@ -272,6 +272,31 @@ def test_ensemble_graph_replay_matches_eager(R, mp):
         assert np.array_equal(np.asarray(x), np.asarray(y))
 
 
+def test_ensemble_failed_admission_leaves_others(R, mp):
+    """A system whose lists overflow the per-particle capacity is refused without
+    disturbing the resident ones: the slot is released and the other trajectory is
+    bitwise the one it has alone."""
+    import dataclasses
+    mp5 = dataclasses.replace(mp, skin=0.5)        # the dense cloud then has up to 80 list partners
+    good = I.build_request({"kind": "patch", "nL": 2500, "seed": 21})
+    alone = R.Ensemble(mp5, R.RBC_MIXED, max_slots=4)
+    sa = alone.admit(good)
+    alone.step(30, 0.01)
+    ref = [to_np(t) for t in alone.get_state(sa)]
+    alone.close()
+    e = R.Ensemble(mp5, R.RBC_MIXED, max_slots=4)
+    a = e.admit(good)
+    e.step(10, 0.01)
+    with pytest.raises(R.RbcError) as ei:
+        e.admit(_dense_cloud())
+    assert ei.value.status == R.RBC_ERR_CAPACITY
+    assert e.info()["live"] == 1
+    e.step(20, 0.01)
+    for x, y in zip(ref, (to_np(t) for t in e.get_state(a))):
+        assert np.array_equal(x, y)
+    e.close()
+
+
 def test_ensemble_budget_admission(R, mp):
     s = I.build_request({"kind": "vesicle", "nL": 4000, "seed": 5})
     probe = R.Ensemble(mp, R.RBC_MIXED, max_slots=2)
