@@ -1181,6 +1181,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
     }
     // ---- pass 1
     int cnt = 0;
+    int my_in = 0;                                       // entries in the inner part of the list
     int32_t *col = S.nl + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
     uint16_t *col16 = S.nl16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
     if (valid && staged) {
@@ -1258,6 +1259,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
         if (nin + nout < MAXNB)
             for (int q = 0; q < nout; ++q)
                 stg(col16 + (nin + q) * CHUNK, ldg(col16 + (MAXNB - nout + q) * CHUNK));
+        my_in = nin;
     } else if (valid) {
         D4 pi = S.pos[i];
         int ti = (int)pi.w;
@@ -1283,7 +1285,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
         rows = MAXNB;
     }
     const int mycnt = min(cnt, MAXNB);
-    if (chunk_ok && lane == 0) S.nlk[chunk] = rows;
+    if (!staged) my_in = mycnt;                          // unordered lists: every row is inner
+    const int rows_in = min(wave_max_int(my_in), rows);
+    if (chunk_ok && lane == 0) {
+        S.nlk[chunk] = rows;
+        S.nlin[chunk] = rows_in;
+    }
     if (lane == 0) atomicMax(&s_rows, rows);
     // ---- pass 2: mark partners in the union, number them, write the stage list
     const int nwords = staged ? (USTAGE / 32) : (SSMAX / 32);

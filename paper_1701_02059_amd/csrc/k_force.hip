@@ -258,7 +258,12 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     const T nix = (T)ni.x, niy = (T)ni.y, niz = (T)ni.z;
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
     double U = 0.0, W = 0.0;
-    const int rows = min(S.nlk[chunk], MAXNB);
+    // Outer rows (partners built beyond rc + skin, after the inner ones) cannot come
+    // within rc while every particle has moved less than (skin - 1.1e-3) / 2 since the
+    // build; the 1.1e-3 covers the FP32 rounding of the build-time distances.
+    const int rows_all = min(S.nlk[chunk], MAXNB);
+    const bool inner_only = 2.0 * sqrt(bitsd(S.sc->maxdisp2)) < P.skip_guard;
+    const int rows = inner_only ? min(S.nlin[chunk], rows_all) : rows_all;
     // cutoff row of this particle's type, selected by the partner's type without
     // dynamic indexing; the periodic min-image only where the system has periodic axes
     const double rcA = P.rc2[ti][0], rcB = P.rc2[ti][1], rcC = P.rc2[ti][2];

@@ -171,6 +171,7 @@ void make_dev_params(rbc_ctx *h) {
     for (int a = 0; a < 3; ++a) d.inv_mass[a] = 1.0 / p.mass[a];
     d.inv_inertia = 1.0 / p.inertia;
     d.cell_search = search;
+    d.skip_guard = p.skin - 1.1e-3;
     d.zeta = (int32_t)p.zeta;
     d.inv_w = 1.0 / (p.rc[0][0] - p.r_min);
     d.dudr_k = p.eps * p.zeta * M_PI / (p.rc[0][0] - p.r_min);
@@ -199,6 +200,7 @@ size_t layout(HostSys &s, char *base) {
     d.gpos = c.take<D4>(k);
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
     d.nl16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK);
+    d.nlin = c.take<int32_t>(s.nchunk);
     d.ori32 = c.take<F4>(n);
     d.ori32b = c.take<F4>(n);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);

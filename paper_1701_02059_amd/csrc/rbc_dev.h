@@ -75,6 +75,7 @@ struct SysDev {
     int32_t *gstart, *gcount, *gseed, *sgcell;      // seed grid (gcap+1, gcap, k, k)
     D4 *gpos;                                       // centroids in grid order, w = seed index (k)
     int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
+    int32_t *nlin;                                  // per chunk: rows holding partners built within rc + skin
     uint16_t *nl16;                                 // the same lists as stage indices (staged blocks)
     F4 *ori32;                                      // FP32 copy of the orientations (mixed-mode staging)
     F4 *ori32b;                                     // its second buffer (fused drift target; pos2 / ori2 likewise)
@@ -97,6 +98,8 @@ struct DevParams {
     float rl2f[3][3];      // (rc + 2 skin + 1e-3)^2 rounded up: list radius for FP32 offsets
     float rlmaxf[3];       // largest list radius (+ 1e-3) of a particle type, rounded up
     float rf2f[3];         // (largest rc of the type + skin)^2: list entries inside come first
+    double skip_guard;     // skin - 1.1e-3: while 2 x (largest displacement) stays below it, the
+                           // outer list rows (built beyond rc + skin) cannot hold a pair in range
     double rc_lipid, r_min, eps, mu, st0, wca_eps, wca_sig2, k_bond;
     double inv_mass[3];
     double inv_inertia;
