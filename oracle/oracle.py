@@ -270,3 +270,78 @@ def voronoi_update(p, x, typ, seeds, owner_prev_order=None):
     owner = new_index[owner].astype(np.int32)
     order = np.argsort(owner, kind="stable")
     return seeds, owner, order
+
+
+# ------------------------------------------- two cell sets (detached cytoskeleton)
+# Force Evaluation section: for a cytoskeleton that has left the bilayer, the
+# protein beads get a Voronoi cell set of their own, built like the lipids' one.
+# Cells [0, kl) are the lipids' and [kl, k) the proteins'; every step above runs
+# within each set, and the Morton renumbering keeps the lipid cells first.
+
+def set_sizes(typ, m):
+    """(kl, kp): ceil(N_L / m) lipid cells and ceil(N_P / m) protein cells."""
+    nL = int(np.count_nonzero(np.asarray(typ) == 0))
+    nP = int(np.asarray(typ).size) - nL
+    return -(-nL // m), -(-nP // m)
+
+
+def assign_sets(p, x, typ, seeds, kl):
+    """E-step per set: a lipid's nearest lipid cell, a protein bead's nearest protein cell."""
+    lip = np.asarray(typ) == 0
+    owner = np.empty(x.shape[0], dtype=np.int32)
+    owner[lip] = assign(p, x[lip], seeds[:kl])
+    owner[~lip] = assign(p, x[~lip], seeds[kl:]) + kl
+    return owner
+
+
+def seed_update_sets(p, x, typ, owner, seeds, kl):
+    """M-step per set: lipid cells move to the mean of their lipid members,
+    protein cells to the mean of their protein members."""
+    lip = np.asarray(typ) == 0
+    out = np.array(seeds, dtype=np.float64, copy=True)
+    out[:kl] = seed_update(p, x[lip], np.asarray(typ)[lip], owner[lip], seeds[:kl])
+    # within the protein set every member counts: present them as the averaged kind
+    nP = int(np.count_nonzero(~lip))
+    out[kl:] = seed_update(p, x[~lip], np.zeros(nP, dtype=np.int32), owner[~lip] - kl, seeds[kl:])
+    return out
+
+
+def morton_sets(p, seeds, kl):
+    """Morton keys over all centroids, with bit 63 set on the protein set's cells."""
+    keys = morton(p, seeds)
+    keys[kl:] |= np.uint64(1) << np.uint64(63)
+    return keys
+
+
+def voronoi_init_sets(p, system, m, lloyd_iters):
+    """Initial seeds of both sets (lipid number floor(j*N_L/kl), protein number
+    floor(j*N_P/kp)), then Lloyd iterations within each set.  Returns (seeds, owner, kl)."""
+    typ = np.asarray(system.type)
+    lip = np.flatnonzero(typ == 0)
+    prot = np.flatnonzero(typ != 0)
+    kl, kp = set_sizes(typ, m)
+    seeds = np.concatenate([system.x[lip[(np.arange(kl) * lip.size) // kl]],
+                            system.x[prot[(np.arange(kp) * prot.size) // max(kp, 1)]][:kp]])
+    for a in range(3):
+        if system.periodic[a]:
+            seeds[:, a] = seeds[:, a] - system.box[a] * np.floor(seeds[:, a] / system.box[a])
+    owner = None
+    for _ in range(lloyd_iters):
+        owner = assign_sets(p, system.x, typ, seeds, kl)
+        seeds = seed_update_sets(p, system.x, typ, owner, seeds, kl)
+    return seeds, owner, kl
+
+
+def voronoi_update_sets(p, x, typ, seeds, kl):
+    """One online-EM update with two cell sets (as voronoi_update); returns
+    (new_seeds, new_owner, order)."""
+    owner = assign_sets(p, x, typ, seeds, kl)
+    seeds = seed_update_sets(p, x, typ, owner, seeds, kl)
+    keys = morton_sets(p, seeds, kl)
+    perm = np.lexsort((np.arange(keys.size), keys))
+    new_index = np.empty_like(perm)
+    new_index[perm] = np.arange(perm.size)
+    seeds = seeds[perm]
+    owner = new_index[owner].astype(np.int32)
+    order = np.argsort(owner, kind="stable")
+    return seeds, owner, order

@@ -31,6 +31,8 @@ LIPID, SPECTRIN, JUNCTION = 0, 1, 2
 GOLDEN_ANGLE = math.pi * (3.0 - math.sqrt(5.0))
 LIPID_AREA = 1.0911          # sigma^2 per lipid (hexagonal sheet at r_min)
 ANCHOR_DEPTH = 1.2           # sigma, depth of the cytoskeleton under the sheet
+DETACHED_DEPTH = 3.0         # sigma, depth of a detached cytoskeleton (beyond every lipid-protein cutoff)
+DETACHED_TETHER = 2          # a detached cytoskeleton keeps the anchor bond of every 2nd junction
 BEADS_PER_EDGE = 8
 
 
@@ -58,6 +60,7 @@ class ModelParams:
     update_every: int = 100
     skin: float = 0.3
     lloyd_iters: int = 10
+    protein_cells: int = 0        # 1: protein beads get their own Voronoi cells (detached cytoskeleton)
 
     def rc_table(self) -> np.ndarray:
         """Per type-pair cutoff: r_c for lipid-lipid, the WCA range otherwise."""
@@ -164,7 +167,8 @@ def _anchor_bonds(jpos: np.ndarray, lip: np.ndarray, nL: int, box=None, periodic
     return np.stack([nL + np.arange(jpos.shape[0]), idx], axis=1)
 
 
-def _assemble(name, lip, nrm, jpos, beads, chain_bonds, anchors, rng_state, kT, params, box, periodic):
+def _assemble(name, lip, nrm, jpos, beads, chain_bonds, anchors, rng_state, kT, params, box, periodic,
+              depth=ANCHOR_DEPTH):
     rng = rng_state
     nL, nJ, nS = lip.shape[0], jpos.shape[0], beads.shape[0]
     N = nL + nJ + nS
@@ -175,7 +179,7 @@ def _assemble(name, lip, nrm, jpos, beads, chain_bonds, anchors, rng_state, kT, 
     mass = np.asarray(params.mass, dtype=np.float64)[typ]
     v, w = _velocities(rng, N, nL, nrm, kT, mass, params.inertia)
     bonds = np.concatenate([chain_bonds, anchors], axis=0).astype(np.int32)
-    r0 = np.concatenate([np.ones(chain_bonds.shape[0]), np.full(anchors.shape[0], ANCHOR_DEPTH)])
+    r0 = np.concatenate([np.ones(chain_bonds.shape[0]), np.full(anchors.shape[0], depth)])
     return System(name, x, n, typ, v, w, bonds, r0, np.asarray(box, dtype=np.float64),
                   np.asarray(periodic, dtype=np.int32), kT)
 
@@ -184,8 +188,12 @@ def _assemble(name, lip, nrm, jpos, beads, chain_bonds, anchors, rng_state, kT, 
 
 def flat_patch(nx: int = 48, ny: int = 48, nj: int = 4, seed: int = 0, kT: float = 0.22,
                params: Optional[ModelParams] = None, spacing: float = 1.12,
-               jitter: float = 0.02, tilt: float = 0.05) -> System:
-    """Periodic flat bilayer patch on a triangular lattice (x, y periodic; z open)."""
+               jitter: float = 0.02, tilt: float = 0.05, depth: float = ANCHOR_DEPTH,
+               tether: int = 1) -> System:
+    """Periodic flat bilayer patch on a triangular lattice (x, y periodic; z open).
+
+    The cytoskeleton lies `depth` under the sheet; every `tether`-th junction keeps
+    its anchor bond to the nearest lipid (1: all, an attached cytoskeleton)."""
     params = params or ModelParams()
     assert ny % 2 == 0 and nj % 2 == 0
     rng = np.random.default_rng(seed)
@@ -208,7 +216,7 @@ def flat_patch(nx: int = 48, ny: int = 48, nj: int = 4, seed: int = 0, kT: float
     p, q = np.meshgrid(np.arange(nj), np.arange(nj), indexing="xy")
     p = p.ravel()
     q = q.ravel()
-    jpos = np.stack([(p + 0.5 * (q % 2)) * ax, q * ay, np.full(p.shape, -ANCHOR_DEPTH)], axis=1).astype(np.float64)
+    jpos = np.stack([(p + 0.5 * (q % 2)) * ax, q * ay, np.full(p.shape, -depth)], axis=1).astype(np.float64)
     idx = lambda pp, qq: (qq % nj) * nj + (pp % nj)
     edges = []
     for a in range(nj * nj):
@@ -230,15 +238,18 @@ def flat_patch(nx: int = 48, ny: int = 48, nj: int = 4, seed: int = 0, kT: float
         return pts
 
     beads, chain_bonds = _chains(jpos, edges, nL, jpos.shape[0], beads_fn)
-    anchors = _anchor_bonds(jpos, lip, nL, box, periodic)
-    return _assemble(f"patch{nx}x{ny}", lip, nrm, jpos, beads, chain_bonds, anchors, rng, kT, params, box, periodic)
+    anchors = _anchor_bonds(jpos, lip, nL, box, periodic)[::tether]
+    return _assemble(f"patch{nx}x{ny}", lip, nrm, jpos, beads, chain_bonds, anchors, rng, kT, params, box, periodic,
+                     depth)
 
 
 # --------------------------------------------------------------------------- vesicle
 
 def vesicle(nL: int = 100_000, nJ: int = 1000, seed: int = 0, kT: float = 0.22,
-            params: Optional[ModelParams] = None, jitter: float = 0.02) -> System:
-    """Spherical vesicle: Fibonacci-sphere lipids, radial orientations, inner spectrin network."""
+            params: Optional[ModelParams] = None, jitter: float = 0.02, depth: float = ANCHOR_DEPTH,
+            tether: int = 1) -> System:
+    """Spherical vesicle: Fibonacci-sphere lipids, radial orientations, inner spectrin network
+    `depth` under the sheet, anchored at every `tether`-th junction."""
     params = params or ModelParams()
     rng = np.random.default_rng(seed)
     R = math.sqrt(nL * 1.09 / (4.0 * math.pi))
@@ -246,7 +257,7 @@ def vesicle(nL: int = 100_000, nJ: int = 1000, seed: int = 0, kT: float = 0.22,
     lip = R * u + rng.normal(0.0, jitter, size=(nL, 3))
     nrm = u.copy()
     uj = _fibonacci_sphere(nJ)
-    Rj = R - ANCHOR_DEPTH
+    Rj = R - depth
     jpos = Rj * uj
     edges = _hull_edges(uj)
 
@@ -259,9 +270,9 @@ def vesicle(nL: int = 100_000, nJ: int = 1000, seed: int = 0, kT: float = 0.22,
         return Rj * (wa[:, :, None] * ua[:, None, :] + wb[:, :, None] * ub[:, None, :])
 
     beads, chain_bonds = _chains(jpos, edges, nL, nJ, beads_fn)
-    anchors = _anchor_bonds(jpos, lip, nL)
+    anchors = _anchor_bonds(jpos, lip, nL)[::tether]
     return _assemble(f"vesicle{nL}", lip, nrm, jpos, beads, chain_bonds, anchors, rng, kT, params,
-                     np.zeros(3), np.zeros(3, dtype=np.int32))
+                     np.zeros(3), np.zeros(3, dtype=np.int32), depth)
 
 
 # --------------------------------------------------------------------------- biconcave cell
@@ -320,7 +331,8 @@ def _ef_points(count: int, t_tab, A_tab, scale):
 
 
 def biconcave_cell(nL: int = 3_600_000, nJ: int = 16_000, seed: int = 0, kT: float = 0.22,
-                   params: Optional[ModelParams] = None, jitter: float = 0.02) -> System:
+                   params: Optional[ModelParams] = None, jitter: float = 0.02, depth: float = ANCHOR_DEPTH,
+                   tether: int = 1) -> System:
     """Whole red cell: lipids by equal-area Fibonacci sampling of the Evans-Fung surface.
 
     The surface is scaled (sigma per micrometre) so that each lipid covers LIPID_AREA.
@@ -329,7 +341,7 @@ def biconcave_cell(nL: int = 3_600_000, nJ: int = 16_000, seed: int = 0, kT: flo
     of the straight chord between their junctions and are then moved along the
     local surface normal (that of the nearest lipid site) to the same depth under
     the sheet as the junctions: on the strongly curved rim a bare chord would cut
-    into the lipid layer.
+    into the lipid layer.  Every `tether`-th junction keeps its anchor bond.
     """
     params = params or ModelParams()
     rng = np.random.default_rng(seed)
@@ -338,17 +350,17 @@ def biconcave_cell(nL: int = 3_600_000, nJ: int = 16_000, seed: int = 0, kT: flo
     site, nrm, _ = _ef_points(nL, t_tab, A_tab, scale)
     lip = site + rng.normal(0.0, jitter, size=(nL, 3))
     jp, jn, jsph = _ef_points(nJ, t_tab, A_tab, scale)
-    jpos = jp - ANCHOR_DEPTH * jn
+    jpos = jp - depth * jn
     edges = _hull_edges(jsph)
 
     def beads_fn(a, b, k):
         return a[:, None, :] + k[None, :, None] * (b - a)[:, None, :]
 
     beads, chain_bonds = _chains(jpos, edges, nL, nJ, beads_fn)
-    beads = _to_depth(beads, site, nrm, ANCHOR_DEPTH)
-    anchors = _anchor_bonds(jpos, lip, nL)
+    beads = _to_depth(beads, site, nrm, depth)
+    anchors = _anchor_bonds(jpos, lip, nL)[::tether]
     s = _assemble(f"rbc{nL + nJ + beads.shape[0]}", lip, nrm, jpos, beads, chain_bonds, anchors, rng, kT,
-                  params, np.zeros(3), np.zeros(3, dtype=np.int32))
+                  params, np.zeros(3), np.zeros(3, dtype=np.int32), depth)
     s.scale = scale
     return s
 
@@ -376,7 +388,23 @@ def vesicle_for_lipids(nL: int, seed: int, kT: float = 0.22, params=None) -> Sys
 
 def config(name: str, seed: int = 0, params: Optional[ModelParams] = None) -> System:
     """The synthetic workloads: 'patch' (2,704 particles), 'vesicle' (124,952),
-    'rbc4m' (3,999,952), 'rbc500k' (499,952), and 'tiny' for fast checks."""
+    'rbc4m' (3,999,952), 'rbc500k' (499,952), and 'tiny' for fast checks.  A
+    '_detached' suffix gives the same sizes with the cytoskeleton DETACHED_DEPTH
+    under the sheet and tethered at every DETACHED_TETHER-th junction only."""
+    if name.endswith("_detached"):
+        base = name[: -len("_detached")]
+        kw = dict(seed=seed, params=params, depth=DETACHED_DEPTH, tether=DETACHED_TETHER)
+        if base == "patch":
+            return flat_patch(48, 48, 4, **kw)
+        if base == "vesicle":
+            return vesicle(100_000, 1000, **kw)
+        if base == "rbc4m":
+            return biconcave_cell(3_600_000, 16_000, **kw)
+        if base == "rbc500k":
+            return biconcave_cell(450_000, 2_000, **kw)
+        if base == "tiny":
+            return vesicle(2_000, 20, **kw)
+        raise ValueError(name)
     if name == "patch":
         return flat_patch(48, 48, 4, seed=seed, params=params)
     if name == "vesicle":

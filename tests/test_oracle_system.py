@@ -226,6 +226,99 @@ def test_cell_pairs_cover_every_neighbour_pair(ves, mp):
     assert all((int(u), int(v)) in cset for u, v in zip(lo, hi))
 
 
+# ------------------------------------------- two cell sets (detached cytoskeleton)
+
+def _two_set_cloud(seed=21, nl=400, npr=90):
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([rng.normal(size=(nl, 3)) * 6, rng.normal(size=(npr, 3)) * 6 + [0, 0, 2.0]])
+    typ = np.concatenate([np.zeros(nl), rng.integers(1, 3, npr)]).astype(np.int32)
+    return x, typ
+
+
+def test_assign_sets_brute_force(mp):
+    """Each particle's cell is the nearest centroid of its own set, ties to the
+    lowest index: brute force over the full distance matrix."""
+    p = O.make_params(mp)
+    x, typ = _two_set_cloud()
+    rng = np.random.default_rng(5)
+    kl = 30
+    seeds = np.concatenate([rng.normal(size=(kl, 3)) * 6, rng.normal(size=(8, 3)) * 6])
+    seeds[kl + 3] = seeds[4]                      # a protein centroid on top of a lipid one
+    own = O.assign_sets(p, x, typ, seeds, kl)
+    d2 = ((x[:, None, :] - seeds[None, :, :]) ** 2).sum(axis=2)
+    lipid = typ == 0
+    d2[np.ix_(lipid, np.arange(kl, seeds.shape[0]))] = np.inf
+    d2[np.ix_(~lipid, np.arange(kl))] = np.inf
+    assert np.array_equal(own, np.argmin(d2, axis=1))
+    assert np.all(own[lipid] < kl) and np.all(own[~lipid] >= kl)
+
+
+def test_seed_update_sets_are_set_means(mp):
+    p = O.make_params(mp)
+    x, typ = _two_set_cloud(seed=3)
+    kl = 25
+    seeds = np.concatenate([x[typ == 0][::16][:kl], x[typ != 0][::10]])
+    seeds = seeds + 0.01
+    own = O.assign_sets(p, x, typ, seeds, kl)
+    new = O.seed_update_sets(p, x, typ, own, seeds, kl)
+    for c in range(seeds.shape[0]):
+        m = own == c
+        if c < kl:
+            m &= typ == 0
+        if m.any():
+            assert np.allclose(new[c], x[m].mean(axis=0), atol=1e-12), c
+        else:
+            assert np.array_equal(new[c], seeds[c])
+    # a protein cell holding only protein members moves (the attached M-step would not move it)
+    moved = [c for c in range(kl, seeds.shape[0]) if (own == c).any()]
+    assert moved and all(not np.array_equal(new[c], seeds[c]) for c in moved)
+
+
+def test_morton_sets_put_lipid_cells_first(mp):
+    p = O.make_params(mp)
+    seeds = np.array([[0.0, 0, 0], [1.0, 1, 1], [0.0, 0, 0], [1.0, 0, 0]])
+    k = O.morton_sets(p, seeds, 2)
+    assert k[0] == 0 and k[1] == (1 << 63) - 1
+    assert k[2] == 1 << 63
+    assert k[3] == (1 << 63) | sum(1 << (3 * b + 2) for b in range(21))
+    x, typ = _two_set_cloud(seed=4)
+    kl, kp = O.set_sizes(typ, 16)
+    assert (kl, kp) == (25, 6)
+    sys_ = I.System("cloud", x, np.zeros_like(x), typ, np.zeros_like(x), np.zeros_like(x),
+                    np.zeros((0, 2), np.int32), np.zeros(0), np.zeros(3), np.zeros(3, np.int32), 0.22)
+    seeds, owner, kl0 = O.voronoi_init_sets(p, sys_, 16, 3)
+    assert kl0 == kl and seeds.shape[0] == kl + kp
+    s2, o2, order = O.voronoi_update_sets(p, x, typ, seeds, kl)
+    assert np.all(o2[typ == 0] < kl) and np.all(o2[typ != 0] >= kl)
+    assert np.array_equal(np.sort(o2), o2[order])
+    keys = O.morton_sets(p, s2, kl)
+    assert np.all(np.diff(keys.astype(np.float64)) >= 0)
+
+
+def test_two_set_cell_pairs_cover_every_neighbour_pair(mp):
+    """Cell pairs found from the two sets' bounding radii still contain every
+    neighbour pair, lipid-protein pairs across the sets included."""
+    import dataclasses
+    det = I.config("tiny_detached")
+    # forty protein beads pulled up to 0.9 sigma under a lipid: lipid-protein pairs
+    prot = np.flatnonzero(det.type != 0)[::5][:40]
+    x = det.x.copy()
+    lip = np.arange(40) * 50                      # lipid ids come first
+    x[prot] = det.x[lip] - 0.9 * det.n[lip]
+    det = dataclasses.replace(det, x=x)
+    p = O.params_for(det, mp)
+    seeds, owner, kl = O.voronoi_init_sets(p, det, 16, 3)
+    R = O.cell_bounds(p, det.x, owner, seeds)
+    cp = O.cell_pairs(p, seeds, R, 2.6, 0.0)
+    cset = set(map(tuple, cp))
+    pairs = O.pairs(p, det.x, det.type)
+    a, b = owner[pairs[:, 0]], owner[pairs[:, 1]]
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    assert all((int(u), int(v)) in cset for u, v in zip(lo, hi))
+    cross = (lo < kl) & (hi >= kl)
+    assert cross.sum() >= 40
+
+
 # ------------------------------------------------------------------ integrator
 
 def _energy_error(sys_, mp, dt, T):
