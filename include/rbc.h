@@ -10,7 +10,10 @@
  *    update (nearest-centroid assignment, centroid move), centroids ordered
  *    along a Morton curve and particles reordered by owning cell (the
  *    two-level reordering), plus the cell-pair and per-particle neighbour
- *    lists derived from them.
+ *    lists derived from them.  Protein beads join the lipids' cells, or, for
+ *    a detached cytoskeleton (params.protein_cells), a second set of cells
+ *    built the same way over the protein beads alone (Force Evaluation
+ *    section); cell pairs then also span the two sets.
  *  - rbc_forces: pairwise forces and torques between lipids, lipids and
  *    proteins and between proteins found through those cells, plus the bond
  *    list of physically linked proteins (Force Evaluation section).
@@ -78,6 +81,11 @@ typedef struct {
     double skin;                                /* displacement bound between updates (sigma) */
     int32_t lloyd_iters;                        /* k-means iterations when cells are first built */
     int32_t precision;                          /* rbc_precision: FP32 pair arithmetic or FP64 */
+    int32_t protein_cells;                      /* 0: protein beads join the lipids' Voronoi cells (a
+                                                   cytoskeleton attached to the bilayer); 1: they get a
+                                                   separate set of cells, ceil(N_P / cell_target) of
+                                                   them (a detached cytoskeleton) -- Force Evaluation
+                                                   section */
 } rbc_params;
 
 /* ---- single-system context (an ensemble with one slot) ---- */
@@ -98,7 +106,8 @@ rbc_status rbc_set_system(rbc_handle h, int64_t n, const double *x, const double
                           int64_t nbond, const int32_t *bonds, const double *r0,
                           const double *box, const int32_t *periodic);
 
-/* Rebuild the cells now.  lloyd_iters > 0: re-seed from the lipids and run that
+/* Rebuild the cells now.  lloyd_iters > 0: re-seed from the lipids (and the
+ * protein beads, for a separate protein cell set) and run that
  * many k-means iterations first; 0: one online-EM update (assign, move
  * centroids, Morton reorder, particle reorder, cell and neighbour lists). */
 rbc_status rbc_update_cells(rbc_handle h, int32_t lloyd_iters);
@@ -125,9 +134,10 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
  * (translational + lipid rotational), total E = KE + U, |sum F|, |sum (r x F + tau)|. */
 rbc_status rbc_energy(rbc_handle h, double *out);
 
-/* Counters (sync).  [host] out[8]: steps done, cell updates, early (skin)
+/* Counters (sync).  [host] out[9]: steps done, cell updates, early (skin)
  * updates, cells k, max neighbour-list rows, max cell-pair row, particles n,
- * lipids. */
+ * lipids, lipid cells (cells [0, out[8]) hold lipids; with protein_cells set,
+ * cells [out[8], k) hold the protein beads; otherwise out[8] == k). */
 rbc_status rbc_stats(rbc_handle h, int64_t *out);
 
 /* Cell structure for inspection (sync).  [host] owner: n ints, the cell of

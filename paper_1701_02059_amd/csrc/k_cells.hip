@@ -138,14 +138,18 @@ __global__ void k_pack_multi(const SysDev *Sd, int s, const double *x, const dou
 
 // ------------------------------------------------------------------ seeds from lipids
 
-// Seed j starts at the position of lipid number floor(j * N_L / k) (lipids in id
-// order; `lip` lists their ids).  No warm start for the first assignment.
+// Seed j < kl starts at the position of lipid number floor(j * N_L / kl) (lipids in
+// id order; `lip` lists their ids).  With a separate protein set, seed kl + j
+// starts at protein number floor(j * N_P / (k - kl)), whose ids follow the lipids'
+// in `lip`.  No warm start for the first assignment.
 __global__ void k_init_seeds(const SysDev *Sd, Maps L_maps, const int32_t *const *lipids) {
     SYS_FROM(c);
     if (!S.sc->rebuild) return;
     int c = lb * BLOCK + threadIdx.x;
     if (c < S.k) {
-        long long j = (long long)c * S.nlip / S.k;
+        long long j;
+        if (c < S.kl) j = (long long)c * S.nlip / S.kl;
+        else j = S.nlip + (long long)(c - S.kl) * S.nsrcp / (S.k - S.kl);
         int g = lipids[s][j];
         D4 p = S.pos[S.slot[g]];
         p.x = wrap_coord(p.x, S.per[0], S.box[0]);
@@ -456,12 +460,14 @@ __device__ __forceinline__ void axis_window(int c, int dim, int per, int r, int 
     }
 }
 
+// Nearest centroid among seeds [slo, shi) (ties: lower index).
 __device__ int nearest_seed(const SysDev &S, const SysScal *sc, double xi, double yi, double zi, int warm,
-                            double &bestd2) {
+                            int slo, int shi, double &bestd2) {
     int best = -1;
     bestd2 = INFINITY;
     double dx, dy, dz;
-    if (warm >= 0 && warm < S.k) {
+    const unsigned span = (unsigned)(shi - slo);
+    if (warm >= 0 && (unsigned)(warm - slo) < span) {
         D4 c = S.seed[warm];
         bestd2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
         best = warm;
@@ -499,6 +505,7 @@ __device__ int nearest_seed(const SysDev &S, const SysScal *sc, double xi, doubl
                     for (int q = ldg(S.gstart + g); q < qe; ++q) {
                         const D4 c = ldg(S.gpos + q);
                         const int sd = (int)c.w;
+                        if ((unsigned)(sd - slo) >= span) continue;   // the other particle set's cells
                         double d2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
                         if (d2 < bestd2 || (d2 == bestd2 && sd < best)) { bestd2 = d2; best = sd; }
                     }
@@ -533,7 +540,10 @@ __global__ void k_assign(const SysDev *Sd, Maps L_maps, int warm) {
     if (i >= S.n) return;
     D4 p = S.pos[i];
     double d2;
-    int best = nearest_seed(S, S.sc, p.x, p.y, p.z, warm ? S.owner[i] : -1, d2);
+    // lipids search cells [0, kl), protein beads [kl, k) (all cells when kl == k)
+    const bool lipid_set = (p.w == 0.0) || S.kl == S.k;
+    const int slo = lipid_set ? 0 : S.kl, shi = lipid_set ? S.kl : S.k;
+    int best = nearest_seed(S, S.sc, p.x, p.y, p.z, warm ? S.owner[i] : -1, slo, shi, d2);
     if (best < 0) { atomicOr(&S.sc->err, ERR_ASSIGN); best = 0; }
     S.key[i] = (uint64_t)best;
     S.val[i] = (uint32_t)i;
@@ -756,6 +766,7 @@ void launch_cell_ranges(const LaunchCtx &L) {
 
 // Each centroid with lipid members moves by the mean min-image offset of those
 // members (summed in slot order); centroids without lipids stay; periodic axes wrap.
+// Cells of a separate protein set (index >= kl) average their protein members.
 __global__ void k_mstep(const SysDev *Sd, Maps L_maps) {
 #pragma clang fp contract(off)
     SYS_FROM(c);
@@ -765,10 +776,11 @@ __global__ void k_mstep(const SysDev *Sd, Maps L_maps) {
     D4 sd = S.seed[c];
     double sx = 0, sy = 0, sz = 0;
     int cnt = 0;
+    const bool lipid_cell = c < S.kl;
     int b = S.cstart[c], e = b + S.ccount[c];
     for (int i = b; i < e; ++i) {
         D4 p = S.pos[i];
-        if (p.w != 0.0) continue;
+        if ((p.w == 0.0) != lipid_cell) continue;
         double dx, dy, dz;
         (void)dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz);
         sx += dx; sy += dy; sz += dz;
@@ -818,7 +830,8 @@ __global__ void k_seed_bbox(const SysDev *Sd, int nsys) {
     }
 }
 
-// 21-bit quantisation per axis, bits interleaved x (most significant), y, z.
+// 21-bit quantisation per axis, bits interleaved x (most significant), y, z; bit 63
+// marks a protein-set cell, so lipid cells keep the indices below kl.
 __global__ void k_morton(const SysDev *Sd, Maps L_maps) {
 #pragma clang fp contract(off)
     SYS_FROM(c);
@@ -840,6 +853,7 @@ __global__ void k_morton(const SysDev *Sd, Maps L_maps) {
     uint64_t key = 0;
     for (int b = 20; b >= 0; --b)
         key = (key << 3) | (((q[0] >> b) & 1ull) << 2) | (((q[1] >> b) & 1ull) << 1) | ((q[2] >> b) & 1ull);
+    if (c >= S.kl) key |= 1ull << 63;
     S.key[c] = key;
     S.val[c] = (uint32_t)c;
 }
@@ -859,7 +873,7 @@ __global__ void k_seed_permute(const SysDev *Sd, Maps L_maps) {
 void launch_morton_sort_seeds(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_seed_bbox, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys);
     hipLaunchKernelGGL(k_morton, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    sort_segments(L, 1, 63);
+    sort_segments(L, 1, 64);
     hipLaunchKernelGGL(k_seed_permute, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     launch_scan(L, 1);
 }

@@ -30,6 +30,8 @@ constexpr int RING = 8;
 struct HostSys {
     bool live = false;
     int64_t n = 0, nlip = 0, nbond = 0;
+    int64_t nsrcp = 0;               // protein beads seeding a separate cell set (0: none)
+    int32_t kl = 0;                  // lipid cells; cells [kl, k) belong to the protein set
     int32_t k = 0, nchunk = 0, gcap = 0, cnbr_cap = 0, ntile_p = 0, ntile_s = 0;
     double box[3] = {0, 0, 0};
     int32_t per[3] = {0, 0, 0};
@@ -38,7 +40,7 @@ struct HostSys {
     void *pairs_mem = nullptr;
     int64_t pairs_cap = 0;
     SysDev dev{};
-    int32_t *lip = nullptr;          // device: lipid ids in id order (the seed list)
+    int32_t *lip = nullptr;          // device: lipid ids in id order, then protein ids (the seed lists)
     int64_t steps_since = 0, steps_total = 0, updates = 0, early = 0;
     bool have_stats = false, rebuilt_last = false;
     double disp2 = 0.0, v2 = 0.0;
@@ -137,6 +139,7 @@ bool valid_params(const rbc_params *p, std::string &why) {
     if (!(p->skin >= 0.0)) { why = "skin must be >= 0"; return false; }
     if (p->lloyd_iters < 1) { why = "lloyd_iters must be >= 1"; return false; }
     if (p->precision != RBC_FP64 && p->precision != RBC_MIXED) { why = "unknown precision"; return false; }
+    if (p->protein_cells != 0 && p->protein_cells != 1) { why = "protein_cells must be 0 or 1"; return false; }
     if (!(p->wca_sigma > 0.0) || !(p->k_bond >= 0.0)) { why = "bad WCA / bond constants"; return false; }
     return true;
 }
@@ -211,7 +214,7 @@ size_t layout(HostSys &s, char *base) {
     d.blkrows = c.take<int32_t>(nblkp);
     d.bred = c.take<double>((size_t)nblkp * BRED);
     d.tsum = c.take<int32_t>((size_t)std::max((k + SCAN_TILE - 1) / SCAN_TILE, (s.gcap + SCAN_TILE - 1) / SCAN_TILE) + 2);
-    s.lip = c.take<int32_t>(s.nlip);
+    s.lip = c.take<int32_t>(s.nlip + s.nsrcp);
     return c.off + 256;
 }
 
@@ -220,7 +223,11 @@ void size_system(const rbc_ctx *h, HostSys &s, int64_t n, int64_t nlip, int64_t 
     s.nlip = nlip > 0 ? nlip : n;
     s.nbond = nbond;
     const int64_t m = h->prm.cell_target;
-    s.k = (int32_t)std::max<int64_t>(1, (s.nlip + m - 1) / m);
+    const int64_t kl = std::max<int64_t>(1, (s.nlip + m - 1) / m);
+    // a separate protein cell set needs lipids and proteins both
+    s.nsrcp = (h->prm.protein_cells && nlip > 0 && n > nlip) ? n - nlip : 0;
+    s.kl = (int32_t)kl;
+    s.k = (int32_t)(kl + (s.nsrcp + m - 1) / m);
     s.nchunk = (int32_t)((n + CHUNK - 1) / CHUNK);
     s.gcap = 8 * s.k + 64;
     s.cnbr_cap = 96 * s.k + 1024;
@@ -587,13 +594,17 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
         if (ht[i] < 0 || ht[i] > 2) return fail(h, RBC_ERR_INVALID_ARG, "particle type must be 0, 1 or 2");
         if (ht[i] == 0) lip.push_back((int32_t)i);
     }
+    const int64_t nlip_real = (int64_t)lip.size();
     if (lip.empty())
         for (int64_t i = 0; i < n; ++i) lip.push_back((int32_t)i);   // no lipids: seed from every particle
     for (int64_t e = 0; e < nbond; ++e)
         if (hb[2 * e] < 0 || hb[2 * e] >= n || hb[2 * e + 1] < 0 || hb[2 * e + 1] >= n || hb[2 * e] == hb[2 * e + 1])
             return fail(h, RBC_ERR_INVALID_ARG, "bond index out of range");
     HostSys fresh;
-    size_system(h, fresh, n, (int64_t)lip.size(), nbond);
+    size_system(h, fresh, n, nlip_real, nbond);
+    if (fresh.nsrcp > 0)                    // the protein set's seeds come from protein beads
+        for (int64_t i = 0; i < n; ++i)
+            if (ht[i] != 0) lip.push_back((int32_t)i);
     const size_t bytes = layout(fresh, nullptr);
     if (h->budget > 0 && h->used + (int64_t)bytes > h->budget)
         return fail(h, RBC_ERR_CAPACITY, "footprint exceeds the remaining device-memory budget");
@@ -615,6 +626,8 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
     d.n = (int32_t)n;
     d.nlip = (int32_t)fresh.nlip;
     d.k = fresh.k;
+    d.kl = fresh.kl;
+    d.nsrcp = (int32_t)fresh.nsrcp;
     d.nchunk = fresh.nchunk;
     d.gcap = fresh.gcap;
     d.cnbr_cap = fresh.cnbr_cap;
@@ -947,6 +960,7 @@ rbc_status rbc_stats(rbc_handle h, int64_t *out) {
     out[5] = h->h_ring[0].cnbr_maxrow;
     out[6] = hs.n;
     out[7] = hs.nlip;
+    out[8] = hs.kl;
     return RBC_OK;
 }
 

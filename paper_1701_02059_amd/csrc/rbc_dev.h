@@ -61,7 +61,9 @@ struct alignas(256) SysScal {
 struct SysDev {
     int32_t n, nlip, k, nchunk, gcap, cnbr_cap, ntile_p, ntile_s;
     int32_t per[3];
-    int32_t pad;
+    int32_t kl;                                     // lipid cells: seeds [0, kl); protein cells: [kl, k)
+    int32_t nsrcp;                                  // protein seed sources after the lipid ids in `lip`
+    int32_t pad2;
     double box[3];
     D4 *pos, *vel, *ori, *angv, *frc, *trq, *xb;   // pos.w = particle type
     D4 *pos2, *vel2, *ori2, *angv2;

@@ -34,7 +34,8 @@ class RbcParams(C.Structure):
                 ("sin_theta0", C.c_double), ("r_min", C.c_double), ("wca_eps", C.c_double),
                 ("wca_sigma", C.c_double), ("k_bond", C.c_double), ("mass", C.c_double * 3),
                 ("inertia", C.c_double), ("cell_target", C.c_int32), ("update_every", C.c_int32),
-                ("skin", C.c_double), ("lloyd_iters", C.c_int32), ("precision", C.c_int32)]
+                ("skin", C.c_double), ("lloyd_iters", C.c_int32), ("precision", C.c_int32),
+                ("protein_cells", C.c_int32)]
 
 
 class RbcError(RuntimeError):
@@ -110,6 +111,7 @@ def make_params(mp, precision: int = RBC_FP64) -> RbcParams:
     p.inertia = mp.inertia
     p.cell_target, p.update_every, p.skin = int(mp.cell_target), int(mp.update_every), float(mp.skin)
     p.lloyd_iters, p.precision = int(mp.lloyd_iters), int(precision)
+    p.protein_cells = int(getattr(mp, "protein_cells", 0))
     return p
 
 
@@ -212,9 +214,10 @@ class Context:
         return out
 
     def stats(self) -> dict:
-        out = np.zeros(8, dtype=np.int64)
+        out = np.zeros(9, dtype=np.int64)
         _check(self._h, lib().rbc_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))))
-        keys = ["steps", "updates", "early_updates", "cells", "max_list_rows", "max_cell_pairs", "n", "lipids"]
+        keys = ["steps", "updates", "early_updates", "cells", "max_list_rows", "max_cell_pairs", "n", "lipids",
+                "lipid_cells"]
         return dict(zip(keys, (int(v) for v in out)))
 
     def cells(self):
