@@ -55,6 +55,19 @@ def params_for(system, mp) -> OrcParams:
     return make_params(mp, system.box, system.periodic)
 
 
+class OrcExt(C.Structure):
+    _fields_ = [("vol_k", C.c_double), ("vol_target", C.c_double), ("lipid_area", C.c_double),
+                ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64)]
+
+
+def make_ext(mp, vol_target=0.0) -> OrcExt:
+    """Volume-constraint and thermostat constants of a ModelParams; V0 given explicitly."""
+    e = OrcExt()
+    e.vol_k, e.vol_target, e.lipid_area = float(mp.vol_k), float(vol_target), float(mp.lipid_area)
+    e.kT, e.gamma, e.gamma_rot, e.seed = float(mp.kT), float(mp.gamma), float(mp.gamma_rot), int(mp.seed)
+    return e
+
+
 _lib = None
 
 
@@ -67,6 +80,7 @@ def lib():
         P = C.POINTER
         dp, ip, i64p, u64p = P(C.c_double), P(C.c_int32), P(C.c_int64), P(C.c_uint64)
         pp = P(OrcParams)
+        ep = P(OrcExt)
         sig = {
             "orc_dist2": (C.c_double, [pp, dp, dp, dp]),
             "orc_pair_lipid": (C.c_double, [pp, dp, dp, dp, dp, dp, dp]),
@@ -84,6 +98,13 @@ def lib():
             "orc_cell_pairs": (C.c_int64, [pp, C.c_int64, dp, dp, C.c_double, C.c_double, C.c_int64, ip]),
             "orc_vv_run": (C.c_int, [pp, C.c_int64, dp, dp, dp, dp, ip, C.c_int64, ip, dp, C.c_double,
                                      C.c_int64, dp, C.c_int]),
+            "orc_philox4x32_10": (None, [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]),
+            "orc_volume": (C.c_double, [ep, C.c_int64, dp, dp, ip]),
+            "orc_volume_forces": (C.c_double, [ep, C.c_int64, dp, dp, ip, dp, dp]),
+            "orc_forces_ext": (C.c_int, [pp, ep, C.c_int64, dp, dp, ip, C.c_int64, ip, dp, dp, dp, dp, C.c_int]),
+            "orc_langevin_step": (None, [pp, ep, C.c_int64, ip, dp, C.c_double, C.c_uint64, dp, dp]),
+            "orc_vv_run_ext": (C.c_int, [pp, ep, C.c_uint64, C.c_int64, dp, dp, dp, dp, ip, C.c_int64, ip, dp,
+                                         C.c_double, C.c_int64, dp, C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -345,3 +366,74 @@ def voronoi_update_sets(p, x, typ, seeds, kl):
     owner = new_index[owner].astype(np.int32)
     order = np.argsort(owner, kind="stable")
     return seeds, owner, order
+
+
+# ------------------------------------------- volume constraint and thermostat
+
+def philox(ctr, key):
+    """Philox4x32-10 of a 4-word counter and 2-word key."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xffffffff for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    out = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, out)
+    return [int(v) for v in out]
+
+
+def volume(e, x, nrm, typ):
+    x, xp = _d(x)
+    nrm, np_ = _d(nrm)
+    typ, tp = _i(typ)
+    return float(lib().orc_volume(C.byref(e), x.shape[0], xp, np_, tp))
+
+
+def volume_forces(e, x, nrm, typ):
+    """(F, T, U_V) of the volume term alone."""
+    x, xp = _d(x)
+    nrm, np_ = _d(nrm)
+    typ, tp = _i(typ)
+    F, T = np.zeros_like(x), np.zeros_like(x)
+    U = lib().orc_volume_forces(C.byref(e), x.shape[0], xp, np_, tp, _d(F)[1], _d(T)[1])
+    return F, T, float(U)
+
+
+def forces_ext(p, e, system, x=None, nrm=None, nthreads=0):
+    x = system.x if x is None else x
+    nrm = system.n if nrm is None else nrm
+    x, xp = _d(x)
+    nrm, np_ = _d(nrm)
+    typ, tp = _i(system.type)
+    b, bp = _i(system.bonds.reshape(-1, 2))
+    r0, r0p = _d(system.r0)
+    n = x.shape[0]
+    F, T, en = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(2)
+    lib().orc_forces_ext(C.byref(p), C.byref(e), n, xp, np_, tp, b.shape[0], bp, r0p, _d(F)[1], _d(T)[1],
+                         _d(en)[1], nthreads)
+    return F, T, en[0], en[1]
+
+
+def langevin_step(p, e, typ, nrm, dt, step, v, w):
+    """The thermostat update on copies of v and w; returns (v, w)."""
+    typ, tp = _i(typ)
+    nrm, np_ = _d(nrm)
+    v = np.array(v, dtype=np.float64, copy=True)
+    w = np.array(w, dtype=np.float64, copy=True)
+    lib().orc_langevin_step(C.byref(p), C.byref(e), typ.shape[0], tp, np_, float(dt), int(step),
+                            _d(v)[1], _d(w)[1])
+    return v, w
+
+
+def vv_run_ext(p, e, system, dt, nsteps, step0=0, nthreads=0):
+    """Velocity Verlet with the volume term and the thermostat on copies of the state;
+    returns (x, v, n, w, energies)."""
+    x = np.array(system.x, dtype=np.float64, copy=True)
+    v = np.array(system.v, dtype=np.float64, copy=True)
+    nrm = np.array(system.n, dtype=np.float64, copy=True)
+    w = np.array(system.w, dtype=np.float64, copy=True)
+    typ, tp = _i(system.type)
+    b, bp = _i(system.bonds.reshape(-1, 2))
+    r0, r0p = _d(system.r0)
+    en = np.zeros((nsteps + 1, 3))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    lib().orc_vv_run_ext(C.byref(p), C.byref(e), int(step0), x.shape[0], dp(x), dp(v), dp(nrm), dp(w), tp,
+                         b.shape[0], bp, r0p, float(dt), int(nsteps), dp(en), nthreads)
+    return x, v, nrm, w, en

@@ -547,13 +547,127 @@ static void rotor_drift(double *n, const double *w, double dt) {
     if (nn > 0.0) for (int a = 0; a < 3; ++a) n[a] /= nn;
 }
 
+/* ------------------------------------------------------------------ volume and thermostat */
+
+/* Philox4x32-10: ten rounds of two 32x32 -> 64-bit products whose halves are
+ * mixed with the other counter words and the key; the key is bumped by the
+ * Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The lipid sums the volume needs: sum x.n, sum x, sum n, count. */
+static void lipid_sums(int64_t n, const double *x, const double *nrm, const int32_t *type,
+                       double *sxn, double sx[3], double sn[3], double *cnt) {
+    *sxn = 0.0; *cnt = 0.0;
+    for (int a = 0; a < 3; ++a) { sx[a] = 0.0; sn[a] = 0.0; }
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] != LIPID) continue;
+        *sxn += dot3(x + 3 * i, nrm + 3 * i);
+        for (int a = 0; a < 3; ++a) { sx[a] += x[3 * i + a]; sn[a] += nrm[3 * i + a]; }
+        *cnt += 1.0;
+    }
+}
+
+double orc_volume(const orc_ext *e, int64_t n, const double *x, const double *nrm, const int32_t *type) {
+    double sxn, sx[3], sn[3], cnt;
+    lipid_sums(n, x, nrm, type, &sxn, sx, sn, &cnt);
+    if (cnt == 0.0) return 0.0;
+    /* sum (x_i - xbar).n_i = sum x.n - (sum x).(sum n) / N_L */
+    return e->lipid_area / 3.0 * (sxn - dot3(sx, sn) / cnt);
+}
+
+double orc_volume_forces(const orc_ext *e, int64_t n, const double *x, const double *nrm,
+                         const int32_t *type, double *F, double *T) {
+    if (!(e->vol_k > 0.0) || !(e->vol_target > 0.0)) return 0.0;
+    double sxn, sx[3], sn[3], cnt;
+    lipid_sums(n, x, nrm, type, &sxn, sx, sn, &cnt);
+    if (cnt == 0.0) return 0.0;
+    const double V = e->lipid_area / 3.0 * (sxn - dot3(sx, sn) / cnt);
+    const double dUdV = e->vol_k * (V - e->vol_target) / e->vol_target;
+    /* dV/dx_i = (a_L/3)(n_i - nbar), dV/dn_i = (a_L/3)(x_i - xbar) */
+    const double kap = dUdV * e->lipid_area / 3.0;
+    double xbar[3], nbar[3];
+    for (int a = 0; a < 3; ++a) { xbar[a] = sx[a] / cnt; nbar[a] = sn[a] / cnt; }
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] != LIPID) continue;
+        const double *xi = x + 3 * i, *ni = nrm + 3 * i;
+        double g[3];                          /* -dU_V/dn_i */
+        for (int a = 0; a < 3; ++a) {
+            F[3 * i + a] -= kap * (ni[a] - nbar[a]);
+            g[a] = -kap * (xi[a] - xbar[a]);
+        }
+        double t[3];
+        cross3(ni, g, t);
+        for (int a = 0; a < 3; ++a) T[3 * i + a] += t[a];
+    }
+    return 0.5 * e->vol_k * (V - e->vol_target) * (V - e->vol_target) / e->vol_target;
+}
+
+int orc_forces_ext(const orc_params *p, const orc_ext *e, int64_t n, const double *x, const double *nrm,
+                   const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
+                   double *F, double *T, double *energy, int nthreads) {
+    int r = orc_forces(p, n, x, nrm, type, nbond, bonds, r0, F, T, energy, nthreads);
+    if (e) energy[0] += orc_volume_forces(e, n, x, nrm, type, F, T);
+    return r;
+}
+
+/* A unit-variance uniform deviate from a 32-bit word: (r - (2^32 - 1)/2) sqrt(12) / 2^32. */
+static double unit_uniform(uint32_t r) {
+    return ((double)r - 2147483647.5) * (sqrt(12.0) / 4294967296.0);
+}
+
+void orc_langevin_step(const orc_params *p, const orc_ext *e, int64_t n, const int32_t *type,
+                       const double *nrm, double dt, uint64_t step, double *v, double *w) {
+    const uint32_t key[2] = {(uint32_t)e->seed, (uint32_t)(e->seed >> 32)};
+    const double c = exp(-e->gamma * dt), cr = exp(-e->gamma_rot * dt);
+    for (int64_t i = 0; i < n; ++i) {
+        const int t = type[i];
+        if (e->gamma > 0.0) {
+            const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+            uint32_t r[4];
+            orc_philox4x32_10(ctr, key, r);
+            const double amp = sqrt((1.0 - c * c) * e->kT / p->mass[t]);
+            for (int a = 0; a < 3; ++a) v[3 * i + a] = c * v[3 * i + a] + amp * unit_uniform(r[a]);
+        }
+        if (t == LIPID && e->gamma_rot > 0.0) {
+            const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), 1u};
+            uint32_t r[4];
+            orc_philox4x32_10(ctr, key, r);
+            double xi[3] = {unit_uniform(r[0]), unit_uniform(r[1]), unit_uniform(r[2])};
+            const double *ni = nrm + 3 * i;
+            const double pn = dot3(xi, ni);
+            const double amp = sqrt((1.0 - cr * cr) * e->kT / p->inertia);
+            for (int a = 0; a < 3; ++a) w[3 * i + a] = cr * w[3 * i + a] + amp * (xi[a] - pn * ni[a]);
+        }
+    }
+}
+
 int orc_vv_run(const orc_params *p, int64_t n, double *x, double *v, double *nrm, double *w,
                const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
                double dt, int64_t nsteps, double *energies, int nthreads) {
+    return orc_vv_run_ext(p, NULL, 0, n, x, v, nrm, w, type, nbond, bonds, r0, dt, nsteps, energies, nthreads);
+}
+
+int orc_vv_run_ext(const orc_params *p, const orc_ext *e, uint64_t step0, int64_t n, double *x, double *v,
+                   double *nrm, double *w, const int32_t *type, int64_t nbond, const int32_t *bonds,
+                   const double *r0, double dt, int64_t nsteps, double *energies, int nthreads) {
     double *F = (double *)malloc(sizeof(double) * (size_t)(3 * n + 3));
     double *T = (double *)malloc(sizeof(double) * (size_t)(3 * n + 3));
     double en[2];
-    orc_forces(p, n, x, nrm, type, nbond, bonds, r0, F, T, en, nthreads);
+    const int thermo = e && (e->gamma > 0.0 || e->gamma_rot > 0.0);
+    orc_forces_ext(p, e, n, x, nrm, type, nbond, bonds, r0, F, T, en, nthreads);
     if (energies) {
         double ke = kinetic(p, n, v, w, type);
         energies[0] = ke; energies[1] = en[0]; energies[2] = ke + en[0];
@@ -567,13 +681,14 @@ int orc_vv_run(const orc_params *p, int64_t n, double *x, double *v, double *nrm
             for (int a = 0; a < 3; ++a) x[3 * i + a] += dt * v[3 * i + a];
             if (type[i] == LIPID) rotor_drift(nrm + 3 * i, w + 3 * i, dt);
         }
-        orc_forces(p, n, x, nrm, type, nbond, bonds, r0, F, T, en, nthreads);
+        orc_forces_ext(p, e, n, x, nrm, type, nbond, bonds, r0, F, T, en, nthreads);
         for (int64_t i = 0; i < n; ++i) {
             double m = p->mass[type[i]];
             for (int a = 0; a < 3; ++a) v[3 * i + a] += 0.5 * dt * F[3 * i + a] / m;
             if (type[i] == LIPID)
                 for (int a = 0; a < 3; ++a) w[3 * i + a] += 0.5 * dt * T[3 * i + a] / p->inertia;
         }
+        if (thermo) orc_langevin_step(p, e, n, type, nrm, dt, step0 + (uint64_t)st, v, w);
         if (energies) {
             double ke = kinetic(p, n, v, w, type);
             energies[3 * st] = ke; energies[3 * st + 1] = en[0]; energies[3 * st + 2] = ke + en[0];

@@ -36,6 +36,14 @@
  *   orc_morton       hand-computed keys for known points.
  *   orc_vv_run       energy error falls ~4x when dt halves; time reversal;
  *                    free rotor; harmonic dimer period.
+ *   orc_philox4x32_10  the generator's published known-answer vectors.
+ *   orc_volume       sphere and Evans-Fung cell volumes (closed form and
+ *                    quadrature); translation and rotation invariance.
+ *   orc_volume_forces  finite differences of U_V in x and n; sum F = 0 and
+ *                    sum(r x F + tau) = 0.
+ *   orc_langevin_step  deviates' mean and variance; equipartition of free
+ *                    particles and free rotors (<m v^2> = 3 kT, <I w^2> = 2 kT);
+ *                    the exact decay of the mean velocity.
  */
 #ifndef RBC_ORACLE_H
 #define RBC_ORACLE_H
@@ -101,6 +109,53 @@ int64_t orc_cell_pairs(const orc_params *p, int64_t k, const double *seeds, cons
 int orc_vv_run(const orc_params *p, int64_t n, double *x, double *v, double *nrm, double *w,
                const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
                double dt, int64_t nsteps, double *energies, int nthreads);
+
+/* ---- Beyond the conservative model: a harmonic volume constraint (the
+ * whole-cell fluctuation run of the Results section keeps the cell's
+ * surface-to-volume ratio with one) and a Langevin thermostat.  The paper
+ * states neither form; these are readings. */
+typedef struct {
+    double vol_k;        /* k_V of U_V = k_V/2 (V - V0)^2 / V0; 0 = no volume term */
+    double vol_target;   /* V0 */
+    double lipid_area;   /* a_L, membrane area per lipid */
+    double kT;           /* thermostat temperature */
+    double gamma;        /* translational friction rate; 0 = none */
+    double gamma_rot;    /* lipid rotational friction rate; 0 = none */
+    uint64_t seed;       /* Philox key */
+} orc_ext;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): counter ctr, key key. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Enclosed volume from the lipids by the divergence theorem: each lipid stands for
+ * a membrane patch of area a_L with outward normal n_i, so
+ * V = (a_L / 3) sum_i (x_i - xbar) . n_i with xbar the lipid centroid. */
+double orc_volume(const orc_ext *e, int64_t n, const double *x, const double *nrm, const int32_t *type);
+
+/* Adds -dU_V/dx_i to F and n_i x (-dU_V/dn_i) to T (lipids only); returns U_V. */
+double orc_volume_forces(const orc_ext *e, int64_t n, const double *x, const double *nrm,
+                         const int32_t *type, double *F, double *T);
+
+/* orc_forces plus the volume term (energy[0] includes U_V; energy[1], the pair and
+ * bond virial, does not). */
+int orc_forces_ext(const orc_params *p, const orc_ext *e, int64_t n, const double *x, const double *nrm,
+                   const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
+                   double *F, double *T, double *energy, int nthreads);
+
+/* The thermostat's exact Ornstein-Uhlenbeck velocity update for step number `step`:
+ * v <- c v + sqrt((1 - c^2) kT / m) xi with c = exp(-gamma dt); for lipids also
+ * w <- c_r w + sqrt((1 - c_r^2) kT / I) (xi' - (xi'.n) n).  xi, xi' hold unit-variance
+ * uniform deviates from Philox4x32-10 with counter (particle id, step low word,
+ * step high word, 0 or 1) and key (seed low word, seed high word). */
+void orc_langevin_step(const orc_params *p, const orc_ext *e, int64_t n, const int32_t *type,
+                       const double *nrm, double dt, uint64_t step, double *v, double *w);
+
+/* Velocity Verlet as orc_vv_run, with the volume term in every force evaluation
+ * and, when a friction rate is set, the thermostat update after each step's
+ * closing half-kick; the steps are numbered step0 + 1 ... step0 + nsteps. */
+int orc_vv_run_ext(const orc_params *p, const orc_ext *e, uint64_t step0, int64_t n, double *x, double *v,
+                   double *nrm, double *w, const int32_t *type, int64_t nbond, const int32_t *bonds,
+                   const double *r0, double dt, int64_t nsteps, double *energies, int nthreads);
 
 #ifdef __cplusplus
 }

@@ -61,6 +61,13 @@ class ModelParams:
     skin: float = 0.3
     lloyd_iters: int = 10
     protein_cells: int = 0        # 1: protein beads get their own Voronoi cells (detached cytoskeleton)
+    vol_k: float = 0.0            # harmonic volume constraint k_V (0: off)
+    vol_target: float = 0.0       # V0; 0: the volume when the system is loaded
+    lipid_area: float = LIPID_AREA
+    kT: float = 0.22              # thermostat temperature
+    gamma: float = 0.0            # Langevin friction rate on translations (0: off)
+    gamma_rot: float = 0.0        # Langevin friction rate on lipid rotations (0: off)
+    seed: int = 0                 # thermostat random stream
 
     def rc_table(self) -> np.ndarray:
         """Per type-pair cutoff: r_c for lipid-lipid, the WCA range otherwise."""

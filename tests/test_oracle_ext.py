@@ -1,0 +1,193 @@
+"""Oracle pins for the volume constraint and the Langevin thermostat.
+
+The paper applies a harmonic volume constraint in its whole-cell fluctuation run
+(Results section) without giving its form, and names no thermostat; the forms
+here are readings.  What pins them besides themselves: the generator's
+published known-answer vectors, closed-form and quadrature volumes, finite
+differences of the volume energy, conservation laws, and equipartition.
+"""
+import dataclasses
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1701_02059_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        assert O.philox(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_deviates_have_zero_mean_unit_variance(mp):
+    """The thermostat's deviates, read back through the update with c = 0 (gamma
+    dt large, kT = m = 1): v' = xi."""
+    n = 200_000
+    m = dataclasses.replace(mp, kT=1.0, gamma=1e6, gamma_rot=0.0, mass=(1.0, 1.0, 1.0))
+    p, e = O.make_params(m), O.make_ext(m)
+    typ = np.ones(n, np.int32)
+    z = np.zeros((n, 3))
+    v, _ = O.langevin_step(p, e, typ, z, 1.0, 7, z, z)
+    xi = v.ravel()
+    assert abs(xi.mean()) < 5 / math.sqrt(xi.size)
+    assert abs(xi.var() - 1.0) < 0.01
+    assert np.abs(xi).max() <= math.sqrt(3.0)              # uniform on [-sqrt 3, sqrt 3]
+    v2, _ = O.langevin_step(p, e, typ, z, 1.0, 7, z, z)
+    v3, _ = O.langevin_step(p, e, typ, z, 1.0, 8, z, z)
+    assert np.array_equal(v, v2) and not np.array_equal(v, v3)
+
+
+# ------------------------------------------------------------------ volume
+
+def _sphere(N=20000, R=40.0):
+    u = I._fibonacci_sphere(N)
+    return R * u, u.copy(), np.zeros(N, np.int32)
+
+
+def test_volume_of_sphere(mp):
+    N, R = 20000, 40.0
+    x, n, t = _sphere(N, R)
+    e = O.make_ext(dataclasses.replace(mp, lipid_area=4 * math.pi * R * R / N))
+    assert O.volume(e, x, n, t) == pytest.approx(4.0 / 3.0 * math.pi * R ** 3, rel=1e-9)
+    # proteins do not count
+    x2 = np.concatenate([x, np.full((5, 3), 3.0)])
+    n2 = np.concatenate([n, np.zeros((5, 3))])
+    t2 = np.concatenate([t, np.ones(5, np.int32)])
+    assert O.volume(e, x2, n2, t2) == O.volume(e, x, n, t)
+
+
+def test_volume_of_evans_fung_cell(mp):
+    """The 499,952-particle cell against the quadrature volume of the Evans-Fung shape."""
+    s = I.config("rbc500k")
+    A, V = I.evans_fung_area_volume()
+    e = O.make_ext(mp)
+    est = O.volume(e, s.x, s.n, s.type)
+    assert est == pytest.approx(V * s.scale ** 3, rel=2e-3)
+
+
+def test_volume_invariances(mp):
+    x, n, t = _sphere(3000, 20.0)
+    rng = np.random.default_rng(3)
+    x = x * np.array([1.0, 0.8, 0.6]) + rng.normal(0, 0.05, x.shape)   # an ellipsoid, jittered
+    e = O.make_ext(mp)
+    V = O.volume(e, x, n, t)
+    assert O.volume(e, x + [3.0, -7.0, 11.0], n, t) == pytest.approx(V, rel=1e-12)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    assert O.volume(e, x @ q.T, n @ q.T, t) == pytest.approx(V, rel=1e-12)
+
+
+def _rot(v, axis, th):
+    k = np.asarray(axis, dtype=np.float64)
+    return v * math.cos(th) + np.cross(k, v) * math.sin(th) + k * np.dot(k, v) * (1 - math.cos(th))
+
+
+def test_volume_forces_finite_differences_and_conservation(mp):
+    rng = np.random.default_rng(11)
+    x, n, t = _sphere(400, 8.0)
+    x = x + rng.normal(0, 0.2, x.shape)
+    t[::7] = 1                                          # some proteins: no volume force on them
+    n[t != 0] = 0.0
+    e0 = O.make_ext(mp)
+    V = O.volume(e0, x, n, t)
+    e = O.make_ext(dataclasses.replace(mp, vol_k=5.0), vol_target=0.9 * V)
+    F, T, U = O.volume_forces(e, x, n, t)
+    assert U == pytest.approx(0.5 * 5.0 * (0.1 * V) ** 2 / (0.9 * V), rel=1e-12)
+
+    def energy(xx, nn):
+        return O.volume_forces(e, xx, nn, t)[2]
+
+    h = 1e-5
+    for i in (0, 3, 7, 50, 399):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            fd = -(energy(xp, n) - energy(xm, n)) / (2 * h)
+            assert F[i, a] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+            if t[i] == 0:
+                ax = np.eye(3)[a]
+                np_, nm = n.copy(), n.copy()
+                np_[i] = _rot(n[i], ax, h)
+                nm[i] = _rot(n[i], ax, -h)
+                tq = -(energy(x, np_) - energy(x, nm)) / (2 * h)
+                assert T[i, a] == pytest.approx(tq, rel=1e-6, abs=1e-9)
+    assert np.all(F[t != 0] == 0) and np.all(T[t != 0] == 0)
+    assert np.abs(F.sum(axis=0)).max() < 1e-12 * np.abs(F).sum()
+    L = np.cross(x, F).sum(axis=0) + T.sum(axis=0)
+    assert np.abs(L).max() < 1e-12 * (np.abs(np.cross(x, F)).sum() + np.abs(T).sum())
+
+
+def test_forces_ext_adds_volume_term(mp):
+    s = I.config("tiny")
+    p = O.params_for(s, mp)
+    V = O.volume(O.make_ext(mp), s.x, s.n, s.type)
+    e = O.make_ext(dataclasses.replace(mp, vol_k=2.0), vol_target=1.05 * V)
+    F0, T0, U0, W0 = O.forces(p, s)
+    F1, T1, U1, W1 = O.forces_ext(p, e, s)
+    Fv, Tv, Uv = O.volume_forces(e, s.x, s.n, s.type)
+    assert np.allclose(F1, F0 + Fv, rtol=0, atol=1e-13) and np.allclose(T1, T0 + Tv, rtol=0, atol=1e-13)
+    assert U1 == pytest.approx(U0 + Uv, rel=1e-14) and W1 == W0
+
+
+# ------------------------------------------------------------------ thermostat
+
+def _free_gas(nl=600, npr=900, spacing=6.0):
+    """Particles on a wide cubic grid: no pair within any cutoff."""
+    N = nl + npr
+    side = int(math.ceil(N ** (1 / 3)))
+    g = np.stack(np.meshgrid(*[np.arange(side)] * 3, indexing="ij"), axis=-1).reshape(-1, 3)[:N] * spacing
+    typ = np.concatenate([np.zeros(nl), np.ones(npr)]).astype(np.int32)
+    rng = np.random.default_rng(2)
+    nrm = np.zeros((N, 3))
+    nrm[:nl] = I._unit(rng.normal(size=(nl, 3)))
+    return I.System("gas", g.astype(np.float64), nrm, typ, np.zeros((N, 3)), np.zeros((N, 3)),
+                    np.zeros((0, 2), np.int32), np.zeros(0), np.zeros(3), np.zeros(3, np.int32))
+
+
+def test_equipartition_free_particles(mp):
+    """<m v^2> -> 3 kT per particle and <I w^2> -> 2 kT per lipid (a linear rotor's two
+    rotational degrees of freedom): the friction and the noise balance."""
+    s = _free_gas()
+    m = dataclasses.replace(mp, kT=0.5, gamma=2.0, gamma_rot=2.0, mass=(1.0, 2.0, 3.0), inertia=0.7)
+    p, e = O.params_for(s, m), O.make_ext(m)
+    nl = int(np.sum(s.type == 0))
+    x, v, n, w, en = O.vv_run_ext(p, e, s, 0.01, 2500)
+    # time average of KE over the second half (5 / gamma relaxation times in)
+    ke = en[1000:, 0].mean()
+    expect = (1.5 * s.N + 1.0 * nl) * m.kT
+    assert ke == pytest.approx(expect, rel=0.03)
+    # per degree of freedom at the end, over particles
+    mass = np.asarray(m.mass)[s.type]
+    assert np.mean(mass * np.sum(v * v, axis=1)) == pytest.approx(3 * m.kT, rel=0.08)
+    lip = s.type == 0
+    assert np.mean(m.inertia * np.sum(w[lip] ** 2, axis=1)) == pytest.approx(2 * m.kT, rel=0.1)
+    # rotations stay perpendicular to the lipid axis
+    assert np.abs(np.sum(w[lip] * n[lip], axis=1)).max() < 1e-12
+
+
+def test_thermostat_exact_decay_without_noise(mp):
+    m = dataclasses.replace(mp, kT=0.0, gamma=3.0, gamma_rot=5.0)
+    s = _free_gas(10, 10)
+    p, e = O.params_for(s, m), O.make_ext(m)
+    rng = np.random.default_rng(4)
+    v0, w0 = rng.normal(size=(20, 3)), rng.normal(size=(20, 3))
+    v, w = O.langevin_step(p, e, s.type, s.n, 0.01, 1, v0, w0)
+    assert np.array_equal(v, math.exp(-0.03) * v0)
+    assert np.array_equal(w[:10], math.exp(-0.05) * w0[:10]) and np.array_equal(w[10:], w0[10:])
+
+
+def test_ext_off_equals_nve(mp):
+    s = I.config("patch")
+    p = O.params_for(s, mp)
+    a = O.vv_run(p, s, 0.01, 5)
+    b = O.vv_run_ext(p, O.make_ext(mp), s, 0.01, 5)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
