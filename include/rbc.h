@@ -86,6 +86,24 @@ typedef struct {
                                                    separate set of cells, ceil(N_P / cell_target) of
                                                    them (a detached cytoskeleton) -- Force Evaluation
                                                    section */
+    /* Harmonic volume constraint (the Results section's whole-cell fluctuation run
+     * keeps the cell's surface-to-volume ratio with one; its form is a reading):
+     * U_V = vol_k/2 (V - V0)^2 / V0 with V = lipid_area/3 sum over lipids of
+     * (x_i - xbar).n_i, xbar the lipid centroid (divergence theorem; lipid
+     * orientations are the outward normals).  Open boundaries only. */
+    double vol_k;                               /* 0: off */
+    double vol_target;                          /* V0; 0: the V of the loaded state */
+    double lipid_area;                          /* membrane area per lipid */
+    /* Langevin thermostat (a reading; the paper names none): after each step's
+     * closing half-kick, v <- c v + sqrt((1 - c^2) kT / m) xi with c = exp(-gamma dt),
+     * and for lipids w <- c_r w + sqrt((1 - c_r^2) kT / I) (xi' - (xi'.n) n).
+     * xi, xi': unit-variance uniform deviates from Philox4x32-10 (Salmon et al.,
+     * SC'11) with counter (particle id, step low and high words, 0 or 1) and key
+     * (seed low and high words); steps count from 1 after loading. */
+    double kT;
+    double gamma;                               /* translational friction rate; 0: none */
+    double gamma_rot;                           /* lipid rotational friction rate; 0: none */
+    uint64_t seed;
 } rbc_params;
 
 /* ---- single-system context (an ensemble with one slot) ---- */
@@ -130,8 +148,10 @@ rbc_status rbc_get_state(rbc_handle h, double *x, double *nrm, double *v, double
  * [host] ij: cap x 2.  *npairs receives the full count even when it exceeds cap. */
 rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs);
 
-/* Energies of the current state (sync).  [host] out[6]: U, W, kinetic energy
- * (translational + lipid rotational), total E = KE + U, |sum F|, |sum (r x F + tau)|. */
+/* Energies of the current state (sync).  [host] out[7]: U (with U_V when the
+ * volume constraint is on), W (pairs and bonds), kinetic energy (translational +
+ * lipid rotational), total E = KE + U, |sum F|, |sum (r x F + tau)|, and the
+ * volume V of the lipid surface (as defined for the volume constraint). */
 rbc_status rbc_energy(rbc_handle h, double *out);
 
 /* Counters (sync).  [host] out[9]: steps done, cell updates, early (skin)
@@ -193,7 +213,7 @@ rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const do
 rbc_status rbc_ensemble_step(rbc_handle h, int64_t nsteps, double dt);
 /* State of one slot in its caller order ([device] n x 3 each, any may be NULL). */
 rbc_status rbc_ensemble_get_state(rbc_handle h, int32_t slot, double *x, double *nrm, double *v, double *w);
-/* Energies of one slot ([host] out[6] as rbc_energy). */
+/* Energies of one slot ([host] out[7] as rbc_energy). */
 rbc_status rbc_ensemble_energy(rbc_handle h, int32_t slot, double *out);
 /* Free a slot and its memory. */
 rbc_status rbc_ensemble_retire(rbc_handle h, int32_t slot);

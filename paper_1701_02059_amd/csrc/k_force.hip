@@ -150,6 +150,7 @@ __device__ __forceinline__ T wca_pair(const DevParams &P, T dx, T dy, T dz, T &f
 // Free linear-rotor drift: n rotated about omega by |omega| dt (Rodrigues), then
 // renormalised.
 __device__ __forceinline__ D4 rotor_drift(D4 n, const D4 &w, double dt) {
+#pragma clang fp contract(off)
     const double wn = sqrt(w.x * w.x + w.y * w.y + w.z * w.z);
     if (wn > 0.0) {
         const double iw = 1.0 / wn;
@@ -179,6 +180,95 @@ __device__ __forceinline__ D4 rotor_drift(D4 n, const D4 &w, double dt) {
         n.x *= in; n.y *= in; n.z *= in;
     }
     return n;
+}
+
+// Half-kick v += h a, drift x += dt v, and the drift's statistics.  Every
+// operation is rounded on its own (no contraction), so the drift fused into the
+// force kernel and the standalone kick-drift give the same bits.
+__device__ __forceinline__ void half_kick(D4 &v, double h, double ax, double ay, double az) {
+#pragma clang fp contract(off)
+    v.x += h * ax;
+    v.y += h * ay;
+    v.z += h * az;
+}
+
+__device__ __forceinline__ void drift_pos(D4 &x, const D4 &v, double dt) {
+#pragma clang fp contract(off)
+    x.x += dt * v.x;
+    x.y += dt * v.y;
+    x.z += dt * v.z;
+}
+
+__device__ __forceinline__ void drift_measures(const D4 &x, const D4 &v, const D4 &b, double &disp2, double &v2,
+                                               bool &bad) {
+#pragma clang fp contract(off)
+    const double ddx = x.x - b.x, ddy = x.y - b.y, ddz = x.z - b.z;
+    disp2 = ddx * ddx + ddy * ddy + ddz * ddz;
+    v2 = v.x * v.x + v.y * v.y + v.z * v.z;
+    bad = !isfinite(x.x + x.y + x.z + v.x + v.y + v.z);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two 32 x 32
+// -> 64-bit products mixed with the other words and the key, which advances by
+// the Weyl constants between rounds.
+__device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                         uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Thermostat update of one particle after its closing half-kick: the exact
+// Ornstein-Uhlenbeck step v <- c v + sqrt((1 - c^2) kT / m) xi, xi uniform with unit
+// variance from the Philox words of counter (caller id, step, 0); lipids also
+// w <- c_r w + sqrt((1 - c_r^2) kT / I) (xi' - (xi'.n) n) from counter (.., 1).
+// Every operation is rounded on its own (no contraction): the fused and the
+// stored-then-reloaded step paths then agree bit for bit.
+__device__ __forceinline__ void langevin_update(const DevParams &P, int gid, unsigned long long step, int t,
+                                                const D4 &n, D4 &v, D4 &w) {
+#pragma clang fp contract(off)
+    const uint32_t s_lo = (uint32_t)step, s_hi = (uint32_t)(step >> 32);
+    constexpr double half = 2147483647.5;   // (2^32 - 1) / 2: centres the words
+    {
+        uint32_t c0 = (uint32_t)gid, c1 = s_lo, c2 = s_hi, c3 = 0u;
+        philox10(c0, c1, c2, c3, P.seed_lo, P.seed_hi);
+        const double a = P.ou_a[t];
+        v.x = P.ou_c * v.x + a * ((double)c0 - half);
+        v.y = P.ou_c * v.y + a * ((double)c1 - half);
+        v.z = P.ou_c * v.z + a * ((double)c2 - half);
+    }
+    if (t == 0) {
+        uint32_t c0 = (uint32_t)gid, c1 = s_lo, c2 = s_hi, c3 = 1u;
+        philox10(c0, c1, c2, c3, P.seed_lo, P.seed_hi);
+        const double xx = (double)c0 - half, xy = (double)c1 - half, xz = (double)c2 - half;
+        const double pn = xx * n.x + xy * n.y + xz * n.z;
+        w.x = P.ou_cr * w.x + P.ou_ar * (xx - pn * n.x);
+        w.y = P.ou_cr * w.y + P.ou_ar * (xy - pn * n.y);
+        w.z = P.ou_cr * w.z + P.ou_ar * (xz - pn * n.z);
+    }
+}
+
+// Volume term on a lipid: F -= kap (n - nbar), tau += n x (-kap (x - xbar)), each
+// operation rounded on its own (the same bits in every kernel variant).
+__device__ __forceinline__ void volume_term(const SysScal *sc, const D4 &x, const D4 &n, double &Fx, double &Fy,
+                                            double &Fz, D4 &Tq) {
+#pragma clang fp contract(off)
+    const double kap = sc->volkap;
+    Fx -= kap * (n.x - sc->nbar[0]);
+    Fy -= kap * (n.y - sc->nbar[1]);
+    Fz -= kap * (n.z - sc->nbar[2]);
+    const double gx = -kap * (x.x - sc->xbar[0]), gy = -kap * (x.y - sc->xbar[1]), gz = -kap * (x.z - sc->xbar[2]);
+    Tq.x += n.y * gz - n.z * gy;
+    Tq.y += n.z * gx - n.x * gz;
+    Tq.z += n.x * gy - n.y * gx;
 }
 
 // Per-wavefront drift statistics: the largest |x - x_build|^2 and |v|^2 of the
@@ -364,7 +454,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     D4 v = {0.0, 0.0, 0.0, 0.0}, w = {0.0, 0.0, 0.0, 0.0};
     double disp2 = 0.0, vmax2 = 0.0;
     bool bad = false;
-    const D4 Tq = {(double)tx, (double)ty, (double)tz, 0.0};
+    D4 Tq = {(double)tx, (double)ty, (double)tz, 0.0};
     if (valid) {
         // bonds of this particle (CSR by caller id), FP64 in both modes
         const int g = S.gid[i];
@@ -384,6 +474,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
                 W += 0.5 * f * d2;
             }
         }
+        if (P.vol_on && ti == 0) volume_term(S.sc, pi, ni, Fx, Fy, Fz, Tq);
         if (KICK != 2) {
             S.frc[i] = D4{Fx, Fy, Fz, 0.0};
             S.trq[i] = Tq;
@@ -393,42 +484,27 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
         if (KICK) {
             const double h = 0.5 * dt * P.inv_mass[ti];
             const double hw = 0.5 * dt * P.inv_inertia;
-            v.x += h * Fx;
-            v.y += h * Fy;
-            v.z += h * Fz;
-            if (ti == 0) {
-                w.x += hw * Tq.x;
-                w.y += hw * Tq.y;
-                w.z += hw * Tq.z;
-            }
+            half_kick(v, h, Fx, Fy, Fz);
+            if (ti == 0) half_kick(w, hw, Tq.x, Tq.y, Tq.z);
+            if (P.thermo_on) langevin_update(P, g, S.sc->step, ti, ni, v, w);
             if (KICK == 1) {
                 S.vel[i] = v;
                 if (ti == 0) S.angv[i] = w;
             } else {
                 D4 vn = v, wn = w, xn = pi;
-                vn.x += h * Fx;
-                vn.y += h * Fy;
-                vn.z += h * Fz;
-                xn.x += dt * vn.x;
-                xn.y += dt * vn.y;
-                xn.z += dt * vn.z;
+                half_kick(vn, h, Fx, Fy, Fz);
+                drift_pos(xn, vn, dt);
                 S.vel[i] = vn;
                 S.pos2[i] = xn;
                 D4 on = ni;
                 if (ti == 0) {
-                    wn.x += hw * Tq.x;
-                    wn.y += hw * Tq.y;
-                    wn.z += hw * Tq.z;
+                    half_kick(wn, hw, Tq.x, Tq.y, Tq.z);
                     S.angv[i] = wn;
                     on = rotor_drift(ni, wn, dt);
                 }
                 S.ori2[i] = on;
                 S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
-                const D4 b = S.xb[i];
-                const double ddx = xn.x - b.x, ddy = xn.y - b.y, ddz = xn.z - b.z;
-                disp2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                vmax2 = vn.x * vn.x + vn.y * vn.y + vn.z * vn.z;
-                bad = !isfinite(xn.x + xn.y + xn.z + vn.x + vn.y + vn.z);
+                drift_measures(xn, vn, S.xb[i], disp2, vmax2, bad);
             }
         }
     }
@@ -469,6 +545,7 @@ static void launch_force_t(const LaunchCtx &L, double dt) {
 }
 
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt) {
+    if (L.prm.vol_on) launch_volume(L);   // the volume force needs V of the current state
     if (kick == 2) {
         if (mixed) launch_force_t<1, 0, 2>(L, dt);
         else launch_force_t<0, 0, 2>(L, dt);
@@ -500,34 +577,25 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
     double disp2 = 0.0, v2 = 0.0;
     bool bad = false;
     if (i < S.n) {
-        D4 p = S.pos[i], v = S.vel[i], f = S.frc[i];
+        D4 p = S.pos[i], v = S.vel[i];
+        const D4 f = S.frc[i];
         const int t = (int)p.w;
         const double h = 0.5 * dt * P.inv_mass[t];
-        v.x += h * f.x;
-        v.y += h * f.y;
-        v.z += h * f.z;
-        p.x += dt * v.x;
-        p.y += dt * v.y;
-        p.z += dt * v.z;
+        half_kick(v, h, f.x, f.y, f.z);
+        drift_pos(p, v, dt);
         S.vel[i] = v;
         S.pos[i] = p;
         if (t == 0) {
             D4 w = S.angv[i];
             const D4 tq = S.trq[i];
             const double hw = 0.5 * dt * P.inv_inertia;
-            w.x += hw * tq.x;
-            w.y += hw * tq.y;
-            w.z += hw * tq.z;
+            half_kick(w, hw, tq.x, tq.y, tq.z);
             const D4 n = rotor_drift(S.ori[i], w, dt);
             S.angv[i] = w;
             S.ori[i] = n;
             S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
         }
-        const D4 b = S.xb[i];
-        const double ddx = p.x - b.x, ddy = p.y - b.y, ddz = p.z - b.z;
-        disp2 = ddx * ddx + ddy * ddy + ddz * ddz;
-        v2 = v.x * v.x + v.y * v.y + v.z * v.z;
-        bad = !isfinite(p.x + p.y + p.z + v.x + v.y + v.z);
+        drift_measures(p, v, S.xb[i], disp2, v2, bad);
     }
     drift_stats(S, lb, disp2, v2, bad);
 }
@@ -565,6 +633,7 @@ __global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int 
             atomicMax(&sc->maxdisp2, dbits(d));
             atomicMax(&sc->maxv2, dbits(v));
         }
+        if (part == 0) sc->step++;   // one drift per statistics pass
         if (swap && part == 0) {
             D4 *t = S.pos; S.pos = S.pos2; S.pos2 = t;
             t = S.ori; S.ori = S.ori2; S.ori2 = t;
@@ -585,7 +654,7 @@ void launch_drift_stats_swap(const LaunchCtx &L) {
 // ------------------------------------------------------------------ energy reduction
 
 // Fixed-order sum of the per-chunk partials of each system (one block per system).
-__global__ __launch_bounds__(256) void k_reduce_energy(const SysDev *Sd, int nsys) {
+__global__ __launch_bounds__(256) void k_reduce_energy(const SysDev *Sd, int nsys, int vol_on) {
     const SysDev &S = Sd[blockIdx.x];
     __shared__ double sh[9][4];
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -596,12 +665,84 @@ __global__ __launch_bounds__(256) void k_reduce_energy(const SysDev *Sd, int nsy
     if ((threadIdx.x & 63) == 0)
         for (int q = 0; q < 9; ++q) sh[q][w] = acc[q];
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int q = 0; q < 9; ++q) S.sc->energy[q] = ((sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]));
+        if (vol_on) S.sc->energy[0] += S.sc->volU;
+    }
 }
 
 void launch_reduce_energy(const LaunchCtx &L) {
-    hipLaunchKernelGGL(k_reduce_energy, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_reduce_energy, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys, L.prm.vol_on);
+}
+
+// ------------------------------------------------------------------ volume
+
+// Per-chunk lipid sums x.n, x, n and the lipid count, reduced across the
+// wavefront in a fixed butterfly (deterministic).
+__global__ __launch_bounds__(BLOCK) void k_volume_partials(const SysDev *Sd, Maps L_maps) {
+    const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
+    const SysDev &S = Sd[s];
+    const int lb = blockIdx.x - L_maps.p[s];
+    const int i = lb * BLOCK + threadIdx.x;
+    const int chunk = i / CHUNK;
+    if (chunk >= S.nchunk) return;
+    double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < S.n) {
+        const D4 p = S.pos[i];
+        if (p.w == 0.0) {
+            const D4 n = S.ori[i];
+            vals[0] = p.x * n.x + p.y * n.y + p.z * n.z;
+            vals[1] = p.x; vals[2] = p.y; vals[3] = p.z;
+            vals[4] = n.x; vals[5] = n.y; vals[6] = n.z;
+            vals[7] = 1.0;
+        }
+    }
+    for (int q = 0; q < 8; ++q) vals[q] = wave_sum(vals[q]);
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        for (int q = 0; q < 8; ++q) S.vpart[(size_t)chunk * 8 + q] = vals[q];
+}
+
+// Fixed-order sum of the chunk sums (one block per system), then
+// V = a_L/3 (sum x.n - (sum x).(sum n) / N_L), U_V = k_V/2 (V - V0)^2 / V0 and the
+// force constant dU_V/dV a_L/3.  V0 is the given target, else the first V measured.
+__global__ __launch_bounds__(256) void k_volume_reduce(const SysDev *Sd, int nsys, DevParams P) {
+    const SysDev &S = Sd[blockIdx.x];
+    __shared__ double sh[8][4];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = threadIdx.x; c < S.nchunk; c += blockDim.x)
+        for (int q = 0; q < 8; ++q) acc[q] += S.vpart[(size_t)c * 8 + q];
+    for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 8; ++q) sh[q][w] = acc[q];
+    __syncthreads();
+    if (threadIdx.x != 0 || S.n == 0) return;
+    double t[8];
+    for (int q = 0; q < 8; ++q) t[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    SysScal *sc = S.sc;
+    const double cnt = t[7];
+    if (cnt == 0.0) {
+        sc->volV = 0.0; sc->volkap = 0.0; sc->volU = 0.0;
+        for (int a = 0; a < 3; ++a) { sc->xbar[a] = 0.0; sc->nbar[a] = 0.0; }
+        return;
+    }
+    const double V = P.vol_a3 * (t[0] - (t[1] * t[4] + t[2] * t[5] + t[3] * t[6]) / cnt);
+    sc->volV = V;
+    for (int a = 0; a < 3; ++a) { sc->xbar[a] = t[1 + a] / cnt; sc->nbar[a] = t[4 + a] / cnt; }
+    if (sc->vol0 == 0.0) sc->vol0 = P.vol_target > 0.0 ? P.vol_target : V;
+    const double V0 = sc->vol0;
+    if (P.vol_on && V0 > 0.0) {
+        sc->volkap = P.vol_k * (V - V0) / V0 * P.vol_a3;
+        sc->volU = 0.5 * P.vol_k * (V - V0) * (V - V0) / V0;
+    } else {
+        sc->volkap = 0.0;
+        sc->volU = 0.0;
+    }
+}
+
+void launch_volume(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_volume_partials, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_volume_reduce, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys, L.prm);
 }
 
 // ------------------------------------------------------------------ outputs in caller order

@@ -140,6 +140,9 @@ bool valid_params(const rbc_params *p, std::string &why) {
     if (p->lloyd_iters < 1) { why = "lloyd_iters must be >= 1"; return false; }
     if (p->precision != RBC_FP64 && p->precision != RBC_MIXED) { why = "unknown precision"; return false; }
     if (p->protein_cells != 0 && p->protein_cells != 1) { why = "protein_cells must be 0 or 1"; return false; }
+    if (!(p->vol_k >= 0.0) || !(p->vol_target >= 0.0)) { why = "vol_k and vol_target must be >= 0"; return false; }
+    if (p->vol_k > 0.0 && !(p->lipid_area > 0.0)) { why = "the volume constraint needs lipid_area > 0"; return false; }
+    if (!(p->kT >= 0.0) || !(p->gamma >= 0.0) || !(p->gamma_rot >= 0.0)) { why = "kT, gamma and gamma_rot must be >= 0"; return false; }
     if (!(p->wca_sigma > 0.0) || !(p->k_bond >= 0.0)) { why = "bad WCA / bond constants"; return false; }
     return true;
 }
@@ -178,6 +181,29 @@ void make_dev_params(rbc_ctx *h) {
     d.zeta = (int32_t)p.zeta;
     d.inv_w = 1.0 / (p.rc[0][0] - p.r_min);
     d.dudr_k = p.eps * p.zeta * M_PI / (p.rc[0][0] - p.r_min);
+    d.vol_on = p.vol_k > 0.0;
+    d.vol_k = p.vol_k;
+    d.vol_target = p.vol_target;
+    d.vol_a3 = p.lipid_area / 3.0;
+    d.thermo_on = p.gamma > 0.0 || p.gamma_rot > 0.0;
+    d.seed_lo = (uint32_t)p.seed;
+    d.seed_hi = (uint32_t)(p.seed >> 32);
+    d.ou_c = d.ou_cr = 1.0;
+    d.ou_a[0] = d.ou_a[1] = d.ou_a[2] = d.ou_ar = 0.0;
+}
+
+// Thermostat coefficients for time step dt: the exact Ornstein-Uhlenbeck decay
+// c = exp(-gamma dt) and the noise amplitude per centred Philox word,
+// sqrt((1 - c^2) kT / m) sqrt(12) / 2^32 (unit variance per component).
+void set_step_dt(rbc_ctx *h, double dt) {
+    DevParams &d = h->dprm;
+    const rbc_params &p = h->prm;
+    const double unit = std::sqrt(12.0) / 4294967296.0;
+    d.ou_c = p.gamma > 0.0 ? std::exp(-p.gamma * dt) : 1.0;
+    for (int t = 0; t < 3; ++t) d.ou_a[t] = std::sqrt((1.0 - d.ou_c * d.ou_c) * p.kT / p.mass[t]) * unit;
+    d.ou_cr = p.gamma_rot > 0.0 ? std::exp(-p.gamma_rot * dt) : 1.0;
+    d.ou_ar = std::sqrt((1.0 - d.ou_cr * d.ou_cr) * p.kT / p.inertia) * unit;
+    h->L.prm = d;
 }
 
 // Sizes of one system and (with base != null) its device layout.
@@ -208,6 +234,7 @@ size_t layout(HostSys &s, char *base) {
     d.ori32b = c.take<F4>(n);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
     d.epart = c.take<double>((size_t)s.nchunk * 9);
+    d.vpart = c.take<double>((size_t)s.nchunk * 8);
     const int64_t nblkp = (n + BLOCK - 1) / BLOCK;
     d.stage = c.take<int32_t>((size_t)nblkp * SMAX);
     d.scount = c.take<int32_t>(nblkp);
@@ -489,6 +516,7 @@ void swap_drift_buffers(rbc_ctx *h, bool launch) {
 rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     if (!any_live(h)) return RBC_OK;
     if (nsteps <= 0) return RBC_OK;
+    set_step_dt(h, dt);
     const bool graphs = h->graphs && !h->timing && ensure_graphs(h, dt);
     ensure_forces(h);
     const double skin = h->prm.skin;
@@ -577,6 +605,8 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
         if (periodic[a] && !(box[a] > 2.0 * search))
             return fail(h, RBC_ERR_INVALID_ARG, "periodic box length must exceed twice the largest cutoff plus skin");
     }
+    if (h->prm.vol_k > 0.0 && (periodic[0] || periodic[1] || periodic[2]))
+        return fail(h, RBC_ERR_INVALID_ARG, "the volume constraint needs open boundaries");
     HostSys &hs = h->sys[slot];
     // type histogram and bond topology are needed on the host: wait for the caller's
     // stream, which may still be producing the input arrays
@@ -920,6 +950,7 @@ static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
     {
         Scope sc(h);
+        if (!h->dprm.vol_on) launch_volume(h->L);   // V is reported with or without the constraint
         force_launch(h, 1, 0, 0.0);
         h->forces_valid = true;
         launch_reduce_energy(h->L);
@@ -933,6 +964,7 @@ static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
     out[3] = e[0] + e[2];
     out[4] = std::sqrt(e[3] * e[3] + e[4] * e[4] + e[5] * e[5]);
     out[5] = std::sqrt(e[6] * e[6] + e[7] * e[7] + e[8] * e[8]);
+    out[6] = h->h_ring[slot].volV;
     return RBC_OK;
 }
 

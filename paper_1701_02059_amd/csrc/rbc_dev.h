@@ -54,6 +54,13 @@ struct alignas(256) SysScal {
     int32_t gdim[3];
     int32_t gtot;
     double energy[9];                 // U, W, KE, sum F (3), sum r x F + tau (3)
+    // volume term, from the lipid sums of the current state
+    double volV;                      // V = a_L/3 sum (x_i - xbar).n_i
+    double vol0;                      // V0 (set at the first evaluation when no target is given)
+    double volkap;                    // dU_V/dV a_L/3: the volume force is -volkap (n_i - nbar)
+    double volU;                      // U_V
+    double xbar[3], nbar[3];          // lipid centroid and mean orientation
+    unsigned long long step;          // drifts done since loading: numbers the thermostat's draws
 };
 
 // One system (slot): sizes and device arrays.  Particle arrays are in cell-sorted
@@ -84,6 +91,7 @@ struct SysDev {
     int32_t *bstart, *bpart;                        // bonds by caller id (n+1, 2 nbond)
     double *br0;
     double *epart;                                  // per-chunk energy partials (nchunk x 9)
+    double *vpart;                                  // per-chunk lipid sums for the volume (nchunk x 8)
     int32_t *pairs;                                 // scratch for exporting the pair set
     int64_t pairs_cap;
     int32_t *stage, *scount;                        // per 256-particle block: staged slots (SMAX), count (-1: none)
@@ -109,7 +117,14 @@ struct DevParams {
     double inv_w;          // 1 / (r_c - r_min)
     double dudr_k;         // eps * zeta * pi / (r_c - r_min)
     int32_t zeta;
+    int32_t vol_on;        // harmonic volume constraint
+    double vol_k, vol_target, vol_a3;   // k_V, V0 (0: measured), a_L / 3
+    // thermostat: v <- c v + a (r - (2^32 - 1)/2) per component, r a Philox word
+    int32_t thermo_on;
+    uint32_t seed_lo, seed_hi;
     int32_t pad;
+    double ou_c, ou_a[3];  // translation: c = exp(-gamma dt), a per type
+    double ou_cr, ou_ar;   // lipid rotation
 };
 
 // Block -> system maps: off[s] = first block of system s, off[nsys] = total blocks.
@@ -233,6 +248,7 @@ void launch_kick_drift(const LaunchCtx &L, double dt);   // includes the per-sys
 void launch_drift_stats_swap(const LaunchCtx &L);         // statistics of a fused drift, then buffer swap
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt);
 void launch_reduce_energy(const LaunchCtx &L);
+void launch_volume(const LaunchCtx &L);                   // lipid sums -> V, volume force constants
 void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count);
 void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, int count);
 void launch_export_pairs(const LaunchCtx &L, int sys, int count);

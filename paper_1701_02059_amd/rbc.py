@@ -35,7 +35,9 @@ class RbcParams(C.Structure):
                 ("wca_sigma", C.c_double), ("k_bond", C.c_double), ("mass", C.c_double * 3),
                 ("inertia", C.c_double), ("cell_target", C.c_int32), ("update_every", C.c_int32),
                 ("skin", C.c_double), ("lloyd_iters", C.c_int32), ("precision", C.c_int32),
-                ("protein_cells", C.c_int32)]
+                ("protein_cells", C.c_int32),
+                ("vol_k", C.c_double), ("vol_target", C.c_double), ("lipid_area", C.c_double),
+                ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64)]
 
 
 class RbcError(RuntimeError):
@@ -112,6 +114,9 @@ def make_params(mp, precision: int = RBC_FP64) -> RbcParams:
     p.cell_target, p.update_every, p.skin = int(mp.cell_target), int(mp.update_every), float(mp.skin)
     p.lloyd_iters, p.precision = int(mp.lloyd_iters), int(precision)
     p.protein_cells = int(getattr(mp, "protein_cells", 0))
+    p.vol_k, p.vol_target = float(mp.vol_k), float(mp.vol_target)
+    p.lipid_area = float(mp.lipid_area)
+    p.kT, p.gamma, p.gamma_rot, p.seed = float(mp.kT), float(mp.gamma), float(mp.gamma_rot), int(mp.seed)
     return p
 
 
@@ -209,7 +214,7 @@ class Context:
         return out[:cnt.value]
 
     def energy(self) -> np.ndarray:
-        out = np.zeros(6)
+        out = np.zeros(7)
         _check(self._h, lib().rbc_energy(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
@@ -311,7 +316,7 @@ class Ensemble:
         return out
 
     def energy(self, slot: int) -> np.ndarray:
-        out = np.zeros(6)
+        out = np.zeros(7)
         _check(self._h, lib().rbc_ensemble_energy(self._h, int(slot), out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 

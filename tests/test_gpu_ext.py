@@ -1,0 +1,193 @@
+"""Harmonic volume constraint and Langevin thermostat, GPU path vs the FP64 oracle
+through the C ABI.
+
+The volume term (the Results section's whole-cell run keeps the cell's
+surface-to-volume ratio with one) is checked as a force at both precision
+bounds; the thermostat through FP64 trajectories against the oracle's (same
+Philox draws on both sides), call-chunking neutrality, batch independence and
+equipartition.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1701_02059_amd import inputs as I
+from tests.gpu_common import rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1701_02059_amd import rbc
+    rbc.lib()
+    return rbc
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return I.config("tiny")
+
+
+@pytest.fixture(scope="module")
+def ves():
+    return I.config("vesicle")
+
+
+def _ctx(R, mp, system, precision):
+    c = R.Context(mp, precision)
+    c.set_system(system)
+    return c
+
+
+def _with_volume(mp, system, k=5.0, ratio=0.95):
+    """Constraint constants and the target volume ratio * V(loaded state)."""
+    V = O.volume(O.make_ext(mp), system.x, system.n, system.type)
+    m = dataclasses.replace(mp, vol_k=k, vol_target=ratio * V)
+    return m, V
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_volume_forces(R, mp, ves, prec):
+    m, V = _with_volume(mp, ves)
+    p, e = O.params_for(ves, m), O.make_ext(m, m.vol_target)
+    F0, T0, U0, W0 = O.forces_ext(p, e, ves)
+    c = _ctx(R, m, ves, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
+    F, T = (to_np(a) for a in c.forces())
+    en = c.energy()
+    c.close()
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    lip = ves.type == 0
+    assert rel_err(F, F0) < tol and rel_err(T[lip], T0[lip]) < tol
+    assert en[0] == pytest.approx(U0, rel=tol)
+    assert en[6] == pytest.approx(V, rel=1e-12)
+    # the volume term alone is a visible share of the force
+    Fv = O.volume_forces(e, ves.x, ves.n, ves.type)[0]
+    assert np.sqrt((Fv ** 2).sum()) > 1e-3 * np.sqrt((F0 ** 2).sum())
+    # momentum and angular momentum are conserved with it
+    assert en[4] < 1e-9 * np.abs(F0).sum() and en[5] < 1e-9 * np.abs(np.cross(ves.x, F0)).sum()
+
+
+def test_volume_reported_without_constraint(R, mp):
+    s = I.config("rbc500k")
+    c = _ctx(R, mp, s, R.RBC_MIXED)
+    V = c.energy()[6]
+    c.close()
+    assert V == pytest.approx(O.volume(O.make_ext(mp), s.x, s.n, s.type), rel=1e-12)
+
+
+def _thermo(mp, **kw):
+    base = dict(kT=0.22, gamma=0.5, gamma_rot=0.8, seed=0x1234_5678_9abc)
+    base.update(kw)
+    return dataclasses.replace(mp, **base)
+
+
+def test_thermostat_and_volume_trajectory_fp64(R, mp, tiny):
+    """30 FP64 steps with the thermostat and the volume term against the oracle."""
+    m, V = _with_volume(_thermo(mp), tiny, k=5.0, ratio=0.97)
+    p, e = O.params_for(tiny, m), O.make_ext(m, m.vol_target)
+    x0, v0, n0, w0, en = O.vv_run_ext(p, e, tiny, 0.01, 30)
+    c = _ctx(R, m, tiny, R.RBC_FP64)
+    c.step(30, 0.01)
+    x, n, v, w = (to_np(t) for t in c.get_state())
+    E = c.energy()
+    c.close()
+    assert np.abs(x - x0).max() < 1e-9
+    assert np.abs(v - v0).max() < 1e-8
+    assert np.abs(n - n0).max() < 1e-9
+    assert np.abs(w - w0).max() < 1e-8
+    assert E[0] == pytest.approx(en[-1, 1], rel=1e-9)
+    assert E[2] == pytest.approx(en[-1, 0], rel=1e-9)
+    # the noise is really there: the same run without it ends elsewhere
+    x1 = O.vv_run_ext(p, O.make_ext(dataclasses.replace(m, gamma=0.0, gamma_rot=0.0), m.vol_target),
+                      tiny, 0.01, 30)[0]
+    assert np.abs(x1 - x0).max() > 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_thermostat_chunking_is_bitwise_neutral(R, mp, tiny, prec):
+    """rbc_step(40) equals 4 x rbc_step(10) and (1, 39) bit for bit: the device step
+    counter numbers the draws across calls."""
+    m, _ = _with_volume(_thermo(mp), tiny, k=5.0, ratio=0.97)
+    pr = R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED
+    outs = []
+    for split in ((40,), (10, 10, 10, 10), (1, 39)):
+        c = _ctx(R, m, tiny, pr)
+        for k in split:
+            c.step(k, 0.01)
+        outs.append([to_np(t) for t in c.get_state()])
+        c.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
+def test_thermostat_batch_independence_and_graphs(R, mp):
+    """A thermostatted system's trajectory is the same alone, in a batch that
+    changes around it, with and without graph replay."""
+    m = _thermo(mp)
+    systems = [I.build_request({"kind": "vesicle", "nL": 3000, "seed": 31}),
+               I.build_request({"kind": "patch", "nL": 2500, "seed": 32})]
+    e = R.Ensemble(m, R.RBC_MIXED, max_slots=4)
+    a = e.admit(systems[0])
+    e.step(50, 0.01)
+    ref = [to_np(t) for t in e.get_state(a)]
+    e.close()
+    for graphs in (True, False):
+        e = R.Ensemble(m, R.RBC_MIXED, max_slots=4)
+        e.set_graphs(graphs)
+        b = e.admit(systems[1])
+        e.step(7, 0.01)
+        a = e.admit(systems[0])
+        e.step(20, 0.01)
+        e.retire(b)
+        e.step(30, 0.01)
+        got = [to_np(t) for t in e.get_state(a)]
+        e.close()
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y)
+
+
+def test_thermostat_equipartition_mixed(R, mp, ves):
+    """From rest, 1,500 steps with the thermostat bring the kinetic energy to
+    kT per degree of freedom (3 per particle, 2 per lipid rotor)."""
+    m = _thermo(mp, gamma=1.0, gamma_rot=1.0, kT=0.22)
+    cold = dataclasses.replace(ves, v=np.zeros_like(ves.v), w=np.zeros_like(ves.w))
+    c = _ctx(R, m, cold, R.RBC_MIXED)
+    kes = []
+    for _ in range(10):
+        c.step(150, 0.01)
+        kes.append(c.energy()[2])
+    c.close()
+    nl = int(np.sum(ves.type == 0))
+    dof = 3 * ves.N + 2 * nl
+    ke = np.mean(kes[5:])
+    assert ke == pytest.approx(0.5 * dof * m.kT, rel=0.03), (kes, 0.5 * dof * m.kT)
+
+
+@pytest.mark.parametrize("ratio", [0.99, 1.01])
+def test_volume_constraint_pulls_towards_target(R, mp, tiny, ratio):
+    """With damping, the volume moves from V(0) towards a target 1% smaller or larger."""
+    m, V = _with_volume(_thermo(mp, kT=0.05, gamma=1.0, gamma_rot=1.0), tiny, k=100.0, ratio=ratio)
+    c = _ctx(R, m, tiny, R.RBC_FP64)
+    c.step(2000, 0.01)
+    Vend = c.energy()[6]
+    c.close()
+    gap = m.vol_target - V
+    assert (Vend - V) / gap > 0.2, (V, Vend, m.vol_target)
+
+
+def test_volume_constraint_rejects_periodic(R, mp):
+    s = I.config("patch")
+    c = R.Context(dataclasses.replace(mp, vol_k=1.0), R.RBC_FP64)
+    with pytest.raises(R.RbcError) as ei:
+        c.set_system(s)
+    assert ei.value.status == R.RBC_ERR_INVALID_ARG
+    c.close()
