@@ -208,6 +208,24 @@ __device__ __forceinline__ void drift_measures(const D4 &x, const D4 &v, const D
     bad = !isfinite(x.x + x.y + x.z + v.x + v.y + v.z);
 }
 
+// The volume's lipid sums of one particle (x.n, x, n, 1; zero for proteins) and
+// their per-chunk totals, a fixed butterfly over the wavefront stored
+// component-major at vpart[q * nchunk + chunk].  The drift computes them for the
+// positions it writes, so the next force evaluation needs only the reduction.
+__device__ __forceinline__ void volume_terms(const D4 &x, const D4 &n, double v[8]) {
+#pragma clang fp contract(off)
+    v[0] = x.x * n.x + x.y * n.y + x.z * n.z;
+    v[1] = x.x; v[2] = x.y; v[3] = x.z;
+    v[4] = n.x; v[5] = n.y; v[6] = n.z;
+    v[7] = 1.0;
+}
+
+__device__ __forceinline__ void volume_chunk_store(const SysDev &S, int chunk, double v[8]) {
+    for (int q = 0; q < 8; ++q) v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        for (int q = 0; q < 8; ++q) S.vpart[(size_t)q * S.nchunk + chunk] = v[q];
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two 32 x 32
 // -> 64-bit products mixed with the other words and the key, which advances by
 // the Weyl constants between rounds.
@@ -455,6 +473,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     double disp2 = 0.0, vmax2 = 0.0;
     bool bad = false;
     D4 Tq = {(double)tx, (double)ty, (double)tz, 0.0};
+    double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (valid) {
         // bonds of this particle (CSR by caller id), FP64 in both modes
         const int g = S.gid[i];
@@ -505,10 +524,14 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
                 S.ori2[i] = on;
                 S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
                 drift_measures(xn, vn, S.xb[i], disp2, vmax2, bad);
+                if (P.vol_on && ti == 0) volume_terms(xn, on, vsum);
             }
         }
     }
-    if (KICK == 2) drift_stats(S, lb, disp2, vmax2, bad);
+    if (KICK == 2) {
+        drift_stats(S, lb, disp2, vmax2, bad);
+        if (P.vol_on) volume_chunk_store(S, chunk, vsum);
+    }
     if (ENERGY) {
         // per-chunk partials of U, W, KE, sum F and sum (r x F + tau), reduced across
         // the wavefront in a fixed butterfly (deterministic)
@@ -545,7 +568,7 @@ static void launch_force_t(const LaunchCtx &L, double dt) {
 }
 
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt) {
-    if (L.prm.vol_on) launch_volume(L);   // the volume force needs V of the current state
+    if (L.prm.vol_on) launch_volume_reduce(L);   // V of the current state from its lipid sums
     if (kick == 2) {
         if (mixed) launch_force_t<1, 0, 2>(L, dt);
         else launch_force_t<0, 0, 2>(L, dt);
@@ -576,6 +599,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
     const int i = lb * BLOCK + threadIdx.x;
     double disp2 = 0.0, v2 = 0.0;
     bool bad = false;
+    double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
         D4 p = S.pos[i], v = S.vel[i];
         const D4 f = S.frc[i];
@@ -594,10 +618,12 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
             S.angv[i] = w;
             S.ori[i] = n;
             S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
+            if (P.vol_on) volume_terms(p, n, vsum);
         }
         drift_measures(p, v, S.xb[i], disp2, v2, bad);
     }
     drift_stats(S, lb, disp2, v2, bad);
+    if (P.vol_on && i / CHUNK < S.nchunk) volume_chunk_store(S, i / CHUNK, vsum);
 }
 
 // Largest displacement since the last build and largest drift speed, per system,
@@ -677,48 +703,57 @@ void launch_reduce_energy(const LaunchCtx &L) {
 
 // ------------------------------------------------------------------ volume
 
-// Per-chunk lipid sums x.n, x, n and the lipid count, reduced across the
-// wavefront in a fixed butterfly (deterministic).
+// The lipid sums per chunk of the current state, for force evaluations that no
+// drift precedes (a freshly loaded system).
 __global__ __launch_bounds__(BLOCK) void k_volume_partials(const SysDev *Sd, Maps L_maps) {
     const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
     const SysDev &S = Sd[s];
     const int lb = blockIdx.x - L_maps.p[s];
     const int i = lb * BLOCK + threadIdx.x;
-    const int chunk = i / CHUNK;
-    if (chunk >= S.nchunk) return;
-    double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i / CHUNK >= S.nchunk) return;           // whole wavefronts past the last chunk
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
         const D4 p = S.pos[i];
-        if (p.w == 0.0) {
-            const D4 n = S.ori[i];
-            vals[0] = p.x * n.x + p.y * n.y + p.z * n.z;
-            vals[1] = p.x; vals[2] = p.y; vals[3] = p.z;
-            vals[4] = n.x; vals[5] = n.y; vals[6] = n.z;
-            vals[7] = 1.0;
-        }
+        if (p.w == 0.0) volume_terms(p, S.ori[i], v);
     }
-    for (int q = 0; q < 8; ++q) vals[q] = wave_sum(vals[q]);
-    if ((threadIdx.x & (WAVE - 1)) == 0)
-        for (int q = 0; q < 8; ++q) S.vpart[(size_t)chunk * 8 + q] = vals[q];
+    volume_chunk_store(S, i / CHUNK, v);
 }
 
-// Fixed-order sum of the chunk sums (one block per system), then
-// V = a_L/3 (sum x.n - (sum x).(sum n) / N_L), U_V = k_V/2 (V - V0)^2 / V0 and the
-// force constant dU_V/dV a_L/3.  V0 is the given target, else the first V measured.
-__global__ __launch_bounds__(256) void k_volume_reduce(const SysDev *Sd, int nsys, DevParams P) {
-    const SysDev &S = Sd[blockIdx.x];
+// Two fixed-order levels: VR1 blocks per system each sum a contiguous range of
+// chunk totals into vred[b * 8 + q]; one block per system then sums those and
+// derives V = a_L/3 (sum x.n - (sum x).(sum n) / N_L), U_V = k_V/2 (V - V0)^2 / V0
+// and the force constant dU_V/dV a_L/3.  V0 is the given target, else the first V.
+constexpr int VR1 = 32;
+
+__global__ __launch_bounds__(256) void k_volume_reduce1(const SysDev *Sd, int nsys) {
+    const SysDev &S = Sd[blockIdx.x / VR1];
+    const int part = blockIdx.x % VR1;
+    const int per = (S.nchunk + VR1 - 1) / VR1;
+    const int c0 = part * per, c1 = min(S.nchunk, c0 + per);
     __shared__ double sh[8][4];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int c = threadIdx.x; c < S.nchunk; c += blockDim.x)
-        for (int q = 0; q < 8; ++q) acc[q] += S.vpart[(size_t)c * 8 + q];
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += 256)
+        for (int q = 0; q < 8; ++q) acc[q] += S.vpart[(size_t)q * S.nchunk + c];
     for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0)
         for (int q = 0; q < 8; ++q) sh[q][w] = acc[q];
     __syncthreads();
+    if (threadIdx.x < 8 && S.n > 0) {
+        const int q = threadIdx.x;
+        S.vred[part * 8 + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_volume_reduce2(const SysDev *Sd, int nsys, DevParams P) {
+    const SysDev &S = Sd[blockIdx.x];
     if (threadIdx.x != 0 || S.n == 0) return;
     double t[8];
-    for (int q = 0; q < 8; ++q) t[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    for (int q = 0; q < 8; ++q) {
+        double a = 0.0;
+        for (int b = 0; b < VR1; ++b) a += S.vred[b * 8 + q];
+        t[q] = a;
+    }
     SysScal *sc = S.sc;
     const double cnt = t[7];
     if (cnt == 0.0) {
@@ -740,9 +775,13 @@ __global__ __launch_bounds__(256) void k_volume_reduce(const SysDev *Sd, int nsy
     }
 }
 
-void launch_volume(const LaunchCtx &L) {
+void launch_volume_partials(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_volume_partials, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_volume_reduce, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys, L.prm);
+}
+
+void launch_volume_reduce(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_volume_reduce1, dim3(L.nsys * VR1), dim3(256), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_volume_reduce2, dim3(L.nsys), dim3(64), 0, L.st, L.S, L.nsys, L.prm);
 }
 
 // ------------------------------------------------------------------ outputs in caller order

@@ -81,6 +81,7 @@ struct rbc_ctx {
     LaunchCtx L{};
     int32_t nsys = 0;                 // descriptors in use (highest live slot + 1)
     bool forces_valid = false;
+    bool vol_fresh = false;          // the per-chunk lipid sums describe the current state of every system
     int sticky = RBC_OK;
     std::string err;
     int64_t ens_steps = 0;
@@ -235,6 +236,7 @@ size_t layout(HostSys &s, char *base) {
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
     d.epart = c.take<double>((size_t)s.nchunk * 9);
     d.vpart = c.take<double>((size_t)s.nchunk * 8);
+    d.vred = c.take<double>(32 * 8);
     const int64_t nblkp = (n + BLOCK - 1) / BLOCK;
     d.stage = c.take<int32_t>((size_t)nblkp * SMAX);
     d.scount = c.take<int32_t>(nblkp);
@@ -429,6 +431,10 @@ rbc_status sync_and_check(rbc_ctx *h) {
 }
 
 void force_launch(rbc_ctx *h, int energy, int kick, double dt) {
+    if (h->dprm.vol_on && !h->vol_fresh) {
+        launch_volume_partials(h->L);   // no drift has produced them since loading
+        h->vol_fresh = true;
+    }
     const bool t = h->timing && h->tcount < (int)h->tb.size();
     if (t) hipEventRecord(h->tb[h->tcount], h->st);
     launch_force(h->L, h->prm.precision == RBC_MIXED, energy, kick, dt);
@@ -523,6 +529,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     const int64_t K = h->prm.update_every;
     rbc_status out = RBC_OK;
     launch_kick_drift(h->L, dt);
+    h->vol_fresh = true;              // every drift also writes the volume's lipid sums
     for (int64_t st = 0; st < nsteps; ++st) {
         const bool last = st + 1 == nsteps;
         const int slot = (int)(h->ring_pos % RING);
@@ -685,6 +692,7 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
     SysScal zero{};
     HIPCHK(hipMemcpy(h->d_sc + slot, &zero, sizeof(SysScal), hipMemcpyHostToDevice));
     hs = fresh;
+    h->vol_fresh = false;
     h->used += (int64_t)bytes;
     rbc_status r = refresh_tables(h);
     if (r != RBC_OK) return r;
@@ -950,7 +958,10 @@ static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
     {
         Scope sc(h);
-        if (!h->dprm.vol_on) launch_volume(h->L);   // V is reported with or without the constraint
+        if (!h->dprm.vol_on) {                        // V is reported with or without the constraint
+            launch_volume_partials(h->L);
+            launch_volume_reduce(h->L);
+        }
         force_launch(h, 1, 0, 0.0);
         h->forces_valid = true;
         launch_reduce_energy(h->L);

@@ -91,7 +91,8 @@ struct SysDev {
     int32_t *bstart, *bpart;                        // bonds by caller id (n+1, 2 nbond)
     double *br0;
     double *epart;                                  // per-chunk energy partials (nchunk x 9)
-    double *vpart;                                  // per-chunk lipid sums for the volume (nchunk x 8)
+    double *vpart;                                  // per-chunk lipid sums for the volume (8 x nchunk)
+    double *vred;                                   // their first-level reduction (32 x 8)
     int32_t *pairs;                                 // scratch for exporting the pair set
     int64_t pairs_cap;
     int32_t *stage, *scount;                        // per 256-particle block: staged slots (SMAX), count (-1: none)
@@ -248,7 +249,8 @@ void launch_kick_drift(const LaunchCtx &L, double dt);   // includes the per-sys
 void launch_drift_stats_swap(const LaunchCtx &L);         // statistics of a fused drift, then buffer swap
 void launch_force(const LaunchCtx &L, int mixed, int energy, int kick, double dt);
 void launch_reduce_energy(const LaunchCtx &L);
-void launch_volume(const LaunchCtx &L);                   // lipid sums -> V, volume force constants
+void launch_volume_partials(const LaunchCtx &L);          // lipid sums of the current state, per chunk
+void launch_volume_reduce(const LaunchCtx &L);            // lipid sums -> V, volume force constants
 void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count);
 void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, int count);
 void launch_export_pairs(const LaunchCtx &L, int sys, int count);
