@@ -308,10 +308,15 @@ __device__ __forceinline__ void drift_stats(const SysDev &S, int blk, double dis
 
 // LDS stage per 256-particle block (structure of arrays): FP64 positions, and either
 // FP32 orientations with the type in w (mixed) or FP64 orientations and a type byte.
+// Mixed mode holds the first 800 stage entries (32 KB: five blocks per CU, the
+// occupancy its register count allows) and reads any further ones from global
+// memory; FP64 mode, limited to three blocks per CU by registers, holds all SMAX.
 template <int MIXED>
-struct StageBytes {
-    static constexpr int value = MIXED ? SMAX * (3 * 8 + 16) : SMAX * (6 * 8 + 1);
+struct Stage {
+    static constexpr int lds = MIXED ? 800 : SMAX;
+    static constexpr int bytes = MIXED ? lds * (3 * 8 + 16) : lds * (6 * 8 + 1);
 };
+static_assert(Stage<1>::lds <= SMAX && (Stage<1>::lds * 24) % 16 == 0, "mixed stage layout");
 
 // One workgroup per 256 consecutive cell-sorted particles.  The block's partners
 // (its stage list) are read once from HBM into LDS; lane i then walks column i of
@@ -325,13 +330,14 @@ struct StageBytes {
 template <int MIXED, int ENERGY, int KICK, int FAST>
 __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     using T = typename std::conditional<MIXED, float, double>::type;
-    __shared__ __align__(16) unsigned char s_raw[StageBytes<MIXED>::value];
+    constexpr int SL = Stage<MIXED>::lds;
+    __shared__ __align__(16) unsigned char s_raw[Stage<MIXED>::bytes];
     double *s_x = reinterpret_cast<double *>(s_raw);
-    double *s_y = s_x + SMAX;
-    double *s_z = s_y + SMAX;
-    F4 *s_n4 = reinterpret_cast<F4 *>(s_z + SMAX);                // mixed
-    double *s_nx = s_z + SMAX, *s_ny = s_nx + SMAX, *s_nz = s_ny + SMAX;   // FP64
-    unsigned char *s_t = reinterpret_cast<unsigned char *>(s_nz + SMAX);   // FP64
+    double *s_y = s_x + SL;
+    double *s_z = s_y + SL;
+    F4 *s_n4 = reinterpret_cast<F4 *>(s_z + SL);                  // mixed
+    double *s_nx = s_z + SL, *s_ny = s_nx + SL, *s_nz = s_ny + SL;        // FP64
+    unsigned char *s_t = reinterpret_cast<unsigned char *>(s_nz + SL);    // FP64
     const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
     const SysDev &S = Sd[s];
     const int lb = blockIdx.x - L_maps.p[s];
@@ -341,7 +347,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     const int i = lb * BLOCK + tid;
     const bool valid = i < S.n;
     const int scnt = S.scount[lb];
-    for (int q = tid; q < scnt; q += BLOCK) {
+    const int nlds = min(scnt, SL);                 // stage entries held in LDS
+    for (int q = tid; q < nlds; q += BLOCK) {
         const int slot = ldg(S.stage + (size_t)lb * SMAX + q);
         const D4 p = ldg(S.pos + slot);
         s_x[q] = p.x;
@@ -376,8 +383,9 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     // dynamic indexing; the periodic min-image only where the system has periodic axes
     const double rcA = P.rc2[ti][0], rcB = P.rc2[ti][1], rcC = P.rc2[ti][2];
     const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
-    auto staged_rows = [&](auto per_tag) {
+    auto staged_rows = [&](auto per_tag, auto part_tag) {
         constexpr bool PER = decltype(per_tag)::value;
+        constexpr bool PARTIAL = decltype(part_tag)::value;   // stage entries beyond the LDS part
         // Software pipeline: the list entry of row r+2 is fetched from global memory and
         // the stage record of row r+1 from LDS while row r is evaluated.
         const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
@@ -389,8 +397,19 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
             int t;
         };
         auto fetch = [&](int e) {
-            const int q = e < scnt ? e : 0;             // in-bounds dummy for padding entries
             Rec c;
+            if constexpr (PARTIAL) {
+                if (e >= nlds && e < scnt) {            // stage entry beyond the LDS part
+                    const int slot = ldg(S.stage + (size_t)lb * SMAX + e);
+                    const D4 p = ldg(S.pos + slot);
+                    const F4 o = ldg(S.ori32 + slot);
+                    c.x = p.x; c.y = p.y; c.z = p.z;
+                    c.nx = o.x; c.ny = o.y; c.nz = o.z;
+                    c.t = (int)p.w;
+                    return c;
+                }
+            }
+            const int q = e < nlds ? e : 0;             // in-bounds dummy for padding entries
             c.x = s_x[q];
             c.y = s_y[q];
             c.z = s_z[q];
@@ -437,8 +456,15 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
         }
     };
     if (scnt >= 0) {
-        if (periodic) staged_rows(std::true_type{});
-        else staged_rows(std::false_type{});
+        // block-uniform choices: periodic min-image, and (mixed mode) whether the stage
+        // overflows the LDS part, so ordinary blocks carry no per-entry test
+        if (SL < SMAX && scnt > SL) {
+            if (periodic) staged_rows(std::true_type{}, std::integral_constant<bool, SL < SMAX>{});
+            else staged_rows(std::false_type{}, std::integral_constant<bool, SL < SMAX>{});
+        } else {
+            if (periodic) staged_rows(std::true_type{}, std::false_type{});
+            else staged_rows(std::false_type{}, std::false_type{});
+        }
     } else {
         // block whose partners did not fit the stage: the lists hold global slots
         const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
