@@ -15,6 +15,7 @@ One JSON line on stdout; progress on stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -93,10 +94,13 @@ def timed_run(R, mp, system, precision, steps, warmup, label):
     out = {"seconds": t1 - t0, "ms_per_step": (t1 - t0) * 1e3 / steps,
            "particle_steps_per_s": system.N * steps / (t1 - t0),
            "force_ms": avg_ms, "force_launches": launches,
-           "cell_updates": st1["updates"] - st0["updates"], "early_updates": st1["early_updates"] - st0["early_updates"],
+           "cell_updates": st1["cell_updates"] - st0["cell_updates"],
+           "list_rebuilds": st1["rebuilds"] - st0["rebuilds"],
+           "early_rebuilds": st1["early_rebuilds"] - st0["early_rebuilds"],
            "max_list_rows": st1["max_list_rows"], "energy": e.tolist()}
     log(f"[{label}] {steps} steps in {t1 - t0:.3f} s -> {out['particle_steps_per_s']:.4g} particle-steps/s, "
-        f"force kernel {avg_ms * 1e3:.1f} us avg over {launches} launches, {out['cell_updates']} cell updates")
+        f"force kernel {avg_ms * 1e3:.1f} us avg over {launches} launches, {out['cell_updates']} cell updates, "
+        f"{out['list_rebuilds']} list builds")
     return ctx, out
 
 
@@ -132,6 +136,39 @@ def cpu_baseline(system, mp):
                                    f"{spent1:.1f} s)"}}
 
 
+def detached_run(R, mp, workload, steps, warmup):
+    """The same cell with its cytoskeleton detached (3 sigma under the sheet, every
+    second junction tethered): mixed-precision throughput with a separate protein
+    cell set and with the proteins sharing the lipids' cells."""
+    from paper_1701_02059_amd import inputs as I
+    name = f"{workload}_detached"
+    system = I.config(name)
+    out = {"workload": name, "particles": system.N}
+    for key, pc in (("separate_cells", 1), ("shared_cells", 0)):
+        m = dataclasses.replace(mp, protein_cells=pc)
+        try:
+            ctx, r = timed_run(R, m, system, R.RBC_MIXED, steps, warmup, f"detached {key}")
+            st = ctx.stats()
+            ctx.close()
+            r.update(cells=st["cells"], lipid_cells=st["lipid_cells"], max_cell_pairs=st["max_cell_pairs"])
+            r.pop("energy", None)
+        except R.RbcError as e:
+            r = {"error": str(e)}
+        out[key] = r
+    return out
+
+
+def ext_run(R, mp, system, steps, warmup):
+    """The same cell with the harmonic volume constraint (V0 = the loaded volume) and
+    the Langevin thermostat on translations and lipid rotations."""
+    m = dataclasses.replace(mp, vol_k=10.0, vol_target=0.0, kT=0.22, gamma=1.0, gamma_rot=1.0, seed=1)
+    ctx, r = timed_run(R, m, system, R.RBC_MIXED, steps, warmup, "volume+thermostat")
+    ctx.close()
+    r.pop("energy", None)
+    r["settings"] = {"vol_k": m.vol_k, "gamma": m.gamma, "gamma_rot": m.gamma_rot, "kT": m.kT}
+    return r
+
+
 def serving_run(R, mp, count, rate, steps, saturated=False):
     from paper_1701_02059_amd import inputs as I
     from paper_1701_02059_amd import serving as SV
@@ -161,6 +198,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-detached", action="store_true")
+    ap.add_argument("--no-ext", action="store_true")
+    ap.add_argument("--detached-steps", type=int, default=500)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
     ap.add_argument("--skin", type=float, default=0.5,
@@ -222,6 +262,14 @@ def main():
         fp64["force_tflops"] = flops / (fp64["force_ms"] * 1e-3) / 1e12
         fp64["force_frac_fp64_peak"] = fp64["force_tflops"] / PEAK_FP64
 
+    ext = None
+    if not args.no_ext:
+        ext = ext_run(R, mp, system, args.detached_steps, min(args.warmup, 20))
+
+    detached = None
+    if not args.no_detached:
+        detached = detached_run(R, mp, args.workload, args.detached_steps, min(args.warmup, 20))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(system, mp)
@@ -265,6 +313,8 @@ def main():
         "fp64": fp64,
         "mixed": mixed,
         "serving": serving,
+        "detached": detached,
+        "volume_and_thermostat": ext,
     }
     print(json.dumps(line))
 

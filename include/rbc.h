@@ -154,10 +154,13 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
  * volume V of the lipid surface (as defined for the volume constraint). */
 rbc_status rbc_energy(rbc_handle h, double *out);
 
-/* Counters (sync).  [host] out[9]: steps done, cell updates, early (skin)
- * updates, cells k, max neighbour-list rows, max cell-pair row, particles n,
- * lipids, lipid cells (cells [0, out[8]) hold lipids; with protein_cells set,
- * cells [out[8], k) hold the protein beads; otherwise out[8] == k). */
+/* Counters (sync).  [host] out[10]: steps done, neighbour-list builds (all
+ * kinds), list-only rebuilds (the skin ran out between cell updates), cells k,
+ * max neighbour-list rows, max cell-pair row, particles n, lipids, lipid cells
+ * (cells [0, out[8]) hold lipids; with protein_cells set, cells [out[8], k)
+ * hold the protein beads; otherwise out[8] == k), and Voronoi cell updates
+ * (the initial build included; every params.update_every steps, each also
+ * rebuilding the lists). */
 rbc_status rbc_stats(rbc_handle h, int64_t *out);
 
 /* Cell structure for inspection (sync).  [host] owner: n ints, the cell of

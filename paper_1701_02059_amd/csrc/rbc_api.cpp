@@ -41,7 +41,10 @@ struct HostSys {
     int64_t pairs_cap = 0;
     SysDev dev{};
     int32_t *lip = nullptr;          // device: lipid ids in id order, then protein ids (the seed lists)
-    int64_t steps_since = 0, steps_total = 0, updates = 0, early = 0;
+    int64_t steps_since = 0, steps_total = 0;
+    int64_t updates = 0;             // Voronoi cell updates (each also rebuilds the lists)
+    int64_t rebuilds = 0;            // neighbour-list builds of any kind
+    int64_t early = 0;               // list-only rebuilds forced by the skin between cell updates
     bool have_stats = false, rebuilt_last = false;
     double disp2 = 0.0, v2 = 0.0;
 };
@@ -337,21 +340,16 @@ bool any_live(const rbc_ctx *h) {
 }
 
 void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd);
+void lists_body(const LaunchCtx &L);
 
-// Run the cell update for the systems in `mask`.  lloyd > 0: seed from lipids and
-// run that many k-means iterations first.
-void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
-    if (which.empty()) return;
+// Launch context whose block maps cover only the systems in `which`, with their
+// rebuild flags set: the device builds the restricted prefix maps from the flags,
+// the host sums the same block counts for the grid sizes.
+LaunchCtx restricted(rbc_ctx *h, const std::vector<int> &which) {
     unsigned long long m[4] = {0, 0, 0, 0};
-    int32_t kmax = 1;
-    for (int s : which) {
-        m[s >> 6] |= 1ull << (s & 63);
-        kmax = std::max(kmax, h->sys[s].k);
-    }
+    for (int s : which) m[s >> 6] |= 1ull << (s & 63);
     const LaunchCtx &L = h->L;
     launch_set_rebuild(L, m);
-    // launch only the rebuilding systems' blocks: the device builds their prefix maps
-    // from the rebuild flags, the host sums the same block counts for the grid sizes
     launch_restrict_maps(L, h->d_umaps);
     LaunchCtx U = L;
     const int ns = h->nsys;
@@ -373,12 +371,32 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
         U.nblk_sc += (hs.k + SCAN_TILE - 1) / SCAN_TILE;
         U.nblk_sg += (hs.gcap + SCAN_TILE - 1) / SCAN_TILE;
     }
+    return U;
+}
+
+// Run the cell update for the systems in `which`.  lloyd > 0: seed from lipids and
+// run that many k-means iterations first.
+void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
+    if (which.empty()) return;
+    int32_t kmax = 1;
+    for (int s : which) kmax = std::max(kmax, h->sys[s].k);
+    const LaunchCtx U = restricted(h, which);
     update_body(h, U, key_bits(kmax), lloyd);
     for (int s : which) {
         HostSys &hs = h->sys[s];
         hs.updates++;
+        hs.rebuilds++;
         hs.steps_since = 0;
     }
+}
+
+// Rebuild only the neighbour lists of the systems in `which`, on their current
+// cells: particles keep their cells, whose radii grow to the members' current
+// distances, so the cell pairs and the lists stay complete.
+void run_lists(rbc_ctx *h, const std::vector<int> &which) {
+    if (which.empty()) return;
+    lists_body(restricted(h, which));
+    for (int s : which) h->sys[s].rebuilds++;
 }
 
 // The cell-update launches for the systems whose rebuild flag is set (L carries
@@ -404,6 +422,11 @@ void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd) {
     launch_morton_sort_seeds(L);
     launch_block_permute(L);
     launch_grid_build(L);
+    lists_body(L);
+}
+
+// Cell radii, cell pairs and neighbour lists on the current cells.
+void lists_body(const LaunchCtx &L) {
     launch_cell_bounds(L);
     launch_cell_pairs(L);
     launch_nlist(L);
@@ -537,23 +560,29 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         SysScal *ring = h->h_ring + (size_t)slot * MAX_SLOTS;
         hipMemcpyAsync(ring, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st);
         hipEventRecord(h->ring_ev[slot], h->st);
-        // decide which systems update before this step's force, from the previous step's statistics
-        std::vector<int> which;
+        // decide, from the previous step's statistics, which systems update their cells
+        // (every K steps) and which only rebuild their lists (the skin is running out)
+        std::vector<int> which, full, lists;
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
             if (!hs.live) continue;
             hs.steps_since++;
-            bool need = hs.steps_since >= K;
-            if (!need && hs.have_stats) {
+            if (hs.steps_since >= K) {
+                full.push_back(s);
+                which.push_back(s);
+                continue;
+            }
+            if (hs.have_stats) {
                 double pred = (hs.rebuilt_last ? 0.0 : std::sqrt(hs.disp2)) + 2.0 * dt * std::sqrt(hs.v2);
                 if (pred > 0.9 * skin) {
-                    need = true;
                     hs.early++;
+                    lists.push_back(s);
+                    which.push_back(s);
                 }
             }
-            if (need) which.push_back(s);
         }
-        run_update(h, which, 0);
+        run_update(h, full, 0);
+        run_lists(h, lists);
         if (graphs) {
             hipGraphLaunch(last ? h->g_last : h->g_step, h->st);
             if (!last) swap_drift_buffers(h, false);
@@ -703,6 +732,7 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
         hs.steps_since = 0;
         hs.have_stats = false;
         hs.updates = 1;
+        hs.rebuilds = 1;
         h->forces_valid = false;
     }
     rbc_status st = sync_and_check(h);
@@ -996,7 +1026,7 @@ rbc_status rbc_stats(rbc_handle h, int64_t *out) {
     rbc_status r = sync_and_check(h);
     if (r != RBC_OK) return r;
     out[0] = hs.steps_total;
-    out[1] = hs.updates;
+    out[1] = hs.rebuilds;
     out[2] = hs.early;
     out[3] = hs.k;
     out[4] = h->h_ring[0].nlrows;
@@ -1004,6 +1034,7 @@ rbc_status rbc_stats(rbc_handle h, int64_t *out) {
     out[6] = hs.n;
     out[7] = hs.nlip;
     out[8] = hs.kl;
+    out[9] = hs.updates;
     return RBC_OK;
 }
 

@@ -219,10 +219,10 @@ class Context:
         return out
 
     def stats(self) -> dict:
-        out = np.zeros(9, dtype=np.int64)
+        out = np.zeros(10, dtype=np.int64)
         _check(self._h, lib().rbc_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))))
-        keys = ["steps", "updates", "early_updates", "cells", "max_list_rows", "max_cell_pairs", "n", "lipids",
-                "lipid_cells"]
+        keys = ["steps", "rebuilds", "early_rebuilds", "cells", "max_list_rows", "max_cell_pairs", "n", "lipids",
+                "lipid_cells", "cell_updates"]
         return dict(zip(keys, (int(v) for v in out)))
 
     def cells(self):

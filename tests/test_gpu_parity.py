@@ -163,7 +163,7 @@ def test_nve_conservation_vesicle(R, mp, ves):
     drift = max(abs(e - e0) for e in es) / ves.N
     assert drift < 2e-3, drift       # per particle, 200 steps of dt = 0.01
     st = c.stats()
-    assert st["steps"] == 200 and st["updates"] >= 2
+    assert st["steps"] == 200 and st["cell_updates"] == 3 and st["rebuilds"] >= 3, st
     c.close()
 
 
@@ -203,7 +203,7 @@ def test_step_chunking_is_bitwise_neutral(R, mp, ves, prec, name):
         c = _ctx(R, mp, s, pr)
         for k in split:
             c.step(k, 0.01)
-        outs.append([to_np(t) for t in c.get_state()] + [c.stats()["updates"]])
+        outs.append([to_np(t) for t in c.get_state()] + [c.stats()["rebuilds"], c.stats()["cell_updates"]])
         c.close()
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
