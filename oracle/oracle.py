@@ -57,7 +57,8 @@ def params_for(system, mp) -> OrcParams:
 
 class OrcExt(C.Structure):
     _fields_ = [("vol_k", C.c_double), ("vol_target", C.c_double), ("lipid_area", C.c_double),
-                ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64)]
+                ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64),
+                ("quench_max", C.c_double), ("quench", C.c_int32), ("pad", C.c_int32)]
 
 
 def make_ext(mp, vol_target=0.0) -> OrcExt:
@@ -65,6 +66,7 @@ def make_ext(mp, vol_target=0.0) -> OrcExt:
     e = OrcExt()
     e.vol_k, e.vol_target, e.lipid_area = float(mp.vol_k), float(vol_target), float(mp.lipid_area)
     e.kT, e.gamma, e.gamma_rot, e.seed = float(mp.kT), float(mp.gamma), float(mp.gamma_rot), int(mp.seed)
+    e.quench, e.quench_max = int(mp.quench), float(mp.quench_max)
     return e
 
 
@@ -103,6 +105,8 @@ def lib():
             "orc_volume_forces": (C.c_double, [ep, C.c_int64, dp, dp, ip, dp, dp]),
             "orc_forces_ext": (C.c_int, [pp, ep, C.c_int64, dp, dp, ip, C.c_int64, ip, dp, dp, dp, dp, C.c_int]),
             "orc_langevin_step": (None, [pp, ep, C.c_int64, ip, dp, C.c_double, C.c_uint64, dp, dp]),
+            "orc_quench_project": (None, [pp, C.c_int64, ip, dp, dp, dp, dp]),
+            "orc_quench_cap": (None, [ep, C.c_int64, ip, C.c_double, dp, dp]),
             "orc_vv_run_ext": (C.c_int, [pp, ep, C.c_uint64, C.c_int64, dp, dp, dp, dp, ip, C.c_int64, ip, dp,
                                          C.c_double, C.c_int64, dp, C.c_int]),
         }
@@ -437,3 +441,22 @@ def vv_run_ext(p, e, system, dt, nsteps, step0=0, nthreads=0):
     lib().orc_vv_run_ext(C.byref(p), C.byref(e), int(step0), x.shape[0], dp(x), dp(v), dp(nrm), dp(w), tp,
                          b.shape[0], bp, r0p, float(dt), int(nsteps), dp(en), nthreads)
     return x, v, nrm, w, en
+
+
+def quench_project(p, typ, F, T, v, w):
+    """The quench projection on copies of v and w; returns (v, w)."""
+    typ, tp = _i(typ)
+    F, Fp = _d(F)
+    T, Tp = _d(T)
+    v = np.array(v, dtype=np.float64, copy=True)
+    w = np.array(w, dtype=np.float64, copy=True)
+    lib().orc_quench_project(C.byref(p), typ.shape[0], tp, Fp, Tp, _d(v)[1], _d(w)[1])
+    return v, w
+
+
+def quench_cap(e, typ, dt, v, w):
+    typ, tp = _i(typ)
+    v = np.array(v, dtype=np.float64, copy=True)
+    w = np.array(w, dtype=np.float64, copy=True)
+    lib().orc_quench_cap(C.byref(e), typ.shape[0], tp, float(dt), _d(v)[1], _d(w)[1])
+    return v, w

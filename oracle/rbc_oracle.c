@@ -654,6 +654,43 @@ void orc_langevin_step(const orc_params *p, const orc_ext *e, int64_t n, const i
     }
 }
 
+/* Keep the part of a along b when it points along b: a <- max(a.b, 0) b / |b|^2. */
+static void project_along(double *a, const double *b) {
+    const double bb = dot3(b, b);
+    const double ab = dot3(a, b);
+    if (bb > 0.0 && ab > 0.0) {
+        const double s = ab / bb;
+        for (int k = 0; k < 3; ++k) a[k] = s * b[k];
+    } else {
+        for (int k = 0; k < 3; ++k) a[k] = 0.0;
+    }
+}
+
+void orc_quench_project(const orc_params *p, int64_t n, const int32_t *type, const double *F, const double *T,
+                        double *v, double *w) {
+    (void)p;
+    for (int64_t i = 0; i < n; ++i) {
+        project_along(v + 3 * i, F + 3 * i);
+        if (type[i] == LIPID) project_along(w + 3 * i, T + 3 * i);
+    }
+}
+
+/* Scale a down so that |a| dt <= m. */
+static void cap_norm(double *a, double dt, double m) {
+    const double s = sqrt(dot3(a, a)) * dt;
+    if (s > m) {
+        const double f = m / s;
+        for (int k = 0; k < 3; ++k) a[k] *= f;
+    }
+}
+
+void orc_quench_cap(const orc_ext *e, int64_t n, const int32_t *type, double dt, double *v, double *w) {
+    for (int64_t i = 0; i < n; ++i) {
+        cap_norm(v + 3 * i, dt, e->quench_max);
+        if (type[i] == LIPID) cap_norm(w + 3 * i, dt, e->quench_max);
+    }
+}
+
 int orc_vv_run(const orc_params *p, int64_t n, double *x, double *v, double *nrm, double *w,
                const int32_t *type, int64_t nbond, const int32_t *bonds, const double *r0,
                double dt, int64_t nsteps, double *energies, int nthreads) {
@@ -666,7 +703,8 @@ int orc_vv_run_ext(const orc_params *p, const orc_ext *e, uint64_t step0, int64_
     double *F = (double *)malloc(sizeof(double) * (size_t)(3 * n + 3));
     double *T = (double *)malloc(sizeof(double) * (size_t)(3 * n + 3));
     double en[2];
-    const int thermo = e && (e->gamma > 0.0 || e->gamma_rot > 0.0);
+    const int quench = e && e->quench;
+    const int thermo = !quench && e && (e->gamma > 0.0 || e->gamma_rot > 0.0);
     orc_forces_ext(p, e, n, x, nrm, type, nbond, bonds, r0, F, T, en, nthreads);
     if (energies) {
         double ke = kinetic(p, n, v, w, type);
@@ -678,6 +716,10 @@ int orc_vv_run_ext(const orc_params *p, const orc_ext *e, uint64_t step0, int64_
             for (int a = 0; a < 3; ++a) v[3 * i + a] += 0.5 * dt * F[3 * i + a] / m;
             if (type[i] == LIPID)
                 for (int a = 0; a < 3; ++a) w[3 * i + a] += 0.5 * dt * T[3 * i + a] / p->inertia;
+            if (quench) {
+                cap_norm(v + 3 * i, dt, e->quench_max);
+                if (type[i] == LIPID) cap_norm(w + 3 * i, dt, e->quench_max);
+            }
             for (int a = 0; a < 3; ++a) x[3 * i + a] += dt * v[3 * i + a];
             if (type[i] == LIPID) rotor_drift(nrm + 3 * i, w + 3 * i, dt);
         }
@@ -689,6 +731,7 @@ int orc_vv_run_ext(const orc_params *p, const orc_ext *e, uint64_t step0, int64_
                 for (int a = 0; a < 3; ++a) w[3 * i + a] += 0.5 * dt * T[3 * i + a] / p->inertia;
         }
         if (thermo) orc_langevin_step(p, e, n, type, nrm, dt, step0 + (uint64_t)st, v, w);
+        if (quench) orc_quench_project(p, n, type, F, T, v, w);
         if (energies) {
             double ke = kinetic(p, n, v, w, type);
             energies[3 * st] = ke; energies[3 * st + 1] = en[0]; energies[3 * st + 2] = ke + en[0];

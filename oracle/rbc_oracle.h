@@ -44,6 +44,9 @@
  *   orc_langevin_step  deviates' mean and variance; equipartition of free
  *                    particles and free rotors (<m v^2> = 3 kT, <I w^2> = 2 kT);
  *                    the exact decay of the mean velocity.
+ *   orc_quench_*     hand-computed projections and caps; a harmonic dimer and
+ *                    a stretched chain relax to their minima; the energy of an
+ *                    overlapping structure falls monotonically.
  */
 #ifndef RBC_ORACLE_H
 #define RBC_ORACLE_H
@@ -122,6 +125,10 @@ typedef struct {
     double gamma;        /* translational friction rate; 0 = none */
     double gamma_rot;    /* lipid rotational friction rate; 0 = none */
     uint64_t seed;       /* Philox key */
+    double quench_max;   /* velocity quenching: largest move per step (sigma, and radians for
+                            a lipid's rotation) */
+    int32_t quench;      /* 1: velocity quenching instead of free dynamics */
+    int32_t pad;
 } orc_ext;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): counter ctr, key key. */
@@ -150,9 +157,22 @@ int orc_forces_ext(const orc_params *p, const orc_ext *e, int64_t n, const doubl
 void orc_langevin_step(const orc_params *p, const orc_ext *e, int64_t n, const int32_t *type,
                        const double *nrm, double dt, uint64_t step, double *v, double *w);
 
+/* Velocity quenching (Initial structure generation section: the generated
+ * structure is relaxed by velocity quenching; the rule is a reading): after the
+ * closing half-kick each particle keeps only the part of its velocity along its
+ * force, v <- max(v.F, 0) F / |F|^2 (v <- 0 where F = 0), and each lipid the
+ * part of its angular velocity along its torque.  The opening half-kick's
+ * velocity is then capped so that one drift moves a particle at most
+ * quench_max (and turns a lipid by at most quench_max radians). */
+void orc_quench_project(const orc_params *p, int64_t n, const int32_t *type, const double *F, const double *T,
+                        double *v, double *w);
+void orc_quench_cap(const orc_ext *e, int64_t n, const int32_t *type, double dt, double *v, double *w);
+
 /* Velocity Verlet as orc_vv_run, with the volume term in every force evaluation
  * and, when a friction rate is set, the thermostat update after each step's
- * closing half-kick; the steps are numbered step0 + 1 ... step0 + nsteps. */
+ * closing half-kick; the steps are numbered step0 + 1 ... step0 + nsteps.  With
+ * quench set, the velocity projection replaces the thermostat and the cap acts
+ * before each drift. */
 int orc_vv_run_ext(const orc_params *p, const orc_ext *e, uint64_t step0, int64_t n, double *x, double *v,
                    double *nrm, double *w, const int32_t *type, int64_t nbond, const int32_t *bonds,
                    const double *r0, double dt, int64_t nsteps, double *energies, int nthreads);

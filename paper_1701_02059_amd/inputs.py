@@ -68,6 +68,8 @@ class ModelParams:
     gamma: float = 0.0            # Langevin friction rate on translations (0: off)
     gamma_rot: float = 0.0        # Langevin friction rate on lipid rotations (0: off)
     seed: int = 0                 # thermostat random stream
+    quench: int = 0               # 1: velocity quenching (structure relaxation) instead of dynamics
+    quench_max: float = 0.05      # largest move per quenching step (sigma; radians for rotations)
 
     def rc_table(self) -> np.ndarray:
         """Per type-pair cutoff: r_c for lipid-lipid, the WCA range otherwise."""
@@ -379,6 +381,35 @@ def _to_depth(p: np.ndarray, site: np.ndarray, nrm: np.ndarray, depth: float) ->
     x0, n0 = site[idx], nrm[idx]
     h = np.sum((p - x0) * n0, axis=1)
     return p - (h + depth)[:, None] * n0
+
+
+# --------------------------------------------------------------------------- triangular meshes
+
+def _hull_triangles(points_on_sphere: np.ndarray) -> np.ndarray:
+    """Triangles of the convex hull of points on the unit sphere, each ordered so that
+    its normal (b - a) x (c - a) points away from the origin."""
+    from scipy.spatial import ConvexHull
+    tri = ConvexHull(points_on_sphere).simplices.astype(np.int64)
+    a, b, c = (points_on_sphere[tri[:, k]] for k in range(3))
+    flip = np.einsum("ij,ij->i", np.cross(b - a, c - a), a + b + c) < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    return tri
+
+
+def sphere_mesh(nv: int = 200, radius: float = 12.0):
+    """Closed triangular mesh of a sphere: nv Fibonacci vertices, outward triangles."""
+    u = _fibonacci_sphere(nv)
+    return radius * u, _hull_triangles(u)
+
+
+def evans_fung_mesh(nv: int = 2000, area: float = 450_000 * LIPID_AREA):
+    """Closed triangular mesh of the Evans-Fung biconcave shape with nv equal-area
+    vertices, scaled to the given surface area (sigma^2), triangulated through the
+    equal-area map to the sphere; triangles oriented outward."""
+    t_tab, A_tab = evans_fung_area_table()
+    scale = math.sqrt(area / A_tab[-1])
+    pos, _, sph = _ef_points(nv, t_tab, A_tab, scale)
+    return pos, _hull_triangles(sph)
 
 
 # --------------------------------------------------------------------------- named workloads

@@ -191,3 +191,52 @@ def test_ext_off_equals_nve(mp):
     b = O.vv_run_ext(p, O.make_ext(mp), s, 0.01, 5)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+# ------------------------------------------------------------------ velocity quenching
+
+def test_quench_projection_and_cap_by_hand(mp):
+    p = O.make_params(mp)
+    typ = np.array([0, 1, 1, 0], dtype=np.int32)
+    F = np.array([[2.0, 0, 0], [1.0, 0, 0], [0.0, 0, 0], [0.0, 3.0, 4.0]])
+    T = np.array([[0.0, 0, 2.0], [0, 0, 0], [0, 0, 0], [1.0, 0, 0]])
+    v = np.array([[1.0, 2.0, 0], [-1.0, 5.0, 0], [3.0, 3.0, 3.0], [0.0, 2.0, 0.0]])
+    w = np.array([[0.0, 1.0, 3.0], [1.0, 1.0, 1.0], [0, 0, 0], [-2.0, 0, 0]])
+    v2, w2 = O.quench_project(p, typ, F, T, v, w)
+    assert np.allclose(v2, [[1.0, 0, 0], [0, 0, 0], [0, 0, 0], [0, 0.72, 0.96]])
+    assert np.allclose(w2, [[0, 0, 3.0], [1.0, 1.0, 1.0], [0, 0, 0], [0, 0, 0]])   # proteins keep w
+    e = O.make_ext(dataclasses.replace(mp, quench=1, quench_max=0.25))
+    v3, w3 = O.quench_cap(e, typ, 0.1, np.array([[3.0, 4.0, 0]] * 4), np.array([[0, 0, 10.0]] * 4))
+    assert np.allclose(v3, [[1.5, 2.0, 0]] * 4)
+    assert np.allclose(w3[[0, 3]], [[0, 0, 2.5]] * 2) and np.allclose(w3[[1, 2]], [[0, 0, 10.0]] * 2)
+
+
+def test_quench_relaxes_a_stretched_chain(mp):
+    """Five bonded beads (bond minimum 1.5 sigma, beyond the WCA range) stretched to
+    2.5: quenching brings every bond to its rest length, the energy never rising."""
+    N = 5
+    x = np.zeros((N, 3))
+    x[:, 0] = 2.5 * np.arange(N)
+    x[2, 1] = 0.7
+    s = I.System("chain", x, np.zeros((N, 3)), np.ones(N, np.int32), np.zeros((N, 3)), np.zeros((N, 3)),
+                 np.stack([np.arange(N - 1), np.arange(1, N)], axis=1).astype(np.int32), np.full(N - 1, 1.5),
+                 np.zeros(3), np.zeros(3, np.int32))
+    m = dataclasses.replace(mp, quench=1, quench_max=0.05)
+    p, e = O.params_for(s, m), O.make_ext(m)
+    xf, vf, _, _, en = O.vv_run_ext(p, e, s, 0.01, 3000)
+    r = np.linalg.norm(np.diff(xf, axis=0), axis=1)
+    assert np.abs(r - 1.5).max() < 1e-6
+    assert np.all(np.diff(en[:, 1]) <= 1e-12 * en[0, 1])
+
+
+def test_quench_removes_overlaps_of_a_generated_structure(mp):
+    from scipy.spatial import cKDTree
+    from paper_1701_02059_amd import structure as G
+    v, t = I.sphere_mesh(200, 28.0)
+    s, ident, face = G.generate(v, t, G.GenParams(seed=5))
+    m = dataclasses.replace(mp, quench=1, quench_max=0.05)
+    p, e = O.params_for(s, m), O.make_ext(m)
+    x, vv, n, w, en = O.vv_run_ext(p, e, s, 0.01, 200)
+    assert en[0, 1] > 0 and en[-1, 1] < 0                      # overlaps relaxed into a bound sheet
+    assert cKDTree(x).query(x, k=2)[0][:, 1].min() > 0.8
+    assert np.abs(np.linalg.norm(n[s.type == 0], axis=1) - 1).max() < 1e-12
