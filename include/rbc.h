@@ -104,6 +104,14 @@ typedef struct {
     double gamma;                               /* translational friction rate; 0: none */
     double gamma_rot;                           /* lipid rotational friction rate; 0: none */
     uint64_t seed;
+    /* Velocity quenching, the relaxation the Initial structure generation section
+     * applies to a generated structure (the rule is a reading): after each closing
+     * half-kick a particle keeps only the part of its velocity along its force,
+     * v <- max(v.F, 0) F / |F|^2, and a lipid likewise the part of its angular
+     * velocity along its torque; before each drift |v| dt and |w| dt are capped at
+     * quench_max.  Excludes the thermostat. */
+    double quench_max;                          /* sigma per step (radians for rotations) */
+    int32_t quench;                             /* 1: quench instead of free dynamics */
 } rbc_params;
 
 /* ---- single-system context (an ensemble with one slot) ---- */

@@ -226,6 +226,30 @@ __device__ __forceinline__ void volume_chunk_store(const SysDev &S, int chunk, d
         for (int q = 0; q < 8; ++q) S.vpart[(size_t)q * S.nchunk + chunk] = v[q];
 }
 
+// Velocity quenching: keep the part of a along b when it points along b,
+// a <- max(a.b, 0) b / |b|^2; and scale a so that |a| dt <= m.  No contraction,
+// as for the kicks.
+__device__ __forceinline__ void project_along(D4 &a, double bx, double by, double bz) {
+#pragma clang fp contract(off)
+    const double bb = bx * bx + by * by + bz * bz;
+    const double ab = a.x * bx + a.y * by + a.z * bz;
+    if (bb > 0.0 && ab > 0.0) {
+        const double s = ab / bb;
+        a.x = s * bx; a.y = s * by; a.z = s * bz;
+    } else {
+        a.x = 0.0; a.y = 0.0; a.z = 0.0;
+    }
+}
+
+__device__ __forceinline__ void cap_move(D4 &a, double dt, double m) {
+#pragma clang fp contract(off)
+    const double s = sqrt(a.x * a.x + a.y * a.y + a.z * a.z) * dt;
+    if (s > m) {
+        const double f = m / s;
+        a.x *= f; a.y *= f; a.z *= f;
+    }
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two 32 x 32
 // -> 64-bit products mixed with the other words and the key, which advances by
 // the Weyl constants between rounds.
@@ -532,18 +556,24 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
             half_kick(v, h, Fx, Fy, Fz);
             if (ti == 0) half_kick(w, hw, Tq.x, Tq.y, Tq.z);
             if (P.thermo_on) langevin_update(P, g, S.sc->step, ti, ni, v, w);
+            if (P.quench_on) {
+                project_along(v, Fx, Fy, Fz);
+                if (ti == 0) project_along(w, Tq.x, Tq.y, Tq.z);
+            }
             if (KICK == 1) {
                 S.vel[i] = v;
                 if (ti == 0) S.angv[i] = w;
             } else {
                 D4 vn = v, wn = w, xn = pi;
                 half_kick(vn, h, Fx, Fy, Fz);
+                if (P.quench_on) cap_move(vn, dt, P.quench_max);
                 drift_pos(xn, vn, dt);
                 S.vel[i] = vn;
                 S.pos2[i] = xn;
                 D4 on = ni;
                 if (ti == 0) {
                     half_kick(wn, hw, Tq.x, Tq.y, Tq.z);
+                    if (P.quench_on) cap_move(wn, dt, P.quench_max);
                     S.angv[i] = wn;
                     on = rotor_drift(ni, wn, dt);
                 }
@@ -632,6 +662,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
         const int t = (int)p.w;
         const double h = 0.5 * dt * P.inv_mass[t];
         half_kick(v, h, f.x, f.y, f.z);
+        if (P.quench_on) cap_move(v, dt, P.quench_max);
         drift_pos(p, v, dt);
         S.vel[i] = v;
         S.pos[i] = p;
@@ -640,6 +671,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
             const D4 tq = S.trq[i];
             const double hw = 0.5 * dt * P.inv_inertia;
             half_kick(w, hw, tq.x, tq.y, tq.z);
+            if (P.quench_on) cap_move(w, dt, P.quench_max);
             const D4 n = rotor_drift(S.ori[i], w, dt);
             S.angv[i] = w;
             S.ori[i] = n;

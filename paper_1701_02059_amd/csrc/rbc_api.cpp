@@ -147,6 +147,9 @@ bool valid_params(const rbc_params *p, std::string &why) {
     if (!(p->vol_k >= 0.0) || !(p->vol_target >= 0.0)) { why = "vol_k and vol_target must be >= 0"; return false; }
     if (p->vol_k > 0.0 && !(p->lipid_area > 0.0)) { why = "the volume constraint needs lipid_area > 0"; return false; }
     if (!(p->kT >= 0.0) || !(p->gamma >= 0.0) || !(p->gamma_rot >= 0.0)) { why = "kT, gamma and gamma_rot must be >= 0"; return false; }
+    if (p->quench != 0 && p->quench != 1) { why = "quench must be 0 or 1"; return false; }
+    if (p->quench && !(p->quench_max > 0.0)) { why = "quenching needs quench_max > 0"; return false; }
+    if (p->quench && (p->gamma > 0.0 || p->gamma_rot > 0.0)) { why = "quenching excludes the thermostat"; return false; }
     if (!(p->wca_sigma > 0.0) || !(p->k_bond >= 0.0)) { why = "bad WCA / bond constants"; return false; }
     return true;
 }
@@ -194,6 +197,8 @@ void make_dev_params(rbc_ctx *h) {
     d.seed_hi = (uint32_t)(p.seed >> 32);
     d.ou_c = d.ou_cr = 1.0;
     d.ou_a[0] = d.ou_a[1] = d.ou_a[2] = d.ou_ar = 0.0;
+    d.quench_on = p.quench;
+    d.quench_max = p.quench_max;
 }
 
 // Thermostat coefficients for time step dt: the exact Ornstein-Uhlenbeck decay

@@ -126,6 +126,10 @@ struct DevParams {
     int32_t pad;
     double ou_c, ou_a[3];  // translation: c = exp(-gamma dt), a per type
     double ou_cr, ou_ar;   // lipid rotation
+    // velocity quenching: projection on the force after the closing kick, move cap
+    int32_t quench_on;
+    int32_t pad2;
+    double quench_max;
 };
 
 // Block -> system maps: off[s] = first block of system s, off[nsys] = total blocks.

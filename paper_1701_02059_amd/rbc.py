@@ -37,7 +37,8 @@ class RbcParams(C.Structure):
                 ("skin", C.c_double), ("lloyd_iters", C.c_int32), ("precision", C.c_int32),
                 ("protein_cells", C.c_int32),
                 ("vol_k", C.c_double), ("vol_target", C.c_double), ("lipid_area", C.c_double),
-                ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64)]
+                ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64),
+                ("quench_max", C.c_double), ("quench", C.c_int32)]
 
 
 class RbcError(RuntimeError):
@@ -117,6 +118,7 @@ def make_params(mp, precision: int = RBC_FP64) -> RbcParams:
     p.vol_k, p.vol_target = float(mp.vol_k), float(mp.vol_target)
     p.lipid_area = float(mp.lipid_area)
     p.kT, p.gamma, p.gamma_rot, p.seed = float(mp.kT), float(mp.gamma), float(mp.gamma_rot), int(mp.seed)
+    p.quench, p.quench_max = int(getattr(mp, "quench", 0)), float(getattr(mp, "quench_max", 0.05))
     return p
 
 
