@@ -169,6 +169,30 @@ def ext_run(R, mp, system, steps, warmup):
     return r
 
 
+def structure_run(R, mp, warmup, steps=1000):
+    """A cell generated on a 2,000-vertex Evans-Fung mesh (about 500k particles),
+    relaxed by velocity quenching: quench throughput and the energy it removes."""
+    from paper_1701_02059_amd import inputs as I
+    from paper_1701_02059_amd import structure as G
+    t0 = time.perf_counter()
+    v, t = I.evans_fung_mesh(2000, 450_000 * I.LIPID_AREA)
+    system, ident, _ = G.generate(v, t, G.GenParams(seed=0))
+    gen_s = time.perf_counter() - t0
+    log(f"[structure] generated {system.N:,} particles on {t.shape[0]:,} triangles in {gen_s:.1f} s")
+    m = dataclasses.replace(mp, quench=1, quench_max=0.05)
+    ctx = R.Context(m, R.RBC_MIXED)
+    ctx.set_system(system)
+    U0 = float(ctx.energy()[0])
+    ctx.close()
+    ctx, r = timed_run(R, m, system, R.RBC_MIXED, steps, warmup, "quench")
+    U1 = float(ctx.energy()[0])
+    ctx.close()
+    r.pop("energy", None)
+    r.update(particles=system.N, generation_s=gen_s, U_start=U0, U_end=U1,
+             quench_steps=steps + warmup)
+    return r
+
+
 def serving_run(R, mp, count, rate, steps, saturated=False):
     from paper_1701_02059_amd import inputs as I
     from paper_1701_02059_amd import serving as SV
@@ -200,6 +224,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-detached", action="store_true")
     ap.add_argument("--no-ext", action="store_true")
+    ap.add_argument("--no-structure", action="store_true")
     ap.add_argument("--detached-steps", type=int, default=500)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
@@ -266,6 +291,10 @@ def main():
     if not args.no_ext:
         ext = ext_run(R, mp, system, args.detached_steps, min(args.warmup, 20))
 
+    structure = None
+    if not args.no_structure:
+        structure = structure_run(R, mp, min(args.warmup, 20))
+
     detached = None
     if not args.no_detached:
         detached = detached_run(R, mp, args.workload, args.detached_steps, min(args.warmup, 20))
@@ -315,6 +344,7 @@ def main():
         "serving": serving,
         "detached": detached,
         "volume_and_thermostat": ext,
+        "structure": structure,
     }
     print(json.dumps(line))
 
