@@ -410,11 +410,13 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
     auto staged_rows = [&](auto per_tag, auto part_tag) {
         constexpr bool PER = decltype(per_tag)::value;
         constexpr bool PARTIAL = decltype(part_tag)::value;   // stage entries beyond the LDS part
-        // Software pipeline: the list entry of row r+2 is fetched from global memory and
+        // Software pipeline: the list entry of row r+4 is fetched from global memory and
         // the stage record of row r+1 from LDS while row r is evaluated.
         const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
         int e_cur = (valid && rows > 0) ? (int)ldg(col) : 0xffff;
         int e_nxt = (valid && rows > 1) ? (int)ldg(col + CHUNK) : 0xffff;
+        int e_n2 = (valid && rows > 2) ? (int)ldg(col + 2 * CHUNK) : 0xffff;
+        int e_n3 = (valid && rows > 3) ? (int)ldg(col + 3 * CHUNK) : 0xffff;
         struct Rec {
             double x, y, z;
             T nx, ny, nz;
@@ -452,7 +454,9 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
             const int e = e_cur;
             const Rec c = rec;
             e_cur = e_nxt;
-            e_nxt = (valid && r + 2 < rows) ? (int)ldg(col + (r + 2) * CHUNK) : 0xffff;
+            e_nxt = e_n2;
+            e_n2 = e_n3;
+            e_n3 = (valid && r + 4 < rows) ? (int)ldg(col + (r + 4) * CHUNK) : 0xffff;
             rec = fetch(e_cur);
             if (e >= scnt) continue;
             const int tj = c.t;
