@@ -332,12 +332,13 @@ __device__ __forceinline__ void drift_stats(const SysDev &S, int blk, double dis
 
 // LDS stage per 256-particle block (structure of arrays): FP64 positions, and either
 // FP32 orientations with the type in w (mixed) or FP64 orientations and a type byte.
-// Mixed mode holds the first 800 stage entries (32 KB: five blocks per CU, the
-// occupancy its register count allows) and reads any further ones from global
-// memory; FP64 mode, limited to three blocks per CU by registers, holds all SMAX.
+// Both modes hold the first 800 stage entries in LDS and read any further ones
+// (about 1% of blocks have more) from global memory.  Mixed mode: 32 KB and 88
+// registers, five blocks (waves per SIMD) per CU; FP64 mode: 39 KB and, with the
+// register budget capped at 128, four.
 template <int MIXED>
 struct Stage {
-    static constexpr int lds = MIXED ? 800 : SMAX;
+    static constexpr int lds = 800;
     static constexpr int bytes = MIXED ? lds * (3 * 8 + 16) : lds * (6 * 8 + 1);
 };
 static_assert(Stage<1>::lds <= SMAX && (Stage<1>::lds * 24) % 16 == 0, "mixed stage layout");
@@ -352,7 +353,7 @@ static_assert(Stage<1>::lds <= SMAX && (Stage<1>::lds * 24) % 16 == 0, "mixed st
 // half-kick and drift of the next step (positions and orientations go to the
 // second buffers, which the stats kernel then swaps in), without storing F, tau.
 template <int MIXED, int ENERGY, int KICK, int FAST>
-__global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4))) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     using T = typename std::conditional<MIXED, float, double>::type;
     constexpr int SL = Stage<MIXED>::lds;
     __shared__ __align__(16) unsigned char s_raw[Stage<MIXED>::bytes];
@@ -428,9 +429,14 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SysDev *Sd, Maps L_maps, 
                 if (e >= nlds && e < scnt) {            // stage entry beyond the LDS part
                     const int slot = ldg(S.stage + (size_t)lb * SMAX + e);
                     const D4 p = ldg(S.pos + slot);
-                    const F4 o = ldg(S.ori32 + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
-                    c.nx = o.x; c.ny = o.y; c.nz = o.z;
+                    if constexpr (MIXED) {
+                        const F4 o = ldg(S.ori32 + slot);
+                        c.nx = o.x; c.ny = o.y; c.nz = o.z;
+                    } else {
+                        const D4 o = ldg(S.ori + slot);
+                        c.nx = o.x; c.ny = o.y; c.nz = o.z;
+                    }
                     c.t = (int)p.w;
                     return c;
                 }
