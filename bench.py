@@ -46,8 +46,8 @@ PEAK_HBM = 8000.0           # GB/s
 # HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
 # skin 0.5: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
-FORCE_TRAFFIC = {"sources_sha256": "b246e6cf2116f361", "bytes": 2520782640,
-                 "fetch_kib": 955119, "write_kib": 551465}
+FORCE_TRAFFIC = {"sources_sha256": "7e33856bb6868727", "bytes": 2520680267,
+                 "fetch_kib": 955070, "write_kib": 551462}
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
                   "paper_1701_02059_amd/csrc/rbc_dev.h")
 
@@ -235,7 +235,7 @@ def main():
                     help="also run one plain device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this library runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
         sys.exit(2)
 
