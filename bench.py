@@ -47,7 +47,9 @@ PEAK_HBM = 8000.0           # GB/s
 # skin 0.5: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
 FORCE_TRAFFIC = {"sources_sha256": "7e33856bb6868727", "bytes": 2520680267,
-                 "fetch_kib": 955070, "write_kib": 551462}
+                 "fetch_kib": 955070, "write_kib": 551462,
+                 "valu_insts": 277259823}   # SQ_INSTS_VALU per launch (wavefront instructions)
+CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
                   "paper_1701_02059_amd/csrc/rbc_dev.h")
 
@@ -265,8 +267,12 @@ def main():
     else:
         bound, achieved, peak, unit = "alu", flops / t_force / 1e12, PEAK_FP32, "TFLOP/s"
     digest = kernel_sources_digest()
-    traffic = FORCE_TRAFFIC["bytes"] if (FORCE_TRAFFIC["sources_sha256"] == digest and
-                                        args.workload == "rbc4m" and args.skin == 0.5) else None
+    counters_valid = (FORCE_TRAFFIC["sources_sha256"] == digest and args.workload == "rbc4m" and
+                      args.skin == 0.5)
+    traffic = FORCE_TRAFFIC["bytes"] if counters_valid else None
+    # a wavefront VALU instruction occupies a 16-lane SIMD for 4 cycles
+    valu_busy = (FORCE_TRAFFIC["valu_insts"] * 4 / (t_force * CLOCK_GHZ * 1e9 * CU_COUNT * SIMDS_PER_CU)
+                 if counters_valid else None)
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": traffic,
             "kernel": "k_force<mixed, fused kick-drift-kick> (pair forces, bonds, integration)",
@@ -277,6 +283,8 @@ def main():
             "roofline_time_us": round(max(t_flop, t_byte) * 1e6, 2),
             "time_frac": round(max(t_flop, t_byte) / t_force, 4),
             "traffic_sources_sha256": digest,
+            "hbm_traffic_tbps": round(traffic / t_force / 1e12, 3) if traffic else None,
+            "valu_busy_frac": round(valu_busy, 4) if valu_busy else None,
             "lipid_pairs": n_ll, "wca_pairs": n_wca, "bonds": n_bond}
     log(f"[roofline] {roof}")
 

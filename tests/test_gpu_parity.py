@@ -397,10 +397,15 @@ def _dense_cloud(n_side=14, spacing=1.36, seed=11):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_dense_3d_cloud_unstaged_blocks(R, mp, prec):
+    """All three stage layouts at once: blocks whose partners fit the 800 LDS entries,
+    blocks with 801-1024 partners (the entries past 800 read from global memory) and
+    blocks past 1024 (global slots in 32-bit lists)."""
     s = _dense_cloud()
     p = O.params_for(s, mp)
     F0, T0, U0, W0 = O.forces(p, s)
     c = _ctx(R, mp, s, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
+    sc = c.debug_array(9).view(np.int32)
+    assert (sc < 0).any() and ((sc > 800) & (sc <= 1024)).any() and ((sc >= 0) & (sc <= 800)).any(), sc
     F, T = (to_np(t) for t in c.forces())
     tol = FP64_TOL if prec == "fp64" else MIXED_TOL
     assert rel_err(F, F0) < tol and rel_err(T, T0) < tol
