@@ -428,7 +428,10 @@ def config(name: str, seed: int = 0, params: Optional[ModelParams] = None) -> Sy
     """The synthetic workloads: 'patch' (2,704 particles), 'vesicle' (124,952),
     'rbc4m' (3,999,952), 'rbc500k' (499,952), and 'tiny' for fast checks.  A
     '_detached' suffix gives the same sizes with the cytoskeleton DETACHED_DEPTH
-    under the sheet and tethered at every DETACHED_TETHER-th junction only."""
+    under the sheet and tethered at every DETACHED_TETHER-th junction only
+    ('tiny_detached' is for static checks: on a sphere that small the deeper
+    network crowds its chain beads at the junctions and does not hold together
+    under dynamics)."""
     if name.endswith("_detached"):
         base = name[: -len("_detached")]
         kw = dict(seed=seed, params=params, depth=DETACHED_DEPTH, tether=DETACHED_TETHER)

@@ -180,3 +180,36 @@ def test_degenerate_sets(R, dmp):
         p = O.params_for(s, dmp)
         assert np.array_equal(c.get_pairs(), O.pairs(p, s.x, s.type, "brute"))
         c.close()
+
+
+def test_ensemble_with_options_alone_equals_mix(R, mp):
+    """Separate protein cells, the volume constraint (each system keeps its own V0)
+    and the thermostat in a changing batch: every trajectory equals its run alone."""
+    m = dataclasses.replace(mp, protein_cells=1, vol_k=5.0, vol_target=0.0, gamma=0.5, gamma_rot=0.5,
+                            seed=99)
+    # detached vesicles below ~5,000 lipids crowd their chain beads at the junctions
+    systems = [I.vesicle(8000, 80, seed=41, depth=I.DETACHED_DEPTH, tether=I.DETACHED_TETHER),
+               I.vesicle(6000, 60, seed=42),
+               I.vesicle(5000, 50, seed=43, depth=I.DETACHED_DEPTH, tether=I.DETACHED_TETHER)]
+    alone = []
+    for s in systems:
+        e = R.Ensemble(m, R.RBC_MIXED, max_slots=4)
+        a = e.admit(s)
+        e.step(40, 0.01)
+        alone.append([to_np(t) for t in e.get_state(a)] + [e.energy(a)])
+        e.close()
+    e = R.Ensemble(m, R.RBC_MIXED, max_slots=4)
+    s0 = e.admit(systems[0])
+    e.step(10, 0.01)
+    s1 = e.admit(systems[1])
+    s2 = e.admit(systems[2])
+    e.step(30, 0.01)
+    got0 = [to_np(t) for t in e.get_state(s0)] + [e.energy(s0)]
+    e.retire(s0)
+    e.step(10, 0.01)
+    got1 = [to_np(t) for t in e.get_state(s1)] + [e.energy(s1)]
+    got2 = [to_np(t) for t in e.get_state(s2)] + [e.energy(s2)]
+    e.close()
+    for ref, got in ((alone[0], got0), (alone[1], got1), (alone[2], got2)):
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
