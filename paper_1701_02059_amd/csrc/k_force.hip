@@ -220,9 +220,30 @@ __device__ __forceinline__ void volume_terms(const D4 &x, const D4 &n, double v[
     v[7] = 1.0;
 }
 
+// Wavefront sum of a double by DPP lane moves in a fixed order (no LDS traffic):
+// a Hillis-Steele scan within each 16-lane row (shifts 1, 2, 4, 8), then row 0's
+// total into row 1 and row 2's into row 3 (row_bcast:15), then the first half's
+// total into rows 2 and 3 (row_bcast:31).  Lane 63 ends with the total.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_total_lane63(double v) {
+    v = dpp_add<0x111, 0xf>(v);     // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);     // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);     // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);     // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);     // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 __device__ __forceinline__ void volume_chunk_store(const SysDev &S, int chunk, double v[8]) {
-    for (int q = 0; q < 8; ++q) v[q] = wave_sum(v[q]);
-    if ((threadIdx.x & (WAVE - 1)) == 0)
+    for (int q = 0; q < 8; ++q) v[q] = wave_total_lane63(v[q]);
+    if ((threadIdx.x & (WAVE - 1)) == WAVE - 1)
         for (int q = 0; q < 8; ++q) S.vpart[(size_t)q * S.nchunk + chunk] = v[q];
 }
 
