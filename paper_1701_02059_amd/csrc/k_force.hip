@@ -241,6 +241,25 @@ __device__ __forceinline__ double wave_total_lane63(double v) {
     return v;
 }
 
+// The same scan taking maxima, for non-negative values (lanes without a source
+// contribute 0).  Lane 63 ends with the largest value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_max(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return fmax(v, __hiloint2double(hi, lo));
+}
+
+__device__ __forceinline__ double wave_max_lane63(double v) {
+    v = dpp_max<0x111, 0xf>(v);
+    v = dpp_max<0x112, 0xf>(v);
+    v = dpp_max<0x114, 0xf>(v);
+    v = dpp_max<0x118, 0xf>(v);
+    v = dpp_max<0x142, 0xa>(v);
+    v = dpp_max<0x143, 0xc>(v);
+    return v;
+}
+
 __device__ __forceinline__ void volume_chunk_store(const SysDev &S, int chunk, double v[8]) {
     for (int q = 0; q < 8; ++q) v[q] = wave_total_lane63(v[q]);
     if ((threadIdx.x & (WAVE - 1)) == WAVE - 1)
@@ -338,10 +357,10 @@ __device__ __forceinline__ void volume_term(const SysScal *sc, const D4 &x, cons
 // wave's particles go to the block's partial slots 2w and 2w+1; a non-finite
 // state raises the system's error bit.
 __device__ __forceinline__ void drift_stats(const SysDev &S, int blk, double disp2, double v2, bool bad) {
-    disp2 = wave_maxd(disp2);
-    v2 = wave_maxd(v2);
+    disp2 = wave_max_lane63(disp2);
+    v2 = wave_max_lane63(v2);
     const unsigned long long anybad = __ballot(bad);
-    if (lane_id_f() == 0) {
+    if (lane_id_f() == WAVE - 1) {
         const int w = (threadIdx.x >> 6) & 3;
         S.bred[(size_t)blk * BRED + 2 * w] = disp2;
         S.bred[(size_t)blk * BRED + 2 * w + 1] = v2;
