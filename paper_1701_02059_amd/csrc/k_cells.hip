@@ -201,7 +201,11 @@ __global__ __launch_bounds__(BLOCK) void k_bbox_partial(const SysDev *Sd, Maps L
 }
 
 // Bounding boxes and grid geometry, one block per system (from the per-block partials).
-__global__ void k_grid_setup(const SysDev *Sd, int nsys) {
+// Uniform grid over the seeds: cubic cells holding about one eighth of a seed each,
+// but no smaller than hmin (twice the cell-pair search radius).  A cell-pair query
+// walks every grid cell within its reach; on small systems a finer grid would make
+// each query a long chain of dependent loads over mostly empty cells.
+__global__ void k_grid_setup(const SysDev *Sd, int nsys, double hmin) {
     const SysDev &S = Sd[blockIdx.x];
     if (!S.sc->rebuild) return;
     __shared__ double s_mn[6][16], s_mx[6][16];
@@ -248,7 +252,7 @@ __global__ void k_grid_setup(const SysDev *Sd, int nsys) {
         }
         double cap = (double)max(1, S.gcap);
         double vol = fmax(ext[0], 1.0) * fmax(ext[1], 1.0) * fmax(ext[2], 1.0);
-        double h = fmax(1.0, cbrt(vol / cap));
+        double h = fmax(hmin, cbrt(vol / cap));
         int dims[3];
         for (int it = 0; it < 200; ++it) {
             double prod = 1.0;
@@ -436,7 +440,7 @@ __global__ void k_grid_sortcells(const SysDev *Sd, Maps L_maps) {
 
 void launch_grid_build(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_bbox_partial, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
-    hipLaunchKernelGGL(k_grid_setup, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys);
+    hipLaunchKernelGGL(k_grid_setup, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys, 2.0 * L.prm.cell_search);
     hipLaunchKernelGGL(k_grid_clear, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     launch_scan(L, 0);
