@@ -314,7 +314,7 @@ def main():
 
     serving = None
     if not args.no_serving:
-        smp = I.ModelParams()
+        smp = I.ModelParams(skin=args.skin)
         serving = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps)
         serving["saturated"] = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps, saturated=True)
 
