@@ -939,9 +939,9 @@ __global__ void k_cell_bounds(const SysDev *Sd, Maps L_maps) {
     if ((threadIdx.x & 63) == 0 && c - (int)(threadIdx.x & 63) < S.k) atomicMax(&S.sc->rmax, dbits(R));
 }
 
-// Cells B paired with A: |minimg(c_A - c_B)| <= R_A + R_B + search + 1e-9 with
-// search = largest (rc + 2 skin).  mode 0 counts, mode 1 writes (grid-scan order).
-__device__ int cell_query(const SysDev &S, const SysScal *sc, int A, double search, int mode, int *out, int cap) {
+// Cells B paired with A (as below), one thread per cell: the serial walk of the
+// window.  mode 0 counts, mode 1 writes (grid-scan order).
+__device__ int cell_query_serial(const SysDev &S, const SysScal *sc, int A, double search, int mode, int *out, int cap) {
     D4 ca = S.seed[A];
     double Ra = ca.w;
     double rho = Ra + bitsd(sc->rmax) + search + 1e-9;
@@ -988,37 +988,175 @@ __device__ int cell_query(const SysDev &S, const SysScal *sc, int A, double sear
     return cnt;
 }
 
-__global__ void k_cnbr_count(const SysDev *Sd, Maps L_maps, double search) {
+// Cells B paired with A: |minimg(c_A - c_B)| <= R_A + R_B + search + 1e-9 with
+// search = largest (rc + 2 skin).  One wavefront per cell A: the grid cells within
+// reach (x slowest, z fastest) are taken 64 at a time, lane l scanning the seeds of
+// the l-th one.  With `out`, the hits are written in that scan order (an exclusive
+// scan of the lanes' counts places each lane's hits), so the row is the same as a
+// serial walk of the window would give.  Returns the row's length on every lane.
+__device__ int cell_query_wave(const SysDev &S, const SysScal *sc, int A, double search, int32_t *out, int cap) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const D4 ca = S.seed[A];
+    const double Ra = ca.w;
+    const double rho = Ra + bitsd(sc->rmax) + search + 1e-9;
+    const double xa[3] = {ca.x, ca.y, ca.z};
+    int lo[3], nw[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = wrap_coord(xa[a], S.per[a], S.box[a]) - sc->glo[a];
+        int dim = sc->gdim[a];
+        double fl = floor((u - rho) / sc->gh[a]), fh = floor((u + rho) / sc->gh[a]);
+        if (!(fl > -1e9 && fh < 1e9)) { fl = 0.0; fh = (double)(dim - 1); }   // non-finite: scan the axis
+        int l = (int)fl;
+        int h = (int)fh;
+        if (S.per[a]) {
+            if (h - l + 1 >= dim) { l = 0; h = dim - 1; }
+        } else {
+            l = max(l, 0);
+            h = min(h, dim - 1);
+        }
+        lo[a] = l;
+        nw[a] = max(0, h - l + 1);
+    }
+    const int W = nw[0] * nw[1] * nw[2];
+    int total = 0;
+    double dx, dy, dz;
+    for (int w0 = 0; w0 < W; w0 += WAVE) {
+        const int wi = w0 + lane;
+        int qb = 0, qe = 0;
+        if (wi < W) {
+            const int iz = wi % nw[2], iy = (wi / nw[2]) % nw[1], ix = wi / (nw[2] * nw[1]);
+            int gx = lo[0] + ix, gy = lo[1] + iy, gz = lo[2] + iz;
+            if (S.per[0]) gx = ((gx % sc->gdim[0]) + sc->gdim[0]) % sc->gdim[0];
+            if (S.per[1]) gy = ((gy % sc->gdim[1]) + sc->gdim[1]) % sc->gdim[1];
+            if (S.per[2]) gz = ((gz % sc->gdim[2]) + sc->gdim[2]) % sc->gdim[2];
+            const int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
+            qb = ldg(S.gstart + g);
+            qe = ldg(S.gstart + g + 1);
+        }
+        auto hit = [&](int q, int &B) {
+            B = ldg(S.gseed + q);
+            const D4 cb = ldg(S.seed + B);
+            const double d = sqrt(dist2_exact(S, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, dx, dy, dz));
+            return d <= Ra + cb.w + search + 1e-9;
+        };
+        int cnt = 0;
+        for (int q = qb; q < qe; ++q) {
+            int B;
+            if (hit(q, B)) ++cnt;
+        }
+        // inclusive scan of the lanes' counts
+        int inc = cnt;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (out && cnt > 0) {
+            int k = total + inc - cnt;
+            for (int q = qb; q < qe; ++q) {
+                int B;
+                if (hit(q, B)) {
+                    if (k < cap) out[k] = B;
+                    ++k;
+                }
+            }
+        }
+        total += __shfl(inc, WAVE - 1);
+    }
+    return total;
+}
+
+// Cell-pair kernels.  Systems of at least CQ_SERIAL_MIN cells take one thread per
+// cell (there are enough threads to hide the serial walk's latency); smaller ones
+// give each cell a wavefront, with four blocks per 256-cell block of the cell map and
+// CQ_WAVE consecutive cells per wavefront in turn.  Both write the same rows.
+constexpr int CQ_WAVE = 16;
+constexpr int CQ_SERIAL_MIN = 20000;
+
+__global__ __launch_bounds__(BLOCK) void k_cnbr_count_serial(const SysDev *Sd, Maps L_maps, double search) {
     SYS_FROM(c);
-    if (!S.sc->rebuild) return;
-    int c = lb * BLOCK + threadIdx.x;
+    if (!S.sc->rebuild || S.k < CQ_SERIAL_MIN) return;
+    const int c = lb * BLOCK + threadIdx.x;
     int n = 0;
     if (c < S.k) {
-        n = cell_query(S, S.sc, c, search, 0, nullptr, 0);
+        n = cell_query_serial(S, S.sc, c, search, 0, nullptr, 0);
         if (n > CNBR_ROW_MAX) {          // keeps the scanned total inside int32
             atomicOr(&S.sc->err, ERR_CNBR);
             n = 0;
         }
         S.cnbr_start[c] = n;
     }
-    int m = wave_max_int(n);
+    const int m = wave_max_int(n);
     if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(&S.sc->cnbr_maxrow, m);
 }
 
-__global__ void k_cnbr_fill(const SysDev *Sd, Maps L_maps, double search) {
+__global__ __launch_bounds__(BLOCK) void k_cnbr_fill_serial(const SysDev *Sd, Maps L_maps, double search) {
     SYS_FROM(c);
-    if (!S.sc->rebuild) return;
-    int c = lb * BLOCK + threadIdx.x;
+    if (!S.sc->rebuild || S.k < CQ_SERIAL_MIN) return;
+    const int c = lb * BLOCK + threadIdx.x;
     if (c >= S.k) return;
-    int total = S.cnbr_start[S.k];
+    const int total = S.cnbr_start[S.k];
     if (c == 0) S.sc->cnbr_total = total;
     if (total > S.cnbr_cap || (S.sc->err & ERR_CNBR)) {
         if (c == 0) atomicOr(&S.sc->err, ERR_CNBR);
         return;
     }
-    int b = S.cnbr_start[c];
-    int room = S.cnbr_start[c + 1] - b;
-    (void)cell_query(S, S.sc, c, search, 1, S.cnbr + b, room);
+    const int b = S.cnbr_start[c];
+    (void)cell_query_serial(S, S.sc, c, search, 1, S.cnbr + b, S.cnbr_start[c + 1] - b);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cnbr_count(const SysDev *Sd, Maps L_maps, double search) {
+    const int cbk = blockIdx.x >> 2;
+    if (cbk >= L_maps.c[L_maps.nsys]) return;
+    const int s = find_sys(L_maps.c, L_maps.nsys, cbk);
+    const SysDev &S = Sd[s];
+    if (!S.sc->rebuild || S.k >= CQ_SERIAL_MIN) return;
+    const int lb = cbk - L_maps.c[s];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int c0 = lb * BLOCK + (blockIdx.x & 3) * WAVE + wv * CQ_WAVE;
+    int m = 0;
+    for (int k = 0; k < CQ_WAVE; ++k) {
+        const int c = c0 + k;
+        if (c >= S.k) break;                       // wavefront-uniform
+        int n = cell_query_wave(S, S.sc, c, search, nullptr, 0);
+        if (n > CNBR_ROW_MAX) {                    // keeps the scanned total inside int32
+            if (lane == 0) atomicOr(&S.sc->err, ERR_CNBR);
+            n = 0;
+        }
+        if (lane == 0) S.cnbr_start[c] = n;
+        m = max(m, n);
+    }
+    __shared__ int s_m[BLOCK / WAVE];
+    if (lane == 0) s_m[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int mm = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+        if (mm > 0) atomicMax(&S.sc->cnbr_maxrow, mm);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cnbr_fill(const SysDev *Sd, Maps L_maps, double search) {
+    const int cbk = blockIdx.x >> 2;
+    if (cbk >= L_maps.c[L_maps.nsys]) return;
+    const int s = find_sys(L_maps.c, L_maps.nsys, cbk);
+    const SysDev &S = Sd[s];
+    if (!S.sc->rebuild || S.k >= CQ_SERIAL_MIN) return;
+    const int lb = cbk - L_maps.c[s];
+    const int wv = threadIdx.x / WAVE;
+    const bool first = lb == 0 && (blockIdx.x & 3) == 0 && threadIdx.x == 0;
+    const int total = S.cnbr_start[S.k];
+    if (first) S.sc->cnbr_total = total;
+    if (total > S.cnbr_cap || (S.sc->err & ERR_CNBR)) {
+        if (first) atomicOr(&S.sc->err, ERR_CNBR);
+        return;
+    }
+    const int c0 = lb * BLOCK + (blockIdx.x & 3) * WAVE + wv * CQ_WAVE;
+    for (int k = 0; k < CQ_WAVE; ++k) {
+        const int c = c0 + k;
+        if (c >= S.k) break;
+        const int b = S.cnbr_start[c];
+        const int room = S.cnbr_start[c + 1] - b;
+        (void)cell_query_wave(S, S.sc, c, search, S.cnbr + b, room);
+    }
 }
 
 void launch_cell_bounds(const LaunchCtx &L) {
@@ -1026,9 +1164,12 @@ void launch_cell_bounds(const LaunchCtx &L) {
 }
 
 void launch_cell_pairs(const LaunchCtx &L) {
-    hipLaunchKernelGGL(k_cnbr_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    if (L.nblk_c == 0) return;
+    hipLaunchKernelGGL(k_cnbr_count_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    hipLaunchKernelGGL(k_cnbr_count, dim3(4 * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
     launch_scan(L, 3);
-    hipLaunchKernelGGL(k_cnbr_fill, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    hipLaunchKernelGGL(k_cnbr_fill_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    hipLaunchKernelGGL(k_cnbr_fill, dim3(4 * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
 }
 
 // ------------------------------------------------------------------ neighbour lists
