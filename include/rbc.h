@@ -185,9 +185,9 @@ rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_
  * and the drift statistics) as a HIP graph captured once per system table and time
  * step (enable = 1), or launch every kernel directly (0).  Cell updates always
  * launch directly, with grids covering only the systems that rebuild.  Results are
- * identical either way.  Default: on for ensembles, off for single-system contexts.
- * Graphs are not used while force timing is enabled.  Synchronises the library
- * stream. */
+ * identical either way.  Default: off (the step is two launches, and a graph launch
+ * costs the host more than the two direct ones).  Graphs are not used while force
+ * timing is enabled.  Synchronises the library stream. */
 rbc_status rbc_set_graphs(rbc_handle h, int32_t enable);
 
 /* Internal cell-list arrays of the single system, for inspection and tests (sync).

@@ -368,6 +368,27 @@ __device__ __forceinline__ void drift_stats(const SysDev &S, int blk, double dis
     }
 }
 
+// The end of a drift's statistics pass over one system, run once by whichever
+// block finishes last: the maxima (every block's atomic max is in) go to the host
+// ring entry of this drift number, tag last, and the drift is counted.
+__device__ __forceinline__ void publish_drift(SysScal *sc, StepStat *hstat) {
+    const unsigned long long st = sc->step;
+    const unsigned long long d = atomicOr(&sc->maxdisp2, 0ull);
+    const unsigned long long v = atomicOr(&sc->maxv2, 0ull);
+    StepStat *e = hstat + st % STAT_RING;
+    e->d2 = bitsd(d);
+    e->v2 = bitsd(v);
+    __threadfence_system();
+    e->tag = st + 1;
+    sc->step = st + 1;
+}
+
+__device__ __forceinline__ void swap_drift(SysDev &W) {
+    D4 *t = W.pos; W.pos = W.pos2; W.pos2 = t;
+    t = W.ori; W.ori = W.ori2; W.ori2 = t;
+    F4 *f = W.ori32; W.ori32 = W.ori32b; W.ori32b = f;
+}
+
 // ------------------------------------------------------------------ force kernel
 
 // LDS stage per 256-particle block (structure of arrays): FP64 positions, and either
@@ -735,11 +756,12 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
 }
 
 // Largest displacement since the last build and largest drift speed, per system,
-// from the per-wavefront (displacement, speed) partials of the drift, which form
-// one pair per 64-particle chunk.  STATS_BLOCKS blocks per system fold their share
-// with an unsigned atomic max on the bits (non-negative doubles order like their
-// bit patterns).  swap: the drift wrote the second position / orientation buffers,
-// which become the current ones.
+// from the per-wavefront (displacement, speed) partials of a drift, one pair per
+// 64-particle chunk.  STATS_BLOCKS blocks per system fold their share with an
+// unsigned atomic max on the bits (non-negative doubles order like their bit
+// patterns); the last one publishes the result.  swap: after the drift fused into
+// the force kernel, which wrote the second position / orientation buffers; the last
+// block swaps them in.
 constexpr int STATS_BLOCKS = 16;
 
 __global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int swap) {
@@ -767,11 +789,12 @@ __global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int 
             atomicMax(&sc->maxdisp2, dbits(d));
             atomicMax(&sc->maxv2, dbits(v));
         }
-        if (part == 0) sc->step++;   // one drift per statistics pass
-        if (swap && part == 0) {
-            D4 *t = S.pos; S.pos = S.pos2; S.pos2 = t;
-            t = S.ori; S.ori = S.ori2; S.ori2 = t;
-            F4 *f = S.ori32; S.ori32 = S.ori32b; S.ori32b = f;
+        __threadfence();
+        if (atomicAdd(&sc->parts_done, 1u) == STATS_BLOCKS - 1) {
+            __threadfence();
+            publish_drift(sc, S.hstat);
+            sc->parts_done = 0;
+            if (swap) swap_drift(S);
         }
     }
 }

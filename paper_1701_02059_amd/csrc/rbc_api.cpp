@@ -47,6 +47,7 @@ struct HostSys {
     int64_t early = 0;               // list-only rebuilds forced by the skin between cell updates
     bool have_stats = false, rebuilt_last = false;
     double disp2 = 0.0, v2 = 0.0;
+    uint64_t drifts = 0;             // statistics passes since loading (the device's step counter)
 };
 
 struct Carve {
@@ -79,6 +80,7 @@ struct rbc_ctx {
     int32_t *d_umaps = nullptr;       // block maps of the systems in the running cell update
     const int32_t **d_lip = nullptr;
     SysScal *h_ring = nullptr;
+    StepStat *h_stat = nullptr, *d_stat = nullptr;   // published drift statistics: host / device view
     hipEvent_t ring_ev[RING] = {};
     int64_t ring_pos = 0;
     LaunchCtx L{};
@@ -298,6 +300,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
             lips[s] = hs.lip;
         }
         d.sc = h->d_sc + s;
+        d.hstat = h->d_stat + (size_t)s * STAT_RING;
         tab[s] = d;
         const int64_t n = hs.live ? hs.n : 0;
         const int32_t k = hs.live ? hs.k : 0;
@@ -534,10 +537,9 @@ bool ensure_graphs(rbc_ctx *h, double dt) {
 }
 
 // The drift of every step but the first is fused into the previous step's force
-// kernel, which wrote the second position / orientation buffers; the stats kernel
-// swaps them in on the device, and the host mirror follows.
-void swap_drift_buffers(rbc_ctx *h, bool launch) {
-    if (launch) launch_drift_stats_swap(h->L);
+// kernel, which wrote the second position / orientation buffers; the statistics
+// kernel swaps them in on the device, and the host mirror follows.
+void swap_drift_buffers(rbc_ctx *h) {
     for (auto &hs : h->sys)
         if (hs.live) {
             std::swap(hs.dev.pos, hs.dev.pos2);
@@ -562,8 +564,8 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         const bool last = st + 1 == nsteps;
         const int slot = (int)(h->ring_pos % RING);
         h->ring_pos++;
-        SysScal *ring = h->h_ring + (size_t)slot * MAX_SLOTS;
-        hipMemcpyAsync(ring, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st);
+        // the statistics of the drift to this step's positions are published when
+        // this event completes
         hipEventRecord(h->ring_ev[slot], h->st);
         // decide, from the previous step's statistics, which systems update their cells
         // (every K steps) and which only rebuild their lists (the skin is running out)
@@ -590,21 +592,26 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         run_lists(h, lists);
         if (graphs) {
             hipGraphLaunch(last ? h->g_last : h->g_step, h->st);
-            if (!last) swap_drift_buffers(h, false);
         } else {
             force_launch(h, 0, last ? 1 : 2, dt);
-            if (!last) swap_drift_buffers(h, true);
+            if (!last) launch_drift_stats_swap(h->L);
         }
-        // while the force runs, read this step's kick-drift statistics
+        if (!last) swap_drift_buffers(h);
+        // while the force runs, read this step's drift statistics
         hipEventSynchronize(h->ring_ev[slot]);
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
             if (!hs.live) continue;
             const bool rebuilt = std::find(which.begin(), which.end(), s) != which.end();
-            double d2;
-            std::memcpy(&d2, &ring[s].maxdisp2, sizeof(double));
-            double v2;
-            std::memcpy(&v2, &ring[s].maxv2, sizeof(double));
+            double d2 = 0.0, v2 = 0.0;
+            if (hs.n > 0) {
+                const volatile StepStat &e = h->h_stat[(size_t)s * STAT_RING + hs.drifts % STAT_RING];
+                if (e.tag != hs.drifts + 1 && out == RBC_OK)
+                    out = fail(h, RBC_ERR_HIP, "drift statistics out of sequence (slot " + std::to_string(s) + ")");
+                d2 = e.d2;
+                v2 = e.v2;
+                hs.drifts++;
+            }
             if (!rebuilt && d2 > skin * skin && out == RBC_OK)
                 out = fail(h, RBC_ERR_SKIN, "a particle moved beyond the skin before its lists were rebuilt (slot " + std::to_string(s) + ")");
             hs.disp2 = d2;
@@ -613,7 +620,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             hs.rebuilt_last = rebuilt;
             hs.steps_total++;
         }
-        if (h->tcount >= (int)h->tb.size()) {
+        if (h->timing && h->tcount >= (int)h->tb.size()) {   // the timing events are all in use
             HIPCHK(hipStreamSynchronize(h->st));
             harvest_timing(h);
         }
@@ -725,6 +732,7 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
     HIPCHK(hipMemcpy(fresh.lip, lip.data(), sizeof(int32_t) * lip.size(), hipMemcpyHostToDevice));
     SysScal zero{};
     HIPCHK(hipMemcpy(h->d_sc + slot, &zero, sizeof(SysScal), hipMemcpyHostToDevice));
+    std::memset(h->h_stat + (size_t)slot * STAT_RING, 0, sizeof(StepStat) * STAT_RING);
     hs = fresh;
     h->vol_fresh = false;
     h->used += (int64_t)bytes;
@@ -778,7 +786,7 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
     h->max_slots = max_slots;
     h->budget = budget;
     h->ensemble = ensemble;
-    h->graphs = ensemble;
+    h->graphs = false;               // direct launches measured faster; rbc_set_graphs opts in
     h->sys.resize(max_slots);
     h->user = (hipStream_t)stream;
     hipGetDevice(&h->device);
@@ -790,7 +798,11 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipMalloc(&h->d_maps, sizeof(int32_t) * 7 * (max_slots + 1)) == hipSuccess &&
               hipMalloc(&h->d_umaps, sizeof(int32_t) * 7 * (MAX_SLOTS + 1)) == hipSuccess &&
               hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
-              hipHostMalloc((void **)&h->h_ring, sizeof(SysScal) * MAX_SLOTS * RING, hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc((void **)&h->h_ring, sizeof(SysScal) * MAX_SLOTS * RING, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void **)&h->h_stat, sizeof(StepStat) * MAX_SLOTS * STAT_RING,
+                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+              hipHostGetDevicePointer((void **)&h->d_stat, h->h_stat, 0) == hipSuccess;
+    if (ok) std::memset(h->h_stat, 0, sizeof(StepStat) * MAX_SLOTS * STAT_RING);
     for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->ring_ev[q], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemset(h->d_sc, 0, sizeof(SysScal) * max_slots) == hipSuccess;
     if (ok) ok = refresh_tables(h) == RBC_OK;
@@ -851,6 +863,7 @@ rbc_status rbc_destroy(rbc_handle h) {
     if (h->d_umaps) hipFree(h->d_umaps);
     if (h->d_lip) hipFree(h->d_lip);
     if (h->h_ring) hipHostFree(h->h_ring);
+    if (h->h_stat) hipHostFree(h->h_stat);
     if (h->ev_in) hipEventDestroy(h->ev_in);
     if (h->ev_out) hipEventDestroy(h->ev_out);
     if (h->st) hipStreamDestroy(h->st);

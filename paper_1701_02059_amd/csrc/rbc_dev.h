@@ -61,6 +61,18 @@ struct alignas(256) SysScal {
     double volU;                      // U_V
     double xbar[3], nbar[3];          // lipid centroid and mean orientation
     unsigned long long step;          // drifts done since loading: numbers the thermostat's draws
+    uint32_t parts_done;              // statistics blocks finished in the running pass
+    uint32_t pad3;
+};
+
+// Drift statistics published to pinned host memory, one ring of STAT_RING entries
+// per system indexed by the drift number: the host reads them without a copy.
+constexpr int STAT_RING = 8;
+struct alignas(32) StepStat {
+    double d2;                        // largest |x - x_build|^2 since the last build
+    double v2;                        // largest |v|^2 used in a drift since the build
+    unsigned long long tag;           // drift number + 1, written last (0: never written)
+    unsigned long long pad;
 };
 
 // One system (slot): sizes and device arrays.  Particle arrays are in cell-sorted
@@ -100,6 +112,7 @@ struct SysDev {
     double *bred;                                   // per particle block: BRED partials (stats, bounding box)
     int32_t *tsum;                                  // segmented-scan tile sums
     SysScal *sc;
+    StepStat *hstat;                                // this system's ring in pinned host memory
 };
 
 // Model constants, passed by value to kernels.
