@@ -195,7 +195,7 @@ def structure_run(R, mp, warmup, steps=1000):
     return r
 
 
-def serving_run(R, mp, count, rate, steps, saturated=False):
+def serving_run(R, mp, count, rate, steps, saturated=False, graphs=False):
     from paper_1701_02059_amd import inputs as I
     from paper_1701_02059_amd import serving as SV
     reqs = I.serving_requests(count, rate=rate, steps=steps)
@@ -207,10 +207,11 @@ def serving_run(R, mp, count, rate, steps, saturated=False):
     log(f"[serving] built {count} requests in {time.perf_counter() - t0:.1f} s "
         f"({sum(s.N for s in systems.values()):,} particles)")
     ens = R.Ensemble(mp, R.RBC_MIXED, max_slots=128, hbm_budget=96 << 30)
+    ens.set_graphs(graphs)
     st = SV.serve(reqs, systems, ens, dt=DT, chunk=10)
     ens.close()
     s = st.summary()
-    log(f"[serving{' saturated' if saturated else ''}] {s}")
+    log(f"[serving{' saturated' if saturated else ''}{' graphs' if graphs else ''}] {s}")
     return s
 
 
@@ -317,6 +318,10 @@ def main():
         smp = I.ModelParams(skin=args.skin)
         serving = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps)
         serving["saturated"] = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps, saturated=True)
+        # the same arrivals with the step replayed as a HIP graph (direct launches are the default)
+        g = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps, graphs=True)
+        serving["graph_replay"] = {k: g[k] for k in ("step_latency_ms_p50", "step_latency_ms_p99",
+                                                     "throughput_busy", "calls")}
 
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20

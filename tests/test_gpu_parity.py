@@ -300,6 +300,37 @@ def test_ensemble_failed_admission_leaves_others(R, mp):
     e.close()
 
 
+def test_ensemble_slot_reuse_restarts_step_statistics(R, mp):
+    """A slot freed by a retirement and taken by a new system starts its drift
+    numbering (thermostat draws, published step statistics) afresh: the new system's
+    trajectory with early list rebuilds equals its run alone, and the resident
+    neighbour's is undisturbed."""
+    import dataclasses
+    m = dataclasses.replace(mp, kT=0.22, gamma=0.5, gamma_rot=0.5, seed=7)
+    first = I.build_request({"kind": "vesicle", "nL": 3000, "seed": 51})
+    second = I.build_request({"kind": "patch", "nL": 2500, "seed": 52})
+    other = I.build_request({"kind": "vesicle", "nL": 4000, "seed": 53})
+    refs = []
+    for s in (second, other):
+        e = R.Ensemble(m, R.RBC_MIXED, max_slots=4)
+        a = e.admit(s)
+        e.step(60 if s is other else 40, 0.01)
+        refs.append([to_np(t) for t in e.get_state(a)])
+        e.close()
+    e = R.Ensemble(m, R.RBC_MIXED, max_slots=4)
+    a = e.admit(first)
+    b = e.admit(other)
+    e.step(20, 0.01)
+    e.retire(a)
+    c = e.admit(second)
+    assert c == a
+    e.step(40, 0.01)
+    for ref, slot in zip(refs, (c, b)):
+        for x, y in zip(ref, (to_np(t) for t in e.get_state(slot))):
+            assert np.array_equal(x, y)
+    e.close()
+
+
 def test_ensemble_budget_admission(R, mp):
     s = I.build_request({"kind": "vesicle", "nL": 4000, "seed": 5})
     probe = R.Ensemble(mp, R.RBC_MIXED, max_slots=2)
