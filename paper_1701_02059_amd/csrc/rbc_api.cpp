@@ -79,10 +79,10 @@ struct rbc_ctx {
     int32_t *d_maps = nullptr;
     int32_t *d_umaps = nullptr;       // block maps of the systems in the running cell update
     const int32_t **d_lip = nullptr;
-    SysScal *h_ring = nullptr;
+    SysScal *h_sc = nullptr;          // pinned mirror of the per-system scalars (read after a sync)
     StepStat *h_stat = nullptr, *d_stat = nullptr;   // published drift statistics: host / device view
-    hipEvent_t ring_ev[RING] = {};
-    int64_t ring_pos = 0;
+    hipEvent_t step_ev[RING] = {};    // one per step in flight: the drift statistics are published
+    int64_t step_pos = 0;
     LaunchCtx L{};
     int32_t nsys = 0;                 // descriptors in use (highest live slot + 1)
     bool forces_valid = false;
@@ -456,9 +456,9 @@ rbc_status read_errors(rbc_ctx *h, const SysScal *sc) {
 rbc_status sync_and_check(rbc_ctx *h) {
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) return fail(h, RBC_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(le));
-    HIPCHK(hipMemcpyAsync(h->h_ring, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
-    return read_errors(h, h->h_ring);
+    return read_errors(h, h->h_sc);
 }
 
 void force_launch(rbc_ctx *h, int energy, int kick, double dt) {
@@ -562,11 +562,11 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     h->vol_fresh = true;              // every drift also writes the volume's lipid sums
     for (int64_t st = 0; st < nsteps; ++st) {
         const bool last = st + 1 == nsteps;
-        const int slot = (int)(h->ring_pos % RING);
-        h->ring_pos++;
+        const int slot = (int)(h->step_pos % RING);
+        h->step_pos++;
         // the statistics of the drift to this step's positions are published when
         // this event completes
-        hipEventRecord(h->ring_ev[slot], h->st);
+        hipEventRecord(h->step_ev[slot], h->st);
         // decide, from the previous step's statistics, which systems update their cells
         // (every K steps) and which only rebuild their lists (the skin is running out)
         std::vector<int> which, full, lists;
@@ -598,7 +598,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         }
         if (!last) swap_drift_buffers(h);
         // while the force runs, read this step's drift statistics
-        hipEventSynchronize(h->ring_ev[slot]);
+        hipEventSynchronize(h->step_ev[slot]);
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
             if (!hs.live) continue;
@@ -798,12 +798,12 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipMalloc(&h->d_maps, sizeof(int32_t) * 7 * (max_slots + 1)) == hipSuccess &&
               hipMalloc(&h->d_umaps, sizeof(int32_t) * 7 * (MAX_SLOTS + 1)) == hipSuccess &&
               hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
-              hipHostMalloc((void **)&h->h_ring, sizeof(SysScal) * MAX_SLOTS * RING, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void **)&h->h_sc, sizeof(SysScal) * MAX_SLOTS, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void **)&h->h_stat, sizeof(StepStat) * MAX_SLOTS * STAT_RING,
                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
               hipHostGetDevicePointer((void **)&h->d_stat, h->h_stat, 0) == hipSuccess;
     if (ok) std::memset(h->h_stat, 0, sizeof(StepStat) * MAX_SLOTS * STAT_RING);
-    for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->ring_ev[q], hipEventDisableTiming) == hipSuccess;
+    for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->step_ev[q], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemset(h->d_sc, 0, sizeof(SysScal) * max_slots) == hipSuccess;
     if (ok) ok = refresh_tables(h) == RBC_OK;
     if (!ok) {
@@ -856,13 +856,13 @@ rbc_status rbc_destroy(rbc_handle h) {
     }
     for (auto e : h->tb) hipEventDestroy(e);
     for (auto e : h->te) hipEventDestroy(e);
-    for (int q = 0; q < RING; ++q) if (h->ring_ev[q]) hipEventDestroy(h->ring_ev[q]);
+    for (int q = 0; q < RING; ++q) if (h->step_ev[q]) hipEventDestroy(h->step_ev[q]);
     if (h->d_sys) hipFree(h->d_sys);
     if (h->d_sc) hipFree(h->d_sc);
     if (h->d_maps) hipFree(h->d_maps);
     if (h->d_umaps) hipFree(h->d_umaps);
     if (h->d_lip) hipFree(h->d_lip);
-    if (h->h_ring) hipHostFree(h->h_ring);
+    if (h->h_sc) hipHostFree(h->h_sc);
     if (h->h_stat) hipHostFree(h->h_stat);
     if (h->ev_in) hipEventDestroy(h->ev_in);
     if (h->ev_out) hipEventDestroy(h->ev_out);
@@ -1016,14 +1016,14 @@ static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
     }
     rbc_status r = sync_and_check(h);
     if (r != RBC_OK) return r;
-    const double *e = h->h_ring[slot].energy;
+    const double *e = h->h_sc[slot].energy;
     out[0] = e[0];
     out[1] = e[1];
     out[2] = e[2];
     out[3] = e[0] + e[2];
     out[4] = std::sqrt(e[3] * e[3] + e[4] * e[4] + e[5] * e[5]);
     out[5] = std::sqrt(e[6] * e[6] + e[7] * e[7] + e[8] * e[8]);
-    out[6] = h->h_ring[slot].volV;
+    out[6] = h->h_sc[slot].volV;
     return RBC_OK;
 }
 
@@ -1047,8 +1047,8 @@ rbc_status rbc_stats(rbc_handle h, int64_t *out) {
     out[1] = hs.rebuilds;
     out[2] = hs.early;
     out[3] = hs.k;
-    out[4] = h->h_ring[0].nlrows;
-    out[5] = h->h_ring[0].cnbr_maxrow;
+    out[4] = h->h_sc[0].nlrows;
+    out[5] = h->h_sc[0].cnbr_maxrow;
     out[6] = hs.n;
     out[7] = hs.nlip;
     out[8] = hs.kl;
@@ -1106,7 +1106,7 @@ rbc_status rbc_debug_array(rbc_handle h, int32_t which, int64_t cap, void *out, 
     rbc_status r = sync_and_check(h);
     if (r != RBC_OK && r != RBC_ERR_CAPACITY) return r;
     const SysDev &d = hs.dev;
-    const SysScal &sc = h->h_ring[0];
+    const SysScal &sc = h->h_sc[0];
     const void *src = nullptr;
     int64_t nb = 0;
     int32_t total = 0;
