@@ -354,14 +354,13 @@ __device__ __forceinline__ void volume_term(const SysScal *sc, const D4 &x, cons
 }
 
 // Per-wavefront drift statistics: the largest |x - x_build|^2 and |v|^2 of the
-// wave's particles go to the block's partial slots 2w and 2w+1; a non-finite
-// state raises the system's error bit.
-__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, double disp2, double v2, bool bad) {
+// wave's particles (chunk w of the particle block) go to the block's partial slots
+// 2w and 2w+1; a non-finite state raises the system's error bit.
+__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, int w, double disp2, double v2, bool bad) {
     disp2 = wave_max_lane63(disp2);
     v2 = wave_max_lane63(v2);
     const unsigned long long anybad = __ballot(bad);
     if (lane_id_f() == WAVE - 1) {
-        const int w = (threadIdx.x >> 6) & 3;
         S.bred[(size_t)blk * BRED + 2 * w] = disp2;
         S.bred[(size_t)blk * BRED + 2 * w + 1] = v2;
         if (anybad) atomicOr(&S.sc->err, ERR_NONFINITE);
@@ -424,13 +423,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     F4 *s_n4 = reinterpret_cast<F4 *>(s_z + SL);                  // mixed
     double *s_nx = s_z + SL, *s_ny = s_nx + SL, *s_nz = s_ny + SL;        // FP64
     unsigned char *s_t = reinterpret_cast<unsigned char *>(s_nz + SL);    // FP64
-    const int s = find_sys(L_maps.p, L_maps.nsys, blockIdx.x);
+    const int s = find_sys(L_maps.f, L_maps.nsys, blockIdx.x);
     const SysDev &S = Sd[s];
-    const int lb = blockIdx.x - L_maps.p[s];
+    const int fb = blockIdx.x - L_maps.f[s];
+    // a split system's particle block runs as four blocks, one per chunk, whose four
+    // waves take every fourth row of that chunk (block-uniform)
+    const bool split = S.split != 0;
+    const int lb = split ? fb >> 2 : fb;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
-    const int chunk = lb * (BLOCK / WAVE) + (tid >> 6);
-    const int i = lb * BLOCK + tid;
+    const int csub = split ? (fb & 3) : (tid >> 6);   // the chunk within the particle block
+    const int chunk = lb * (BLOCK / WAVE) + csub;
+    const int i = lb * BLOCK + csub * WAVE + lane;
     const bool valid = i < S.n;
     const int scnt = S.scount[lb];
     const int nlds = min(scnt, SL);                 // stage entries held in LDS
@@ -469,16 +473,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     // dynamic indexing; the periodic min-image only where the system has periodic axes
     const double rcA = P.rc2[ti][0], rcB = P.rc2[ti][1], rcC = P.rc2[ti][2];
     const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
-    auto staged_rows = [&](auto per_tag, auto part_tag) {
+    auto staged_rows = [&](auto per_tag, auto part_tag, auto split_tag) {
         constexpr bool PER = decltype(per_tag)::value;
         constexpr bool PARTIAL = decltype(part_tag)::value;   // stage entries beyond the LDS part
+        constexpr bool SPLIT = decltype(split_tag)::value;    // this wave takes every fourth row
+        constexpr int rstep = SPLIT ? BLOCK / WAVE : 1;
+        const int r0 = SPLIT ? (tid >> 6) : 0;
         // Software pipeline: the list entry of row r+4 is fetched from global memory and
         // the stage record of row r+1 from LDS while row r is evaluated.
-        const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + lane;
-        int e_cur = (valid && rows > 0) ? (int)ldg(col) : 0xffff;
-        int e_nxt = (valid && rows > 1) ? (int)ldg(col + CHUNK) : 0xffff;
-        int e_n2 = (valid && rows > 2) ? (int)ldg(col + 2 * CHUNK) : 0xffff;
-        int e_n3 = (valid && rows > 3) ? (int)ldg(col + 3 * CHUNK) : 0xffff;
+        const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + r0 * CHUNK + lane;
+        const int cstep = rstep * CHUNK;
+        const int nr = rows > r0 ? (rows - r0 + rstep - 1) / rstep : 0;   // this wave's rows
+        int e_cur = (valid && nr > 0) ? (int)ldg(col) : 0xffff;
+        int e_nxt = (valid && nr > 1) ? (int)ldg(col + cstep) : 0xffff;
+        int e_n2 = (valid && nr > 2) ? (int)ldg(col + 2 * cstep) : 0xffff;
+        int e_n3 = (valid && nr > 3) ? (int)ldg(col + 3 * cstep) : 0xffff;
         struct Rec {
             double x, y, z;
             T nx, ny, nz;
@@ -517,13 +526,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             return c;
         };
         Rec rec = fetch(e_cur);
-        for (int r = 0; r < rows; ++r) {
+        for (int r = 0; r < nr; ++r) {
             const int e = e_cur;
             const Rec c = rec;
             e_cur = e_nxt;
             e_nxt = e_n2;
             e_n2 = e_n3;
-            e_n3 = (valid && r + 4 < rows) ? (int)ldg(col + (r + 4) * CHUNK) : 0xffff;
+            e_n3 = (valid && r + 4 < nr) ? (int)ldg(col + (r + 4) * cstep) : 0xffff;
             rec = fetch(e_cur);
             if (e >= scnt) continue;
             const int tj = c.t;
@@ -553,17 +562,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     if (scnt >= 0) {
         // block-uniform choices: periodic min-image, and (mixed mode) whether the stage
         // overflows the LDS part, so ordinary blocks carry no per-entry test
+        auto rows_by_split = [&](auto per_tag, auto part_tag) {
+            if (split) staged_rows(per_tag, part_tag, std::true_type{});
+            else staged_rows(per_tag, part_tag, std::false_type{});
+        };
         if (SL < SMAX && scnt > SL) {
-            if (periodic) staged_rows(std::true_type{}, std::integral_constant<bool, SL < SMAX>{});
-            else staged_rows(std::false_type{}, std::integral_constant<bool, SL < SMAX>{});
+            if (periodic) rows_by_split(std::true_type{}, std::integral_constant<bool, SL < SMAX>{});
+            else rows_by_split(std::false_type{}, std::integral_constant<bool, SL < SMAX>{});
         } else {
-            if (periodic) staged_rows(std::true_type{}, std::false_type{});
-            else staged_rows(std::false_type{}, std::false_type{});
+            if (periodic) rows_by_split(std::true_type{}, std::false_type{});
+            else rows_by_split(std::false_type{}, std::false_type{});
         }
     } else {
         // block whose partners did not fit the stage: the lists hold global slots
         const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
-        for (int r = 0; r < rows; ++r) {
+        const int r0 = split ? (tid >> 6) : 0, rstep = split ? BLOCK / WAVE : 1;
+        for (int r = r0; r < rows; r += rstep) {
             const int j = valid ? col[r * CHUNK] : -1;
             if (j < 0 || j >= S.n) continue;
             const D4 pj = S.pos[j];
@@ -587,6 +601,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 U += 0.5 * (double)u;
                 W += 0.5 * (dx * (double)ax + dy * (double)ay + dz * (double)az);
             }
+        }
+    }
+    if (split) {
+        // the four waves' partial sums, added in wave order by wave 0, which goes on
+        // with the chunk's particles; the stage is free again
+        __syncthreads();
+        T *red = reinterpret_cast<T *>(s_raw);
+        double *redd = reinterpret_cast<double *>(s_raw + 6 * BLOCK * sizeof(T));
+        const int wv = tid >> 6;
+        const T mine[6] = {fx, fy, fz, tx, ty, tz};
+        for (int q = 0; q < 6; ++q) red[q * BLOCK + wv * WAVE + lane] = mine[q];
+        if (ENERGY) {
+            redd[wv * WAVE + lane] = U;
+            redd[BLOCK + wv * WAVE + lane] = W;
+        }
+        __syncthreads();
+        if (wv != 0) return;
+        T sum[6];
+        for (int q = 0; q < 6; ++q)
+            sum[q] = ((red[q * BLOCK + lane] + red[q * BLOCK + WAVE + lane]) + red[q * BLOCK + 2 * WAVE + lane]) +
+                     red[q * BLOCK + 3 * WAVE + lane];
+        fx = sum[0]; fy = sum[1]; fz = sum[2];
+        tx = sum[3]; ty = sum[4]; tz = sum[5];
+        if (ENERGY) {
+            U = ((redd[lane] + redd[WAVE + lane]) + redd[2 * WAVE + lane]) + redd[3 * WAVE + lane];
+            W = ((redd[BLOCK + lane] + redd[BLOCK + WAVE + lane]) + redd[BLOCK + 2 * WAVE + lane]) +
+                redd[BLOCK + 3 * WAVE + lane];
         }
     }
     double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
@@ -656,7 +697,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         }
     }
     if (KICK == 2) {
-        drift_stats(S, lb, disp2, vmax2, bad);
+        drift_stats(S, lb, csub, disp2, vmax2, bad);
         if (P.vol_on) volume_chunk_store(S, chunk, vsum);
     }
     if (ENERGY) {
@@ -687,10 +728,10 @@ template <int MIXED, int ENERGY, int KICK>
 static void launch_force_t(const LaunchCtx &L, double dt) {
     const bool fast = L.prm.zeta == 4 && L.prm.st0 == 0.0;
     if (fast)
-        hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 1>), dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
+        hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 1>), dim3(L.nblk_f), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
                            dt);
     else
-        hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 0>), dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
+        hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 0>), dim3(L.nblk_f), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
                            dt);
 }
 
@@ -751,7 +792,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
         }
         drift_measures(p, v, S.xb[i], disp2, v2, bad);
     }
-    drift_stats(S, lb, disp2, v2, bad);
+    drift_stats(S, lb, (threadIdx.x >> 6) & 3, disp2, v2, bad);
     if (P.vol_on && i / CHUNK < S.nchunk) volume_chunk_store(S, i / CHUNK, vsum);
 }
 

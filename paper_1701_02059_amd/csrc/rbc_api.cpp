@@ -289,9 +289,9 @@ rbc_status refresh_tables(rbc_ctx *h) {
     const int ns = h->nsys;
     std::vector<SysDev> tab(ns);
     std::vector<const int32_t *> lips(ns, nullptr);
-    std::vector<int32_t> maps(7 * (ns + 1), 0);
+    std::vector<int32_t> maps(8 * (ns + 1), 0);
     int32_t *mp = maps.data(), *mc = mp + (ns + 1), *mg = mc + (ns + 1), *mtp = mg + (ns + 1), *mts = mtp + (ns + 1);
-    int32_t *msc = mts + (ns + 1), *msg = msc + (ns + 1);
+    int32_t *msc = mts + (ns + 1), *msg = msc + (ns + 1), *mf = msg + (ns + 1);
     for (int s = 0; s < ns; ++s) {
         HostSys &hs = h->sys[s];
         SysDev d{};
@@ -311,6 +311,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
         mts[s + 1] = mts[s] + (hs.live ? hs.ntile_s : 0);
         msc[s + 1] = msc[s] + (k + SCAN_TILE - 1) / SCAN_TILE;
         msg[s + 1] = msg[s] + (hs.live ? (hs.gcap + SCAN_TILE - 1) / SCAN_TILE : 0);
+        mf[s + 1] = mf[s] + (mp[s + 1] - mp[s]) * (d.split ? 4 : 1);
     }
     HIPCHK(hipMemcpyAsync(h->d_sys, tab.data(), sizeof(SysDev) * ns, hipMemcpyHostToDevice, h->st));
     HIPCHK(hipMemcpyAsync(h->d_maps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice, h->st));
@@ -327,6 +328,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
     L.maps.ts = h->d_maps + 4 * (ns + 1);
     L.maps.sc = h->d_maps + 5 * (ns + 1);
     L.maps.sg = h->d_maps + 6 * (ns + 1);
+    L.maps.f = h->d_maps + 7 * (ns + 1);
     L.maps.nsys = ns;
     L.nblk_p = mp[ns];
     L.nblk_c = mc[ns];
@@ -335,6 +337,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
     L.nblk_ts = mts[ns];
     L.nblk_sc = msc[ns];
     L.nblk_sg = msg[ns];
+    L.nblk_f = mf[ns];
     L.nsys = ns;
     L.prm = h->dprm;
     L.st = h->st;
@@ -707,6 +710,7 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
     d.kl = fresh.kl;
     d.nsrcp = (int32_t)fresh.nsrcp;
     d.nchunk = fresh.nchunk;
+    d.split = (n + BLOCK - 1) / BLOCK <= SPLIT_MAX_BLOCKS;
     d.gcap = fresh.gcap;
     d.cnbr_cap = fresh.cnbr_cap;
     d.ntile_p = fresh.ntile_p;
@@ -795,7 +799,7 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(&h->d_sys, sizeof(SysDev) * max_slots) == hipSuccess &&
               hipMalloc(&h->d_sc, sizeof(SysScal) * max_slots) == hipSuccess &&
-              hipMalloc(&h->d_maps, sizeof(int32_t) * 7 * (max_slots + 1)) == hipSuccess &&
+              hipMalloc(&h->d_maps, sizeof(int32_t) * 8 * (max_slots + 1)) == hipSuccess &&
               hipMalloc(&h->d_umaps, sizeof(int32_t) * 7 * (MAX_SLOTS + 1)) == hipSuccess &&
               hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
               hipHostMalloc((void **)&h->h_sc, sizeof(SysScal) * MAX_SLOTS, hipHostMallocDefault) == hipSuccess &&

@@ -68,6 +68,11 @@ struct alignas(256) SysScal {
 // Drift statistics published to pinned host memory, one ring of STAT_RING entries
 // per system indexed by the drift number: the host reads them without a copy.
 constexpr int STAT_RING = 8;
+// Systems of at most this many 256-particle blocks run the step kernel with each
+// 64-particle chunk's list rows spread over the four waves of a block (four blocks
+// per particle block): too small to fill the GPU, their step time is one wave's walk
+// over its rows, which this cuts by four.
+constexpr int SPLIT_MAX_BLOCKS = 32;
 struct alignas(32) StepStat {
     double d2;                        // largest |x - x_build|^2 since the last build
     double v2;                        // largest |v|^2 used in a drift since the build
@@ -82,7 +87,7 @@ struct SysDev {
     int32_t per[3];
     int32_t kl;                                     // lipid cells: seeds [0, kl); protein cells: [kl, k)
     int32_t nsrcp;                                  // protein seed sources after the lipid ids in `lip`
-    int32_t pad2;
+    int32_t split;                                  // the step kernel spreads each chunk's rows over four waves
     double box[3];
     D4 *pos, *vel, *ori, *angv, *frc, *trq, *xb;   // pos.w = particle type
     D4 *pos2, *vel2, *ori2, *angv2;
@@ -154,6 +159,7 @@ struct Maps {
     const int32_t *ts;     // seed sort tiles
     const int32_t *sc;     // scan tiles over cells
     const int32_t *sg;     // scan tiles over seed-grid cells
+    const int32_t *f;      // step-kernel blocks (four per particle block of a split system)
     int32_t nsys;
 };
 
@@ -255,7 +261,7 @@ struct LaunchCtx {
     const SysDev *S;         // device array of systems
     SysDev *Sw;              // the same array, for the kernel that swaps the drift buffers
     Maps maps;
-    int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts, nblk_sc, nblk_sg;   // totals over systems
+    int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts, nblk_sc, nblk_sg, nblk_f;   // totals over systems
     int32_t nsys;
     DevParams prm;
     hipStream_t st;
