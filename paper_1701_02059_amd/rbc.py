@@ -312,7 +312,10 @@ class Ensemble:
 
     def get_state(self, slot: int):
         import torch
-        n = self.sizes[slot]
+        n = self.sizes.get(slot)
+        if n is None:       # not a live slot here: the library reports it
+            _check(self._h, lib().rbc_ensemble_get_state(self._h, int(slot), None, None, None, None))
+            raise RbcError(RBC_ERR_NOT_READY, f"slot {slot} is not live")
         out = [torch.empty((n, 3), dtype=torch.float64, device="cuda") for _ in range(4)]
         _check(self._h, lib().rbc_ensemble_get_state(self._h, int(slot), *[_dev(t) for t in out]))
         return out

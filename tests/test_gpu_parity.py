@@ -331,6 +331,32 @@ def test_ensemble_slot_reuse_restarts_step_statistics(R, mp):
     e.close()
 
 
+def test_ensemble_slot_limits_and_retired_slots(R, mp):
+    """A full slot table refuses admission (None) until a slot is retired; a retired
+    or never-used slot answers every per-slot call with RBC_ERR_NOT_READY, and the
+    live neighbour keeps stepping."""
+    a_sys = I.build_request({"kind": "patch", "nL": 2000, "seed": 61})
+    b_sys = I.build_request({"kind": "vesicle", "nL": 2000, "seed": 62})
+    e = R.Ensemble(mp, R.RBC_MIXED, max_slots=2)
+    a = e.admit(a_sys)
+    b = e.admit(b_sys)
+    assert {a, b} == {0, 1}
+    assert e.admit(a_sys) is None
+    e.step(5, 0.01)
+    e.retire(a)
+    for call in (lambda: e.retire(a), lambda: e.get_state(a), lambda: e.energy(a), lambda: e.retire(5)):
+        with pytest.raises(R.RbcError) as ei:
+            call()
+        assert ei.value.status == R.RBC_ERR_NOT_READY
+    assert e.info()["live"] == 1
+    e.step(5, 0.01)
+    assert np.isfinite(to_np(e.get_state(b)[0])).all()
+    c = e.admit(a_sys)
+    assert c == a
+    e.step(5, 0.01)
+    e.close()
+
+
 def test_ensemble_budget_admission(R, mp):
     s = I.build_request({"kind": "vesicle", "nL": 4000, "seed": 5})
     probe = R.Ensemble(mp, R.RBC_MIXED, max_slots=2)
