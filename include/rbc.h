@@ -220,6 +220,23 @@ rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const do
                               const int32_t *type, const double *v, const double *w,
                               int64_t nbond, const int32_t *bonds, const double *r0,
                               const double *box, const int32_t *periodic, int32_t *slot);
+/* Admission in two phases, for callers that admit several systems at once.
+ * rbc_ensemble_stage validates, allocates and uploads a system exactly as
+ * rbc_ensemble_admit does (same arguments, same errors, *slot receives the slot;
+ * the input arrays may be released on return) but leaves its cell build pending.
+ * rbc_ensemble_commit then builds the cells of every pending slot in one set of
+ * launches: the seeding, Lloyd iterations and reordering of the Voronoi
+ * Tessellation section, then the cell pairs and lists of the Force Evaluation
+ * section.  Each system's result equals that of rbc_ensemble_admit.  A slot whose
+ * build fails (capacity, non-finite input) is released and its index written to
+ * failed[0..min(*nfailed, cap)); rbc_last_error holds the first failure's message,
+ * and commit still returns RBC_OK.  While a slot is pending, rbc_ensemble_step and
+ * rbc_ensemble_energy return RBC_ERR_NOT_READY. */
+rbc_status rbc_ensemble_stage(rbc_handle h, int64_t n, const double *x, const double *nrm,
+                              const int32_t *type, const double *v, const double *w,
+                              int64_t nbond, const int32_t *bonds, const double *r0,
+                              const double *box, const int32_t *periodic, int32_t *slot);
+rbc_status rbc_ensemble_commit(rbc_handle h, int64_t cap, int32_t *failed, int64_t *nfailed);
 /* Advance every live slot by nsteps (sync at the end). */
 rbc_status rbc_ensemble_step(rbc_handle h, int64_t nsteps, double dt);
 /* State of one slot in its caller order ([device] n x 3 each, any may be NULL). */

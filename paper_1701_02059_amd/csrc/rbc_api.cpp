@@ -48,6 +48,7 @@ struct HostSys {
     bool have_stats = false, rebuilt_last = false;
     double disp2 = 0.0, v2 = 0.0;
     uint64_t drifts = 0;             // statistics passes since loading (the device's step counter)
+    bool pending = false;            // staged: uploaded, cells not built yet
 };
 
 struct Carve {
@@ -444,16 +445,28 @@ void lists_body(const LaunchCtx &L) {
     launch_finish_update(L);
 }
 
+// The status and message of one slot's error bits.
+rbc_status slot_error(rbc_ctx *h, int s, int e) {
+    if (e & ERR_NONFINITE) return fail(h, RBC_ERR_NONFINITE, "non-finite positions or velocities in slot " + std::to_string(s));
+    if (e & ERR_NLIST) return fail(h, RBC_ERR_CAPACITY, "a particle has more than 64 neighbours within rc + 2 skin (slot " + std::to_string(s) + ")");
+    if (e & ERR_CNBR) return fail(h, RBC_ERR_CAPACITY, "cell-pair list capacity exceeded (slot " + std::to_string(s) + ")");
+    if (e & ERR_ASSIGN) return fail(h, RBC_ERR_CAPACITY, "nearest-seed search failed (slot " + std::to_string(s) + ")");
+    return RBC_OK;
+}
+
 rbc_status read_errors(rbc_ctx *h, const SysScal *sc) {
     for (int s = 0; s < h->nsys; ++s) {
         if (!h->sys[s].live) continue;
-        int e = sc[s].err;
-        if (e & ERR_NONFINITE) return fail(h, RBC_ERR_NONFINITE, "non-finite positions or velocities in slot " + std::to_string(s));
-        if (e & ERR_NLIST) return fail(h, RBC_ERR_CAPACITY, "a particle has more than 64 neighbours within rc + 2 skin (slot " + std::to_string(s) + ")");
-        if (e & ERR_CNBR) return fail(h, RBC_ERR_CAPACITY, "cell-pair list capacity exceeded (slot " + std::to_string(s) + ")");
-        if (e & ERR_ASSIGN) return fail(h, RBC_ERR_CAPACITY, "nearest-seed search failed (slot " + std::to_string(s) + ")");
+        const rbc_status r = slot_error(h, s, sc[s].err);
+        if (r != RBC_OK) return r;
     }
     return RBC_OK;
+}
+
+bool any_pending(const rbc_ctx *h) {
+    for (const auto &hs : h->sys)
+        if (hs.live && hs.pending) return true;
+    return false;
 }
 
 rbc_status sync_and_check(rbc_ctx *h) {
@@ -643,7 +656,9 @@ size_t footprint(const rbc_ctx *h, int64_t n, int64_t nlip, int64_t nbond) {
 
 void release(rbc_ctx *h, int32_t slot);
 
-rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const double *nrm, const int32_t *type,
+// Everything of an admission but the cell build: validation, allocation, uploads and
+// the packed state.  The slot is live and pending.
+rbc_status stage(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const double *nrm, const int32_t *type,
                  const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
                  const double *box, const int32_t *periodic) {
     if (n < 0 || n > (1ll << 29)) return fail(h, RBC_ERR_INVALID_ARG, "n out of range (at most 2^29 particles)");
@@ -740,27 +755,66 @@ rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
     hs = fresh;
     h->vol_fresh = false;
     h->used += (int64_t)bytes;
+    hs.pending = true;
     rbc_status r = refresh_tables(h);
     if (r != RBC_OK) return r;
     {
         Scope sc(h);
         launch_pack(h->L, slot, x, nrm, type, v, w, (int)n);
-        run_update(h, std::vector<int>{slot}, h->prm.lloyd_iters);
-        hs.steps_since = 0;
-        hs.have_stats = false;
-        hs.updates = 1;
-        hs.rebuilds = 1;
+    }
+    HIPCHK(hipStreamSynchronize(h->st));   // the caller may release its input arrays on return
+    return RBC_OK;
+}
+
+// The initial cell build (seeding and Lloyd iterations, then lists) of the pending
+// slots in `which`, in one set of launches.  Slots whose build fails are released
+// and listed in `failed`; the first failure's status is returned, with its message.
+rbc_status build_pending(rbc_ctx *h, const std::vector<int> &which, std::vector<int> &failed) {
+    if (which.empty()) return RBC_OK;
+    {
+        Scope sc(h);
+        run_update(h, which, h->prm.lloyd_iters);
+        for (int s : which) {
+            HostSys &hs = h->sys[s];
+            hs.pending = false;
+            hs.steps_since = 0;
+            hs.have_stats = false;
+            hs.updates = 1;
+            hs.rebuilds = 1;
+        }
         h->forces_valid = false;
     }
-    rbc_status st = sync_and_check(h);
-    if (st != RBC_OK) {
-        // the initial cell build failed (capacity, non-finite input): the slot is not admitted
-        const std::string why = h->err;
-        release(h, slot);
-        h->err = why;
-        if (h->d_sc) hipMemset(h->d_sc + slot, 0, sizeof(SysScal));
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return fail(h, RBC_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(le));
+    HIPCHK(hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    rbc_status first = RBC_OK;
+    std::string why;
+    for (int s : which) {
+        const rbc_status r = slot_error(h, s, h->h_sc[s].err);
+        if (r == RBC_OK) continue;
+        // the initial cell build failed (capacity, non-finite input): not admitted
+        if (first == RBC_OK) {
+            first = r;
+            why = h->err;
+        }
+        failed.push_back(s);
     }
-    return st;
+    for (int s : failed) {
+        release(h, s);
+        if (h->d_sc) hipMemset(h->d_sc + s, 0, sizeof(SysScal));
+    }
+    if (first != RBC_OK) h->err = why;
+    return first;
+}
+
+rbc_status admit(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const double *nrm, const int32_t *type,
+                 const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
+                 const double *box, const int32_t *periodic) {
+    const rbc_status r = stage(h, slot, n, x, nrm, type, v, w, nbond, bonds, r0, box, periodic);
+    if (r != RBC_OK) return r;
+    std::vector<int> failed;
+    return build_pending(h, std::vector<int>{slot}, failed);
 }
 
 void release(rbc_ctx *h, int32_t slot) {
@@ -929,6 +983,7 @@ rbc_status rbc_step(rbc_handle h, int64_t nsteps, double dt) {
     if (!h) return RBC_ERR_INVALID_ARG;
     if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(h, RBC_ERR_INVALID_ARG, "need nsteps >= 0 and dt > 0");
     if (!any_live(h)) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     rbc_status r;
     {
         Scope sc(h);
@@ -1008,6 +1063,7 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
 
 static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     {
         Scope sc(h);
         if (!h->dprm.vol_on) {                        // V is reported with or without the constraint
@@ -1160,6 +1216,33 @@ rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const do
     if (r == RBC_OK) *slot = free_slot;
     else release(h, free_slot);
     return r;
+}
+
+rbc_status rbc_ensemble_stage(rbc_handle h, int64_t n, const double *x, const double *nrm, const int32_t *type,
+                              const double *v, const double *w, int64_t nbond, const int32_t *bonds, const double *r0,
+                              const double *box, const int32_t *periodic, int32_t *slot) {
+    if (!h || !slot) return RBC_ERR_INVALID_ARG;
+    if (n <= 0) return fail(h, RBC_ERR_INVALID_ARG, "an admitted system needs n > 0");
+    int32_t free_slot = -1;
+    for (int s = 0; s < h->max_slots; ++s)
+        if (!h->sys[s].live) { free_slot = s; break; }
+    if (free_slot < 0) return fail(h, RBC_ERR_CAPACITY, "no free slot");
+    rbc_status r = stage(h, free_slot, n, x, nrm, type, v, w, nbond, bonds, r0, box, periodic);
+    if (r == RBC_OK) *slot = free_slot;
+    else release(h, free_slot);
+    return r;
+}
+
+rbc_status rbc_ensemble_commit(rbc_handle h, int64_t cap, int32_t *failed, int64_t *nfailed) {
+    if (!h || !nfailed || cap < 0 || (cap > 0 && !failed)) return RBC_ERR_INVALID_ARG;
+    std::vector<int> which, bad;
+    for (int s = 0; s < h->max_slots; ++s)
+        if (h->sys[s].live && h->sys[s].pending) which.push_back(s);
+    const rbc_status r = build_pending(h, which, bad);
+    *nfailed = (int64_t)bad.size();
+    for (size_t q = 0; q < bad.size() && (int64_t)q < cap; ++q) failed[q] = bad[q];
+    if (r == RBC_ERR_HIP) return r;
+    return RBC_OK;                                // failed builds are reported through the list
 }
 
 rbc_status rbc_ensemble_retire(rbc_handle h, int32_t slot) {

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from typing import Optional, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -25,7 +25,7 @@ FUNCTIONS = [
     "rbc_get_pairs", "rbc_energy", "rbc_stats", "rbc_get_cells", "rbc_force_timing", "rbc_sync", "rbc_destroy",
     "rbc_status_string", "rbc_last_error", "rbc_ensemble_create", "rbc_ensemble_footprint", "rbc_ensemble_admit",
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
-    "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs",
+    "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs", "rbc_ensemble_stage", "rbc_ensemble_commit",
 ]
 
 
@@ -81,6 +81,8 @@ def lib():
             "rbc_ensemble_create": [pp, vp, C.c_int32, C.c_int64, C.POINTER(h)],
             "rbc_ensemble_footprint": [h, C.c_int64, C.c_int64, C.c_int64, i64p],
             "rbc_ensemble_admit": [h, C.c_int64, vp, vp, vp, vp, vp, C.c_int64, vp, vp, dp, ip, ip],
+            "rbc_ensemble_stage": [h, C.c_int64, vp, vp, vp, vp, vp, C.c_int64, vp, vp, dp, ip, ip],
+            "rbc_ensemble_commit": [h, C.c_int64, ip, i64p],
             "rbc_ensemble_step": [h, C.c_int64, C.c_double],
             "rbc_ensemble_get_state": [h, C.c_int32, vp, vp, vp, vp],
             "rbc_ensemble_energy": [h, C.c_int32, dp],
@@ -291,10 +293,29 @@ class Ensemble:
         """Slot index, or None when no slot or budget is free.  A system that cannot be
         admitted at all (for example, its lists overflow the per-particle capacity)
         raises RbcError."""
+        return self._admit(system, lib().rbc_ensemble_admit)
+
+    def stage(self, system) -> Optional[int]:
+        """As admit, with the cell build left to commit()."""
+        return self._admit(system, lib().rbc_ensemble_stage)
+
+    def commit(self) -> List[int]:
+        """Build the cells of every staged system in one set of launches; returns the
+        slots whose build failed (released; rbc_last_error names the first)."""
+        failed = np.zeros(max(self.max_slots, 1), dtype=np.int32)
+        nf = C.c_int64(0)
+        _check(self._h, lib().rbc_ensemble_commit(self._h, failed.size, failed.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  C.byref(nf)))
+        out = [int(q) for q in failed[:nf.value]]
+        for q in out:
+            self.sizes.pop(q, None)
+        return out
+
+    def _admit(self, system, fn) -> Optional[int]:
         u = _Uploaded(system)
         slot = C.c_int32(-1)
-        st = lib().rbc_ensemble_admit(self._h, u.n, _dev(u.x), _dev(u.nrm), _dev(u.type), _dev(u.v), _dev(u.w),
-                                      u.nbond, _dev(u.bonds), _dev(u.r0), u.box, u.per, C.byref(slot))
+        st = fn(self._h, u.n, _dev(u.x), _dev(u.nrm), _dev(u.type), _dev(u.v), _dev(u.w),
+                u.nbond, _dev(u.bonds), _dev(u.r0), u.box, u.per, C.byref(slot))
         if st == RBC_ERR_CAPACITY:
             info = self.info()
             if info["live"] >= self.max_slots or (

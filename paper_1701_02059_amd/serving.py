@@ -84,16 +84,28 @@ def serve(requests: List[dict], systems: Dict[int, object], executor, dt: float 
         now = clock() - t0
         while pending and pending[0]["arrival"] <= now:
             waiting.append(pending.popleft())
+        # requests that arrived together are staged, and their cells built in one set of
+        # launches, where the executor supports it
+        two_phase = hasattr(executor, "stage") and hasattr(executor, "commit")
+        staged = []
         while waiting:
             req = waiting[0]
-            slot = executor.admit(systems[req["id"]])
+            sys_ = systems[req["id"]]
+            slot = executor.stage(sys_) if two_phase else executor.admit(sys_)
             if slot is None:
-                if not live:
+                if not live and not staged:
                     raise RuntimeError(f"request {req['id']} does not fit on an empty device")
                 break
             waiting.popleft()
-            live[slot] = {"req": req, "left": int(req["steps"]), "n": int(systems[req["id"]].N),
-                          "admitted": clock() - t0}
+            staged.append(slot)
+            live[slot] = {"req": req, "left": int(req["steps"]), "n": int(sys_.N),
+                          "admitted": None if two_phase else clock() - t0}
+        if two_phase and staged:
+            failed = executor.commit()
+            if failed:
+                raise RuntimeError(f"requests {[live[q]['req']['id'] for q in failed]} could not be admitted")
+            for slot in staged:
+                live[slot]["admitted"] = clock() - t0
         max_res = max(max_res, len(live))
         if not live:
             if pending:

@@ -357,6 +357,35 @@ def test_ensemble_slot_limits_and_retired_slots(R, mp):
     e.close()
 
 
+def test_ensemble_staged_admission_equals_admit(R, mp):
+    """Systems staged together and built by one commit end up exactly as when admitted
+    one by one; a staged system whose build fails (list overflow) is released and
+    listed while the others go on; stepping waits for the commit."""
+    import dataclasses
+    mp5 = dataclasses.replace(mp, skin=0.5)
+    systems = [I.build_request({"kind": "patch", "nL": 2500, "seed": 71}),
+               I.build_request({"kind": "vesicle", "nL": 4000, "seed": 72}),
+               I.build_request({"kind": "vesicle", "nL": 9000, "seed": 73})]
+    e = R.Ensemble(mp5, R.RBC_MIXED, max_slots=8)
+    ref_slots = [e.admit(s) for s in systems]
+    e.step(20, 0.01)
+    ref = [[to_np(t) for t in e.get_state(q)] for q in ref_slots]
+    e.close()
+    e = R.Ensemble(mp5, R.RBC_MIXED, max_slots=8)
+    slots = [e.stage(systems[0]), e.stage(_dense_cloud()), e.stage(systems[1]), e.stage(systems[2])]
+    with pytest.raises(R.RbcError) as ei:
+        e.step(1, 0.01)
+    assert ei.value.status == R.RBC_ERR_NOT_READY
+    assert e.commit() == [slots[1]]
+    assert e.info()["live"] == 3
+    e.step(20, 0.01)
+    for want, q in zip(ref, (slots[0], slots[2], slots[3])):
+        for x, y in zip(want, (to_np(t) for t in e.get_state(q))):
+            assert np.array_equal(x, y)
+    assert e.commit() == []              # nothing pending
+    e.close()
+
+
 def test_ensemble_budget_admission(R, mp):
     s = I.build_request({"kind": "vesicle", "nL": 4000, "seed": 5})
     probe = R.Ensemble(mp, R.RBC_MIXED, max_slots=2)
