@@ -108,3 +108,60 @@ def test_summary_fields():
     s = st.summary()
     assert s["requests"] == 10 and s["step_latency_ms_p99"] >= s["step_latency_ms_p50"] > 0
     assert s["throughput_busy"] >= s["throughput_wall"] > 0
+
+
+class TwoPhaseExec(MockExec):
+    """Stages systems and builds them in one commit, like the HIP ensemble's two-phase
+    admission; a commit costs a fixed time whatever the number of systems, and the
+    systems listed in `refuse` fail their build."""
+
+    def __init__(self, clock, slots, budget, refuse=()):
+        super().__init__(clock, slots, budget)
+        self.pending = []
+        self.commits = []
+        self.refuse = set(refuse)
+
+    def admit(self, s):
+        raise AssertionError("a two-phase executor is staged, not admitted")
+
+    def stage(self, s):
+        k = MockExec.admit(self, s)
+        if k is not None:
+            self.pending.append(k)
+        return k
+
+    def commit(self):
+        self.clock.t += 3e-3
+        self.commits.append(list(self.pending))
+        failed = [k for k in self.pending if self.slots[k].N in self.refuse]
+        for k in failed:
+            self.retire(k)
+        self.pending = []
+        return failed
+
+    def step(self, n, dt):
+        assert not self.pending, "stepped with staged systems"
+        super().step(n, dt)
+
+
+def test_two_phase_admission_batches_arrivals():
+    """Requests arriving together are staged and committed once; every request still
+    takes exactly its steps, in arrival order of admission."""
+    reqs = [{"id": i, "arrival": 0.0, "steps": 30} for i in range(12)]
+    systems = {i: FakeSys(1000 + i) for i in range(12)}
+    clk = Clock()
+    ex = TwoPhaseExec(clk, 8, 10 ** 12)
+    st = serving.serve(reqs, systems, ex, chunk=10, clock=clk, sleep=clk.sleep, keep_state=set(range(12)))
+    assert len(st.results) == 12 and all(r.state == 30 for r in st.results)
+    assert ex.commits[0] == list(range(8))              # the first eight in one commit
+    assert sum(len(c) for c in ex.commits) == 12
+    assert all(r.admitted is not None for r in st.results)
+
+
+def test_two_phase_failed_build_raises():
+    reqs = [{"id": i, "arrival": 0.0, "steps": 10} for i in range(3)]
+    systems = {i: FakeSys(1000 + i) for i in range(3)}
+    clk = Clock()
+    ex = TwoPhaseExec(clk, 4, 10 ** 12, refuse={1001})
+    with pytest.raises(RuntimeError):
+        serving.serve(reqs, systems, ex, chunk=10, clock=clk, sleep=clk.sleep)
