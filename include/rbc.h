@@ -230,8 +230,9 @@ rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const do
  * section.  Each system's result equals that of rbc_ensemble_admit.  A slot whose
  * build fails (capacity, non-finite input) is released and its index written to
  * failed[0..min(*nfailed, cap)); rbc_last_error holds the first failure's message,
- * and commit still returns RBC_OK.  While a slot is pending, rbc_ensemble_step and
- * rbc_ensemble_energy return RBC_ERR_NOT_READY. */
+ * and commit still returns RBC_OK.  While a slot is pending, the calls that need
+ * built cells (rbc_ensemble_step, rbc_ensemble_energy, rbc_update_cells, rbc_forces,
+ * rbc_get_pairs, rbc_get_cells) return RBC_ERR_NOT_READY. */
 rbc_status rbc_ensemble_stage(rbc_handle h, int64_t n, const double *x, const double *nrm,
                               const int32_t *type, const double *v, const double *w,
                               int64_t nbond, const int32_t *bonds, const double *r0,

@@ -945,6 +945,7 @@ rbc_status rbc_update_cells(rbc_handle h, int32_t lloyd_iters) {
     if (!h) return RBC_ERR_INVALID_ARG;
     if (lloyd_iters < 0) return fail(h, RBC_ERR_INVALID_ARG, "lloyd_iters must be >= 0");
     if (!any_live(h)) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     std::vector<int> which;
     for (int s = 0; s < h->nsys; ++s)
         if (h->sys[s].live) which.push_back(s);
@@ -976,6 +977,7 @@ static rbc_status forces_slot(rbc_handle h, int32_t slot, double *F, double *T, 
 rbc_status rbc_forces(rbc_handle h, double *F, double *T, double *energy) {
     if (!h) return RBC_ERR_INVALID_ARG;
     if (!h->sys[0].live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     return forces_slot(h, 0, F, T, energy);
 }
 
@@ -1023,6 +1025,7 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
     if (!h || !npairs || cap < 0 || (cap > 0 && !ij)) return RBC_ERR_INVALID_ARG;
     HostSys &hs = h->sys[0];
     if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     int64_t want = std::max<int64_t>(1024, 32 * hs.n);
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (hs.pairs_cap < want) {
@@ -1120,6 +1123,7 @@ rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds) {
     if (!h) return RBC_ERR_INVALID_ARG;
     HostSys &hs = h->sys[0];
     if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     HIPCHK(hipStreamSynchronize(h->st));
     if (owner) {
         std::vector<int32_t> own(hs.n), gid(hs.n);
