@@ -112,6 +112,14 @@ typedef struct {
      * quench_max.  Excludes the thermostat. */
     double quench_max;                          /* sigma per step (radians for rotations) */
     int32_t quench;                             /* 1: quench instead of free dynamics */
+    /* Pruned lists.  The neighbour lists are built with the full skin (radius rc + 2
+     * skin) every update_every steps or when a particle could move more than the
+     * skin; between builds the step kernel walks pruned copies that keep only the
+     * partners within rc + 2 inner_skin at the moment of pruning, refreshed from the
+     * full lists whenever a particle could move more than inner_skin since the last
+     * prune.  A value outside (0, skin) prunes only at the builds (pruned lists =
+     * full lists).  The neighbour set is unchanged either way. */
+    double inner_skin;
 } rbc_params;
 
 /* ---- single-system context (an ensemble with one slot) ---- */
@@ -162,13 +170,13 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
  * volume V of the lipid surface (as defined for the volume constraint). */
 rbc_status rbc_energy(rbc_handle h, double *out);
 
-/* Counters (sync).  [host] out[10]: steps done, neighbour-list builds (all
+/* Counters (sync).  [host] out[11]: steps done, neighbour-list builds (all
  * kinds), list-only rebuilds (the skin ran out between cell updates), cells k,
  * max neighbour-list rows, max cell-pair row, particles n, lipids, lipid cells
  * (cells [0, out[8]) hold lipids; with protein_cells set, cells [out[8], k)
- * hold the protein beads; otherwise out[8] == k), and Voronoi cell updates
+ * hold the protein beads; otherwise out[8] == k), Voronoi cell updates
  * (the initial build included; every params.update_every steps, each also
- * rebuilding the lists). */
+ * rebuilding the lists), and prunes of the lists between builds. */
 rbc_status rbc_stats(rbc_handle h, int64_t *out);
 
 /* Cell structure for inspection (sync).  [host] owner: n ints, the cell of

@@ -115,7 +115,8 @@ __device__ void pack_one(const SysDev &S, const double *x, const double *n, cons
     const int t = type[i];
     D4 p = {x[3 * i], x[3 * i + 1], x[3 * i + 2], (double)t};
     S.pos[i] = p;
-    S.xb[i] = p;
+    S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
+    S.xp[i] = S.xb[i];
     S.vel[i] = D4{v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0};
     if (t == 0) {
         S.ori[i] = D4{n[3 * i], n[3 * i + 1], n[3 * i + 2], 0.0};
@@ -1211,6 +1212,20 @@ __device__ __forceinline__ float sel3f(int t, float a, float b, float c) {
     return __int_as_float(r);
 }
 
+// 32 byte flags (each 0 or 1, 4-byte aligned in LDS) as one word, flag k in bit k.
+// Marking set members with plain byte stores of 1 avoids serialising many lanes'
+// atomics on a few bitmap words.
+__device__ __forceinline__ unsigned pack_flags(const unsigned char *f) {
+    const unsigned *w = reinterpret_cast<const unsigned *>(f);
+    unsigned bits = 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const unsigned v = w[q];
+        bits |= ((v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u)) << (4 * q);
+    }
+    return bits;
+}
+
 // Last candidate cell whose particle offset is <= u (offsets of empty cells repeat).
 __device__ __forceinline__ int union_cell(const int *ofs, int nsc, int u) {
     int lo = 0, hi = nsc;
@@ -1547,6 +1562,170 @@ void launch_nlist(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_nlist, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm);
 }
 
+// ------------------------------------------------------------------ pruned lists
+
+// One block per 256 consecutive cell-sorted particles.  The block's lists hold every
+// partner within rc + 2 skin at the last build; between builds, the partners within
+// rc + 2 inner skin at the current positions are kept in a pruned list, which the
+// force kernel walks instead.  A pair left out was farther apart than rc + 2 inner
+// skin when the lists were pruned, so it cannot come within rc before some particle
+// has moved more than the inner skin since then; the runtime prunes again before
+// that.  As in the list build, the test runs on FP32 offsets from the block's first
+// particle against the radius widened by 1e-3 sigma (offsets are limited to 4096
+// sigma), so the pruned list is a superset of the exact neighbour set; blocks whose
+// offsets exceed that keep every entry.  The partners kept form the block's pruned
+// stage (in stage order); the pruned list holds indices into it, padded with 0xffff.
+// Blocks without a stage (32-bit global lists) are not pruned (pruned count -1).
+// Every particle's current position becomes its reference for the displacement
+// since the prune.
+__global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, DevParams P) {
+    SYS_FROM(p);
+    __shared__ F4 s_o[SMAX];
+    __shared__ __align__(16) unsigned char s_flag[SMAX];   // stage entry kept by some lane (plain stores of 1)
+    __shared__ unsigned s_bits[SMAX / 32];
+    __shared__ int s_pre[SMAX / 32];
+    __shared__ int s_w[16];
+    __shared__ int s_big;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int chunk = lb * (BLOCK / WAVE) + wv;
+    const bool chunk_ok = chunk < S.nchunk;
+    const int i = lb * BLOCK + tid;
+    const bool valid = i < S.n;
+    if (lb == 0 && tid == 0) S.sc->maxdisp2p = 0ull;
+    const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
+    if (valid) S.xp[i] = F4{(float)pi.x, (float)pi.y, (float)pi.z, 0.0f};
+    const int scnt = S.scount[lb];
+    const int rows = chunk_ok ? min(S.nlk[chunk], MAXNB) : 0;
+    if (scnt < 0) {
+        if (chunk_ok && lane == 0) S.ilk[chunk] = rows;
+        if (tid == 0) S.iscount[lb] = -1;
+        return;
+    }
+    if (tid == 0) s_big = 0;
+    for (int w = tid; w < SMAX / 4; w += BLOCK) reinterpret_cast<unsigned *>(s_flag)[w] = 0u;
+    const D4 ref = ldg(S.pos + (size_t)lb * BLOCK);
+    float big = 0.0f;
+    for (int q = tid; q < scnt; q += BLOCK) {
+        const int slot = ldg(S.stage + (size_t)lb * SMAX + q);
+        const D4 pj = ldg(S.pos + slot);
+        const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
+        const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
+        const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
+        s_o[q] = F4{ox, oy, oz, __int_as_float((int)pj.w & 3)};
+        big = fmaxf(big, fmaxf(fabsf(ox), fmaxf(fabsf(oy), fabsf(oz))));
+    }
+    if (!(big <= LIST_EXTENT)) s_big = 1;            // also catches non-finite offsets
+    __syncthreads();
+    const bool keep_all = s_big != 0;
+    int cnt = 0;
+    const uint16_t *col = S.nl16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
+    uint16_t *icol = S.il16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
+    constexpr int BATCH = 8;     // list rows whose entries are loaded together
+    if (valid && chunk_ok) {
+        const int ti = (int)pi.w;
+        const float oix = (float)minimg1(pi.x - ref.x, S.per[0], S.box[0]);
+        const float oiy = (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]);
+        const float oiz = (float)minimg1(pi.z - ref.z, S.per[2], S.box[2]);
+        const float rA = ti == 0 ? P.rin2f[0][0] : (ti == 1 ? P.rin2f[1][0] : P.rin2f[2][0]);
+        const float rB = ti == 0 ? P.rin2f[0][1] : (ti == 1 ? P.rin2f[1][1] : P.rin2f[2][1]);
+        const float rC = ti == 0 ? P.rin2f[0][2] : (ti == 1 ? P.rin2f[1][2] : P.rin2f[2][2]);
+        const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
+        const float Lx = S.per[0] ? (float)S.box[0] : 0.0f, Ly = S.per[1] ? (float)S.box[1] : 0.0f,
+                    Lz = S.per[2] ? (float)S.box[2] : 0.0f;
+        const float iLx = S.per[0] ? 1.0f / Lx : 0.0f, iLy = S.per[1] ? 1.0f / Ly : 0.0f,
+                    iLz = S.per[2] ? 1.0f / Lz : 0.0f;
+        for (int r0 = 0; r0 < rows; r0 += BATCH) {
+            int e[BATCH];
+#pragma unroll
+            for (int q = 0; q < BATCH; ++q) e[q] = (int)ldg(col + min(r0 + q, rows - 1) * CHUNK);
+#pragma unroll
+            for (int q = 0; q < BATCH; ++q) {
+                const int eq = (r0 + q < rows) ? e[q] : 0xffff;
+                const F4 c = s_o[eq < scnt ? eq : 0];
+                float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
+                if (periodic) {
+                    dx -= Lx * rintf(dx * iLx);
+                    dy -= Ly * rintf(dy * iLy);
+                    dz -= Lz * rintf(dz * iLz);
+                }
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                const float rr = sel3f(__float_as_int(c.w), rA, rB, rC);
+                if (eq < scnt && (keep_all || d2 < rr)) {
+                    stg(icol + cnt * CHUNK, (uint16_t)eq);
+                    ++cnt;
+                    s_flag[eq] = 1;
+                }
+            }
+        }
+    }
+    const int irows = wave_max_int(cnt);
+    if (chunk_ok && lane == 0) S.ilk[chunk] = irows;
+    __syncthreads();
+    const int nwords = (scnt + 31) / 32;
+    for (int w = tid; w < nwords; w += BLOCK) {
+        s_bits[w] = pack_flags(s_flag + 32 * w);
+        s_pre[w] = __popc(s_bits[w]);
+    }
+    __syncthreads();
+    const int nkept = block_scan_lds(s_pre, nwords, s_w);
+    for (int w = tid; w < nwords; w += BLOCK) {
+        unsigned bits = s_bits[w];
+        int r = s_pre[w];
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1u;
+            stg(S.istage + (size_t)lb * SMAX + r, ldg(S.stage + (size_t)lb * SMAX + w * 32 + b));
+            ++r;
+        }
+    }
+    // rewrite the kept entries as pruned-stage indices (the lane reads back what it
+    // wrote), padding every lane to the chunk's row count rounded up to even (the step
+    // kernel takes rows in pairs)
+    const int prows = (irows + 1) & ~1;
+    if (chunk_ok)
+        for (int r0 = 0; r0 < prows; r0 += BATCH) {
+            int e[BATCH];
+#pragma unroll
+            for (int q = 0; q < BATCH; ++q) e[q] = r0 + q < cnt ? (int)ldg(icol + (r0 + q) * CHUNK) : -1;
+#pragma unroll
+            for (int q = 0; q < BATCH; ++q) {
+                if (r0 + q >= prows) break;
+                int local = 0xffff;
+                if (e[q] >= 0) {
+                    const int w = e[q] >> 5;
+                    local = s_pre[w] + __popc(s_bits[w] & ((1u << (e[q] & 31)) - 1u));
+                }
+                stg(icol + (r0 + q) * CHUNK, (uint16_t)local);
+            }
+        }
+    if (tid == 0) S.iscount[lb] = nkept;
+}
+
+// Block map of the systems in the mask (particle blocks only), for prunes outside a
+// cell update.  One block of MAX_SLOTS threads.
+__global__ __launch_bounds__(MAX_SLOTS) void k_mask_maps(const SysDev *Sd, int nsys, unsigned long long m0,
+                                                         unsigned long long m1, unsigned long long m2,
+                                                         unsigned long long m3, int32_t *out) {
+    __shared__ int s_w[16];
+    const int s = threadIdx.x;
+    int cnt = 0;
+    if (s < nsys) {
+        const unsigned long long w = (s < 64) ? m0 : (s < 128) ? m1 : (s < 192) ? m2 : m3;
+        if ((w >> (s & 63)) & 1ull) cnt = (Sd[s].n + BLOCK - 1) / BLOCK;
+    }
+    int tot;
+    const int ex = block_excl_scan(cnt, s_w, tot);
+    if (s <= nsys) out[s] = ex;
+}
+
+void launch_prune(const LaunchCtx &L) {
+    if (L.nblk_p > 0) hipLaunchKernelGGL(k_prune, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm);
+}
+
+void launch_mask_maps(const LaunchCtx &L, const unsigned long long m[4], int32_t *out) {
+    hipLaunchKernelGGL(k_mask_maps, dim3(1), dim3(MAX_SLOTS), 0, L.st, L.S, L.nsys, m[0], m[1], m[2], m[3], out);
+}
+
 // ------------------------------------------------------------------ finish
 
 __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
@@ -1554,7 +1733,8 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
     if (!S.sc->rebuild) return;
     int i = lb * BLOCK + threadIdx.x;
     if (i < S.n) {
-        S.xb[i] = S.pos[i];
+        const D4 p = S.pos[i];
+        S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
         const D4 o = S.ori[i];
         S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, 0.0f};
     }
@@ -1575,6 +1755,7 @@ __global__ __launch_bounds__(256) void k_finish_sys(const SysDev *Sd, int nsys) 
         sc->nlrows = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
         sc->maxdisp2 = 0ull;
         sc->maxv2 = 0ull;
+        sc->maxdisp2p = 0ull;
         sc->rebuild = 0;
     }
 }

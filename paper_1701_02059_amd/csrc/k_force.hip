@@ -45,6 +45,12 @@ __device__ __forceinline__ double sel_cut(int t, double a, double b, double c) {
     return __longlong_as_double(r);
 }
 
+__device__ __forceinline__ float sel_cutf(int t, float a, float b, float c) {
+    int r = (t == 1) ? __float_as_int(b) : __float_as_int(c);
+    r = (t == 0) ? __float_as_int(a) : r;
+    return __int_as_float(r);
+}
+
 // ------------------------------------------------------------------ pair laws
 
 // Lipid-lipid orientation-dependent law; d = x_i - x_j.  Adds the force and torque
@@ -199,11 +205,16 @@ __device__ __forceinline__ void drift_pos(D4 &x, const D4 &v, double dt) {
     x.z += dt * v.z;
 }
 
-__device__ __forceinline__ void drift_measures(const D4 &x, const D4 &v, const D4 &b, double &disp2, double &v2,
-                                               bool &bad) {
+// Displacements since the last list build and since the last prune, measured
+// against FP32 copies of the reference positions (their rounding, below 6e-5 sigma for
+// coordinates under 1000 sigma, is covered by the runtime's margins).
+__device__ __forceinline__ void drift_measures(const D4 &x, const D4 &v, const F4 &b, const F4 &p, double &disp2,
+                                               double &disp2p, double &v2, bool &bad) {
 #pragma clang fp contract(off)
-    const double ddx = x.x - b.x, ddy = x.y - b.y, ddz = x.z - b.z;
+    const double ddx = x.x - (double)b.x, ddy = x.y - (double)b.y, ddz = x.z - (double)b.z;
     disp2 = ddx * ddx + ddy * ddy + ddz * ddz;
+    const double dpx = x.x - (double)p.x, dpy = x.y - (double)p.y, dpz = x.z - (double)p.z;
+    disp2p = dpx * dpx + dpy * dpy + dpz * dpz;
     v2 = v.x * v.x + v.y * v.y + v.z * v.z;
     bad = !isfinite(x.x + x.y + x.z + v.x + v.y + v.z);
 }
@@ -353,16 +364,20 @@ __device__ __forceinline__ void volume_term(const SysScal *sc, const D4 &x, cons
     Tq.z += n.x * gy - n.y * gx;
 }
 
-// Per-wavefront drift statistics: the largest |x - x_build|^2 and |v|^2 of the
-// wave's particles (chunk w of the particle block) go to the block's partial slots
-// 2w and 2w+1; a non-finite state raises the system's error bit.
-__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, int w, double disp2, double v2, bool bad) {
+// Per-wavefront drift statistics: the largest |x - x_build|^2, |v|^2 and
+// |x - x_prune|^2 of the wave's particles (chunk w of the particle block) go to the
+// block's partial slots 3w, 3w+1 and 3w+2; a non-finite state raises the system's
+// error bit.
+__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, int w, double disp2, double v2, double disp2p,
+                                            bool bad) {
     disp2 = wave_max_lane63(disp2);
     v2 = wave_max_lane63(v2);
+    disp2p = wave_max_lane63(disp2p);
     const unsigned long long anybad = __ballot(bad);
     if (lane_id_f() == WAVE - 1) {
-        S.bred[(size_t)blk * BRED + 2 * w] = disp2;
-        S.bred[(size_t)blk * BRED + 2 * w + 1] = v2;
+        S.bred[(size_t)blk * BRED + 3 * w] = disp2;
+        S.bred[(size_t)blk * BRED + 3 * w + 1] = v2;
+        S.bred[(size_t)blk * BRED + 3 * w + 2] = disp2p;
         if (anybad) atomicOr(&S.sc->err, ERR_NONFINITE);
     }
 }
@@ -374,9 +389,11 @@ __device__ __forceinline__ void publish_drift(SysScal *sc, StepStat *hstat) {
     const unsigned long long st = sc->step;
     const unsigned long long d = atomicOr(&sc->maxdisp2, 0ull);
     const unsigned long long v = atomicOr(&sc->maxv2, 0ull);
+    const unsigned long long dp = atomicOr(&sc->maxdisp2p, 0ull);
     StepStat *e = hstat + st % STAT_RING;
     e->d2 = bitsd(d);
     e->v2 = bitsd(v);
+    e->d2p = bitsd(dp);
     __threadfence_system();
     e->tag = st + 1;
     sc->step = st + 1;
@@ -390,24 +407,111 @@ __device__ __forceinline__ void swap_drift(SysDev &W) {
 
 // ------------------------------------------------------------------ force kernel
 
+// Minimum-image separation for the step kernel: k = rint(d * (1/L)) instead of
+// rint(d / L).  The two differ only where d / L lies within a few ulp of a
+// half-integer, that is at separations near L / 2, beyond every list radius (a
+// periodic length exceeds twice the largest cutoff plus skin); every pair that can
+// be in range gets the same k, hence the same separation bits, as the exact test.
+__device__ __forceinline__ double minimg_fast(double d, double L, double iL) {
+#pragma clang fp contract(off)
+    const double k = __builtin_rint(d * iL);
+    const double kl = k * L;
+    return d - kl;
+}
+
+// Branch-free FP32 lipid-lipid law for the mixed-precision step kernel, on the
+// separation (dx, dy, dz) = x_i - x_j with r2 = |d|^2 > 0.  Both radial branches are
+// evaluated and selected (the repulsive core below r_min, the cos^(2 zeta) well above
+// it); `on` masks the pair out (no force, torque or energy) without a branch.  Returns
+// U; the force on i is minus (mx, my, mz) as returned, the torque on i (tx, ty, tz).
+// The same law as lipid_pair, rearranged for fewer operations: with g = -t n_i -
+// s n_j + sin(th0) (n_j - n_i) and k = dU/da / r, the force on i is
+// -[(dU/dr - k g.e) e + k g], and g.e = -2 s t + sin(th0) (t - s).
+template <bool FAST>
+__device__ __forceinline__ float lipid_pair_bf(const DevParams &P, float dx, float dy, float dz, float r2, float nix,
+                                               float niy, float niz, float njx, float njy, float njz, bool on,
+                                               float &mx, float &my, float &mz, float &tx, float &ty, float &tz) {
+    const float eps = (float)P.eps, mu = (float)P.mu, rmin = (float)P.r_min;
+    const float st0 = FAST ? 0.0f : (float)P.st0;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+    const float s = nix * ex + niy * ey + niz * ez;
+    const float t = njx * ex + njy * ey + njz * ez;
+    const float c = nix * njx + niy * njy + niz * njz;
+    float a = c - s * t;
+    if (!FAST) a += st0 * (t - s) - st0 * st0;
+    const float phi = mu * a + (1.0f - mu);
+    // repulsive core, r < r_min: U = eps (q^2 - 2 q) + (1 - phi) eps with q = (r_min / r)^2
+    const float q = (rmin * rmin) * (rinv * rinv);
+    const float dUdrR = (4.0f * eps) * ((q - q * q) * rinv);
+    const float dUdaR = -mu * eps;
+    // attractive well, r_min <= r < r_c: x = (pi/2) u with u clamped to [0, 1]; the
+    // hardware sine and cosine take revolutions, x / 2pi = u / 4
+    const float w4 = 0.25f * (float)P.inv_w;
+    const float arg = __builtin_amdgcn_fmed3f(r * w4 - rmin * w4, 0.0f, 0.25f);
+    const float sx = __builtin_amdgcn_sinf(arg);
+    const float cx = __builtin_amdgcn_cosf(arg);
+    const float c2 = cx * cx;
+    float cz1;                                           // cos^(2 zeta - 2)
+    if (FAST) cz1 = (c2 * c2) * c2;
+    else cz1 = ipow(c2, P.zeta - 1);
+    const float c2z = cz1 * c2;                          // cos^(2 zeta)
+    const float dUdrA = (phi * (float)P.dudr_k) * ((sx * cx) * cz1);
+    const float dUdaA = (-mu * eps) * c2z;
+    const bool rep = r < rmin;
+    float dUdr = rep ? dUdrR : dUdrA;
+    float dUda = rep ? dUdaR : dUdaA;
+    float U = rep ? (eps * (q * q - 2.0f * q) + (1.0f - phi) * eps) : -eps * c2z * phi;
+    dUdr = on ? dUdr : 0.0f;
+    dUda = on ? dUda : 0.0f;
+    U = on ? U : 0.0f;
+    const float k = dUda * rinv;
+    const float kt = k * t, ks = k * s;
+    float ge2 = 2.0f * kt * s;                           // -k g.e
+    if (!FAST) ge2 -= k * st0 * (t - s);
+    const float A = dUdr + ge2;
+    float bi = -kt, bj = -ks;                            // k g = bi n_i + bj n_j
+    if (!FAST) {
+        bi -= k * st0;
+        bj += k * st0;
+    }
+    mx = A * ex + bi * nix + bj * njx;
+    my = A * ey + bi * niy + bj * njy;
+    mz = A * ez + bi * niz + bj * njz;
+    // torque on i: n_i x g_i with g_i = -dU/da (n_j - (t + sin th0) e)
+    const float bb = t + st0;
+    const float wx = -dUda * (njx - bb * ex), wy = -dUda * (njy - bb * ey), wz = -dUda * (njz - bb * ez);
+    tx = niy * wz - niz * wy;
+    ty = niz * wx - nix * wz;
+    tz = nix * wy - niy * wx;
+    return U;
+}
+
 // LDS stage per 256-particle block (structure of arrays): FP64 positions, and either
 // FP32 orientations with the type in w (mixed) or FP64 orientations and a type byte.
-// Both modes hold the first 800 stage entries in LDS and read any further ones
-// (about 1% of blocks have more) from global memory.  Mixed mode: 32 KB and 88
-// registers, five blocks (waves per SIMD) per CU; FP64 mode: 39 KB and, with the
-// register budget capped at 128, four.
+// The stage is the block's pruned partner set; entries beyond the LDS part (rare)
+// are read from global memory.  Mixed mode keeps one more entry, a sentinel far
+// from every particle, which list padding points to.
 template <int MIXED>
 struct Stage {
-    static constexpr int lds = 800;
-    static constexpr int bytes = MIXED ? lds * (3 * 8 + 16) : lds * (6 * 8 + 1);
+    static constexpr int lds = MIXED ? 640 : 800;
+    static constexpr int ext = MIXED ? lds + 2 : lds;   // LDS entries (mixed: the sentinel and one pad)
+    static constexpr int bytes = MIXED ? ext * (3 * 8 + 16) : lds * (6 * 8 + 1);
 };
-static_assert(Stage<1>::lds <= SMAX && (Stage<1>::lds * 24) % 16 == 0, "mixed stage layout");
+static_assert(Stage<1>::lds < SMAX && (Stage<1>::ext * 24) % 16 == 0, "mixed stage layout");
+constexpr double SENTINEL = 1.0e8;    // sigma: the padding entry's coordinates (finite FP32 squares)
 
-// One workgroup per 256 consecutive cell-sorted particles.  The block's partners
-// (its stage list) are read once from HBM into LDS; lane i then walks column i of
-// its chunk's 16-bit list of stage indices.  Every candidate takes the exact FP64
-// neighbour test on FP64 positions in both modes; mixed mode rounds the
-// separation and uses FP32 orientations for the pair law.
+// One workgroup per 256 consecutive cell-sorted particles.  The block's pruned
+// partners (its stage) are read once from HBM into LDS; lane i then walks column i of
+// its chunk's pruned list of stage indices.
+//  - Mixed mode: each row is evaluated without branches, two rows per trip.  The
+//    FP64-formed separation is rounded to FP32 and its FP32 square decides the
+//    neighbour test where it lies clear of the cutoff (beyond the FP32 rounding of the
+//    square, a relative 4e-7 at most); in the band between, which a wavefront rarely
+//    meets, the exact FP64 test of the neighbour-set definition decides.  The pair
+//    law then runs in FP32.
+//  - FP64 mode: every entry takes the exact FP64 test; the pair law runs in FP64.
 // KICK: 0 stores F and tau; 1 also applies the closing half-kick of the step;
 // 2 applies the closing half-kick and then, with the same force, the opening
 // half-kick and drift of the next step (positions and orientations go to the
@@ -416,16 +520,18 @@ template <int MIXED, int ENERGY, int KICK, int FAST>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4))) void k_force(const SysDev *Sd, Maps L_maps, DevParams P, double dt) {
     using T = typename std::conditional<MIXED, float, double>::type;
     constexpr int SL = Stage<MIXED>::lds;
+    constexpr int SX = Stage<MIXED>::ext;
     __shared__ __align__(16) unsigned char s_raw[Stage<MIXED>::bytes];
     double *s_x = reinterpret_cast<double *>(s_raw);
-    double *s_y = s_x + SL;
-    double *s_z = s_y + SL;
-    F4 *s_n4 = reinterpret_cast<F4 *>(s_z + SL);                  // mixed
+    double *s_y = s_x + SX;
+    double *s_z = s_y + SX;
+    F4 *s_n4 = reinterpret_cast<F4 *>(s_z + SX);                  // mixed
     double *s_nx = s_z + SL, *s_ny = s_nx + SL, *s_nz = s_ny + SL;        // FP64
     unsigned char *s_t = reinterpret_cast<unsigned char *>(s_nz + SL);    // FP64
-    const int s = find_sys(L_maps.f, L_maps.nsys, blockIdx.x);
+    const int gb = xcd_group_block(blockIdx.x, gridDim.x);
+    const int s = find_sys(L_maps.f, L_maps.nsys, gb);
     const SysDev &S = Sd[s];
-    const int fb = blockIdx.x - L_maps.f[s];
+    const int fb = gb - L_maps.f[s];
     // a split system's particle block runs as four blocks, one per chunk, whose four
     // waves take every fourth row of that chunk (block-uniform)
     const bool split = S.split != 0;
@@ -436,17 +542,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int chunk = lb * (BLOCK / WAVE) + csub;
     const int i = lb * BLOCK + csub * WAVE + lane;
     const bool valid = i < S.n;
-    const int scnt = S.scount[lb];
+    const int scnt = __builtin_amdgcn_readfirstlane(S.iscount[lb]);
     const int nlds = min(scnt, SL);                 // stage entries held in LDS
     for (int q = tid; q < nlds; q += BLOCK) {
-        const int slot = ldg(S.stage + (size_t)lb * SMAX + q);
+        const int slot = ldg(S.istage + (size_t)lb * SMAX + q);
         const D4 p = ldg(S.pos + slot);
         s_x[q] = p.x;
         s_y[q] = p.y;
         s_z[q] = p.z;
         if constexpr (MIXED) {
             const F4 o = ldg(S.ori32 + slot);
-            s_n4[q] = F4{o.x, o.y, o.z, (float)p.w};
+            s_n4[q] = F4{o.x, o.y, o.z, __int_as_float((int)p.w)};
         } else {
             const D4 o = S.ori[slot];
             s_nx[q] = o.x;
@@ -454,6 +560,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             s_nz[q] = o.z;
             s_t[q] = (unsigned char)p.w;
         }
+    }
+    if (MIXED && tid == 0) {
+        s_x[SL] = SENTINEL;
+        s_y[SL] = SENTINEL;
+        s_z[SL] = SENTINEL;
+        s_n4[SL] = F4{0.0f, 0.0f, 1.0f, __int_as_float(0)};
     }
     __syncthreads();
     if (chunk >= S.nchunk) return;
@@ -463,27 +575,153 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const T nix = (T)ni.x, niy = (T)ni.y, niz = (T)ni.z;
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
     double U = 0.0, W = 0.0;
-    // Outer rows (partners built beyond rc + skin, after the inner ones) cannot come
-    // within rc while every particle has moved less than (skin - 1.1e-3) / 2 since the
-    // build; the 1.1e-3 covers the FP32 rounding of the build-time distances.
-    const int rows_all = min(S.nlk[chunk], MAXNB);
-    const bool inner_only = 2.0 * sqrt(bitsd(S.sc->maxdisp2)) < P.skip_guard;
-    const int rows = inner_only ? min(S.nlin[chunk], rows_all) : rows_all;
+    const int rows = __builtin_amdgcn_readfirstlane(min(S.ilk[chunk], MAXNB));   // wave-uniform
     // cutoff row of this particle's type, selected by the partner's type without
     // dynamic indexing; the periodic min-image only where the system has periodic axes
-    const double rcA = P.rc2[ti][0], rcB = P.rc2[ti][1], rcC = P.rc2[ti][2];
+    const double rcA = ti == 0 ? P.rc2[0][0] : (ti == 1 ? P.rc2[1][0] : P.rc2[2][0]);
+    const double rcB = ti == 0 ? P.rc2[0][1] : (ti == 1 ? P.rc2[1][1] : P.rc2[2][1]);
+    const double rcC = ti == 0 ? P.rc2[0][2] : (ti == 1 ? P.rc2[1][2] : P.rc2[2][2]);
     const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
-    auto staged_rows = [&](auto per_tag, auto part_tag, auto split_tag) {
+    const double iLx = S.per[0] ? 1.0 / S.box[0] : 0.0, iLy = S.per[1] ? 1.0 / S.box[1] : 0.0,
+                 iLz = S.per[2] ? 1.0 / S.box[2] : 0.0;
+
+    // ---- mixed mode: branch-free rows, two per trip
+    auto mixed_rows = [&](auto per_tag, auto part_tag, auto split_tag) {
         constexpr bool PER = decltype(per_tag)::value;
         constexpr bool PARTIAL = decltype(part_tag)::value;   // stage entries beyond the LDS part
-        constexpr bool SPLIT = decltype(split_tag)::value;    // this wave takes every fourth row
+        constexpr bool SPLIT = decltype(split_tag)::value;    // the four waves take every fourth pair of rows
+        constexpr int UNR = 2;          // rows per trip (consecutive), evaluated side by side
+        // The pruned lists are padded with 0xffff to an even row count in every lane, so
+        // both rows of a trip are always valid entries or padding.
+        const int nrow = (rows + 1) & ~1;
+        const int r0 = SPLIT ? UNR * (tid >> 6) : 0;
+        constexpr int tstride = SPLIT ? UNR * (BLOCK / WAVE) : UNR;
+        const uint16_t *col = S.il16 + (size_t)chunk * MAXNB * CHUNK + r0 * CHUNK + lane;
+        const int ntrip = nrow > r0 ? (nrow - r0 + tstride - 1) / tstride : 0;
+        // this particle's row of the FP32 bounds, chosen by selects (no dynamic indexing
+        // of the parameter block, which would go through scratch memory)
+        auto row_of = [&](const float (&m)[3][3], int b) {
+            return ti == 0 ? m[0][b] : (ti == 1 ? m[1][b] : m[2][b]);
+        };
+        const float loA = row_of(P.rc2lo, 0), loB = row_of(P.rc2lo, 1), loC = row_of(P.rc2lo, 2);
+        const float hiA = row_of(P.rc2hi, 0), hiB = row_of(P.rc2hi, 1), hiC = row_of(P.rc2hi, 2);
+        struct Rec {
+            double x, y, z;
+            float nx, ny, nz;
+            int t;
+        };
+        auto fetch = [&](int e) {
+            Rec c;
+            if constexpr (PARTIAL) {
+                if (e >= nlds && e < scnt) {            // stage entry beyond the LDS part
+                    const int slot = ldg(S.istage + (size_t)lb * SMAX + e);
+                    const D4 p = ldg(S.pos + slot);
+                    const F4 o = ldg(S.ori32 + slot);
+                    c.x = p.x; c.y = p.y; c.z = p.z;
+                    c.nx = o.x; c.ny = o.y; c.nz = o.z;
+                    c.t = (int)p.w;
+                    return c;
+                }
+            }
+            // padding -> the sentinel (every entry below the LDS part when not PARTIAL)
+            const int q = PARTIAL ? (e < nlds ? e : SL) : min(e, SL);
+            c.x = s_x[q];
+            c.y = s_y[q];
+            c.z = s_z[q];
+            const F4 nj = s_n4[q];
+            c.nx = nj.x; c.ny = nj.y; c.nz = nj.z;
+            c.t = __float_as_int(nj.w);
+            return c;
+        };
+        // Software pipeline: the list entries of the next trip are loaded from global
+        // memory while this trip's rows are evaluated (the lists carry padding rows past
+        // the last chunk, so the load after the last trip stays in bounds).
+        int en[UNR];
+        for (int q = 0; q < UNR; ++q) en[q] = ntrip > 0 ? (int)ldg(col + q * CHUNK) : 0xffff;
+        for (int it = 0; it < ntrip; ++it) {
+            Rec c[UNR];
+            for (int q = 0; q < UNR; ++q) c[q] = fetch(en[q]);
+            const uint16_t *nxt = col + (size_t)(it + 1) * tstride * CHUNK;
+            for (int q = 0; q < UNR; ++q) en[q] = (int)ldg(nxt + q * CHUNK);
+            // separations and the neighbour test of every row of the trip
+            double dx[UNR], dy[UNR], dz[UNR];
+            float fdx[UNR], fdy[UNR], fdz[UNR], r2[UNR];
+            bool in[UNR], band[UNR], lip[UNR];
+            bool anyband = false;
+            for (int q = 0; q < UNR; ++q) {
+                dx[q] = pi.x - c[q].x;
+                dy[q] = pi.y - c[q].y;
+                dz[q] = pi.z - c[q].z;
+                if constexpr (PER) {
+                    if (S.per[0]) dx[q] = minimg_fast(dx[q], S.box[0], iLx);
+                    if (S.per[1]) dy[q] = minimg_fast(dy[q], S.box[1], iLy);
+                    if (S.per[2]) dz[q] = minimg_fast(dz[q], S.box[2], iLz);
+                }
+                fdx[q] = (float)dx[q];
+                fdy[q] = (float)dy[q];
+                fdz[q] = (float)dz[q];
+                r2[q] = fdx[q] * fdx[q] + fdy[q] * fdy[q] + fdz[q] * fdz[q];
+                const int tj = c[q].t;
+                const float lo = FAST ? (tj == 0 ? loA : loB) : sel_cutf(tj, loA, loB, loC);
+                const float hi = FAST ? (tj == 0 ? hiA : hiB) : sel_cutf(tj, hiA, hiB, hiC);
+                in[q] = r2[q] < lo;
+                band[q] = !in[q] && r2[q] < hi;
+                anyband = anyband || band[q];
+                lip[q] = (ti | tj) == 0;
+            }
+            if (__builtin_expect(__ballot(anyband) != 0ull, 0)) {
+#pragma clang fp contract(off)
+                // FP32 rounding cannot decide: the exact test of the neighbour-set definition
+                for (int q = 0; q < UNR; ++q) {
+                    const double d2 = (dx[q] * dx[q] + dy[q] * dy[q]) + dz[q] * dz[q];
+                    if (band[q]) in[q] = d2 < sel_cut(c[q].t, rcA, rcB, rcC);
+                }
+            }
+            // the pair law of every row, in one block of straight-line code; (ax, ay, az)
+            // receives minus the pair's force on i
+            float ax[UNR], ay[UNR], az[UNR], u[UNR], qx[UNR], qy[UNR], qz[UNR];
+            bool anywca = false;
+            for (int q = 0; q < UNR; ++q) {
+                in[q] = in[q] && valid;
+                u[q] = lipid_pair_bf<FAST>(P, fdx[q], fdy[q], fdz[q], r2[q], nix, niy, niz, c[q].nx, c[q].ny,
+                                           c[q].nz, in[q] && lip[q], ax[q], ay[q], az[q], qx[q], qy[q], qz[q]);
+                anywca = anywca || (in[q] && !lip[q]);
+            }
+            if (__builtin_expect(__ballot(anywca) != 0ull, 0)) {
+                for (int q = 0; q < UNR; ++q) {
+                    const bool wca = in[q] && !lip[q];
+                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                    const float uw = wca_pair<float>(P, wca ? fdx[q] : 2.0f, fdy[q], fdz[q], bx, by, bz);
+                    if (wca) { ax[q] = -bx; ay[q] = -by; az[q] = -bz; u[q] = uw; }
+                }
+            }
+            for (int q = 0; q < UNR; ++q) {
+                fx -= ax[q];
+                fy -= ay[q];
+                fz -= az[q];
+                tx += qx[q];
+                ty += qy[q];
+                tz += qz[q];
+                if (ENERGY) {
+                    U += 0.5 * (double)u[q];
+                    W -= 0.5 * (dx[q] * (double)ax[q] + dy[q] * (double)ay[q] + dz[q] * (double)az[q]);
+                }
+            }
+        }
+    };
+
+    // ---- FP64 mode: exact test on every entry, FP64 pair law
+    auto fp64_rows = [&](auto per_tag, auto part_tag, auto split_tag) {
+        constexpr bool PER = decltype(per_tag)::value;
+        constexpr bool PARTIAL = decltype(part_tag)::value;
+        constexpr bool SPLIT = decltype(split_tag)::value;
         constexpr int rstep = SPLIT ? BLOCK / WAVE : 1;
         const int r0 = SPLIT ? (tid >> 6) : 0;
         // Software pipeline: the list entry of row r+4 is fetched from global memory and
         // the stage record of row r+1 from LDS while row r is evaluated.
-        const uint16_t *col = S.nl16 + (size_t)chunk * MAXNB * CHUNK + r0 * CHUNK + lane;
+        const uint16_t *col = S.il16 + (size_t)chunk * MAXNB * CHUNK + r0 * CHUNK + lane;
         const int cstep = rstep * CHUNK;
-        const int nr = rows > r0 ? (rows - r0 + rstep - 1) / rstep : 0;   // this wave's rows
+        const int nr = rows > r0 ? (rows - r0 + rstep - 1) / rstep : 0;
         int e_cur = (valid && nr > 0) ? (int)ldg(col) : 0xffff;
         int e_nxt = (valid && nr > 1) ? (int)ldg(col + cstep) : 0xffff;
         int e_n2 = (valid && nr > 2) ? (int)ldg(col + 2 * cstep) : 0xffff;
@@ -496,17 +734,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         auto fetch = [&](int e) {
             Rec c;
             if constexpr (PARTIAL) {
-                if (e >= nlds && e < scnt) {            // stage entry beyond the LDS part
-                    const int slot = ldg(S.stage + (size_t)lb * SMAX + e);
+                if (e >= nlds && e < scnt) {
+                    const int slot = ldg(S.istage + (size_t)lb * SMAX + e);
                     const D4 p = ldg(S.pos + slot);
+                    const D4 o = ldg(S.ori + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
-                    if constexpr (MIXED) {
-                        const F4 o = ldg(S.ori32 + slot);
-                        c.nx = o.x; c.ny = o.y; c.nz = o.z;
-                    } else {
-                        const D4 o = ldg(S.ori + slot);
-                        c.nx = o.x; c.ny = o.y; c.nz = o.z;
-                    }
+                    c.nx = o.x; c.ny = o.y; c.nz = o.z;
                     c.t = (int)p.w;
                     return c;
                 }
@@ -515,14 +748,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             c.x = s_x[q];
             c.y = s_y[q];
             c.z = s_z[q];
-            if constexpr (MIXED) {
-                const F4 nj = s_n4[q];
-                c.nx = nj.x; c.ny = nj.y; c.nz = nj.z;
-                c.t = (int)nj.w;
-            } else {
-                c.nx = s_nx[q]; c.ny = s_ny[q]; c.nz = s_nz[q];
-                c.t = s_t[q];
-            }
+            c.nx = s_nx[q]; c.ny = s_ny[q]; c.nz = s_nz[q];
+            c.t = s_t[q];
             return c;
         };
         Rec rec = fetch(e_cur);
@@ -536,7 +763,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             rec = fetch(e_cur);
             if (e >= scnt) continue;
             const int tj = c.t;
-            const T njx = c.nx, njy = c.ny, njz = c.nz;
             double dx, dy, dz, d2;
             if constexpr (PER) {
                 d2 = dist2_exact(S, pi.x, pi.y, pi.z, c.x, c.y, c.z, dx, dy, dz);
@@ -547,7 +773,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             if (!(d2 < rc2)) continue;
             T ax = 0, ay = 0, az = 0, u;
             if ((ti | tj) == 0)
-                u = lipid_pair<T, FAST>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, njx, njy, njz, ax, ay, az, tx, ty, tz);
+                u = lipid_pair<T, FAST>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, c.nx, c.ny, c.nz, ax, ay, az, tx, ty,
+                                        tz);
             else
                 u = wca_pair<T>(P, (T)dx, (T)dy, (T)dz, ax, ay, az);
             fx += ax;
@@ -559,22 +786,28 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             }
         }
     };
+
     if (scnt >= 0) {
-        // block-uniform choices: periodic min-image, and (mixed mode) whether the stage
-        // overflows the LDS part, so ordinary blocks carry no per-entry test
-        auto rows_by_split = [&](auto per_tag, auto part_tag) {
-            if (split) staged_rows(per_tag, part_tag, std::true_type{});
-            else staged_rows(per_tag, part_tag, std::false_type{});
+        // block-uniform choices: periodic min-image, whether the stage overflows the LDS
+        // part, and the row split, so ordinary blocks carry no per-entry test
+        auto dispatch = [&](auto per_tag, auto part_tag) {
+            if constexpr (MIXED) {
+                if (split) mixed_rows(per_tag, part_tag, std::true_type{});
+                else mixed_rows(per_tag, part_tag, std::false_type{});
+            } else {
+                if (split) fp64_rows(per_tag, part_tag, std::true_type{});
+                else fp64_rows(per_tag, part_tag, std::false_type{});
+            }
         };
-        if (SL < SMAX && scnt > SL) {
-            if (periodic) rows_by_split(std::true_type{}, std::integral_constant<bool, SL < SMAX>{});
-            else rows_by_split(std::false_type{}, std::integral_constant<bool, SL < SMAX>{});
+        if (scnt > SL) {
+            if (periodic) dispatch(std::true_type{}, std::true_type{});
+            else dispatch(std::false_type{}, std::true_type{});
         } else {
-            if (periodic) rows_by_split(std::true_type{}, std::false_type{});
-            else rows_by_split(std::false_type{}, std::false_type{});
+            if (periodic) dispatch(std::true_type{}, std::false_type{});
+            else dispatch(std::false_type{}, std::false_type{});
         }
     } else {
-        // block whose partners did not fit the stage: the lists hold global slots
+        // block whose partners did not fit a stage: its (unpruned) lists hold global slots
         const int32_t *col = S.nl + (size_t)chunk * MAXNB * CHUNK + lane;
         const int r0 = split ? (tid >> 6) : 0, rstep = split ? BLOCK / WAVE : 1;
         for (int r = r0; r < rows; r += rstep) {
@@ -632,7 +865,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
     double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
     D4 v = {0.0, 0.0, 0.0, 0.0}, w = {0.0, 0.0, 0.0, 0.0};
-    double disp2 = 0.0, vmax2 = 0.0;
+    double disp2 = 0.0, disp2p = 0.0, vmax2 = 0.0;
     bool bad = false;
     D4 Tq = {(double)tx, (double)ty, (double)tz, 0.0};
     double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -691,13 +924,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 }
                 S.ori2[i] = on;
                 S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
-                drift_measures(xn, vn, S.xb[i], disp2, vmax2, bad);
+                drift_measures(xn, vn, S.xb[i], S.xp[i], disp2, disp2p, vmax2, bad);
                 if (P.vol_on && ti == 0) volume_terms(xn, on, vsum);
             }
         }
     }
     if (KICK == 2) {
-        drift_stats(S, lb, csub, disp2, vmax2, bad);
+        drift_stats(S, lb, csub, disp2, vmax2, disp2p, bad);
         if (P.vol_on) volume_chunk_store(S, chunk, vsum);
     }
     if (ENERGY) {
@@ -726,7 +959,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 
 template <int MIXED, int ENERGY, int KICK>
 static void launch_force_t(const LaunchCtx &L, double dt) {
-    const bool fast = L.prm.zeta == 4 && L.prm.st0 == 0.0;
+    // FAST: the default pair-law constants, and one cutoff for both protein types
+    bool fast = L.prm.zeta == 4 && L.prm.st0 == 0.0;
+    for (int t = 0; t < 3; ++t) fast = fast && L.prm.rc2[t][1] == L.prm.rc2[t][2];
     if (fast)
         hipLaunchKernelGGL((k_force<MIXED, ENERGY, KICK, 1>), dim3(L.nblk_f), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm,
                            dt);
@@ -765,7 +1000,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
     const SysDev &S = Sd[s];
     const int lb = blockIdx.x - L_maps.p[s];
     const int i = lb * BLOCK + threadIdx.x;
-    double disp2 = 0.0, v2 = 0.0;
+    double disp2 = 0.0, disp2p = 0.0, v2 = 0.0;
     bool bad = false;
     double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
@@ -790,15 +1025,15 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
             S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
             if (P.vol_on) volume_terms(p, n, vsum);
         }
-        drift_measures(p, v, S.xb[i], disp2, v2, bad);
+        drift_measures(p, v, S.xb[i], S.xp[i], disp2, disp2p, v2, bad);
     }
-    drift_stats(S, lb, (threadIdx.x >> 6) & 3, disp2, v2, bad);
+    drift_stats(S, lb, (threadIdx.x >> 6) & 3, disp2, v2, disp2p, bad);
     if (P.vol_on && i / CHUNK < S.nchunk) volume_chunk_store(S, i / CHUNK, vsum);
 }
 
-// Largest displacement since the last build and largest drift speed, per system,
-// from the per-wavefront (displacement, speed) partials of a drift, one pair per
-// 64-particle chunk.  STATS_BLOCKS blocks per system fold their share with an
+// Largest displacements since the last build and since the last prune, and the
+// largest drift speed, per system, from the per-wavefront partials of a drift, three
+// per 64-particle chunk.  STATS_BLOCKS blocks per system fold their share with an
 // unsigned atomic max on the bits (non-negative doubles order like their bit
 // patterns); the last one publishes the result.  swap: after the drift fused into
 // the force kernel, which wrote the second position / orientation buffers; the last
@@ -810,25 +1045,31 @@ __global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int 
     const int part = blockIdx.x % STATS_BLOCKS;
     const int per = (S.nchunk + STATS_BLOCKS - 1) / STATS_BLOCKS;
     const int c0 = part * per, c1 = min(S.nchunk, c0 + per);
-    const double2 *dv = reinterpret_cast<const double2 *>(S.bred);
-    double d = 0.0, v = 0.0;
+    double d = 0.0, v = 0.0, dp = 0.0;
     for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
-        const double2 x = dv[c];
-        d = fmax(d, x.x);
-        v = fmax(v, x.y);
+        d = fmax(d, S.bred[3 * c]);
+        v = fmax(v, S.bred[3 * c + 1]);
+        dp = fmax(dp, S.bred[3 * c + 2]);
     }
     d = wave_maxd(d);
     v = wave_maxd(v);
-    __shared__ double s_m[2][4];
-    if ((threadIdx.x & 63) == 0) { s_m[0][threadIdx.x >> 6] = d; s_m[1][threadIdx.x >> 6] = v; }
+    dp = wave_maxd(dp);
+    __shared__ double s_m[3][4];
+    if ((threadIdx.x & 63) == 0) {
+        s_m[0][threadIdx.x >> 6] = d;
+        s_m[1][threadIdx.x >> 6] = v;
+        s_m[2][threadIdx.x >> 6] = dp;
+    }
     __syncthreads();
     if (threadIdx.x == 0 && S.n > 0) {
         d = fmax(fmax(s_m[0][0], s_m[0][1]), fmax(s_m[0][2], s_m[0][3]));
         v = fmax(fmax(s_m[1][0], s_m[1][1]), fmax(s_m[1][2], s_m[1][3]));
+        dp = fmax(fmax(s_m[2][0], s_m[2][1]), fmax(s_m[2][2], s_m[2][3]));
         SysScal *sc = S.sc;
         if (c1 > c0) {
             atomicMax(&sc->maxdisp2, dbits(d));
             atomicMax(&sc->maxv2, dbits(v));
+            atomicMax(&sc->maxdisp2p, dbits(dp));
         }
         __threadfence();
         if (atomicAdd(&sc->parts_done, 1u) == STATS_BLOCKS - 1) {
@@ -990,15 +1231,15 @@ void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, in
 
 // ------------------------------------------------------------------ neighbour-set export
 
-// Pairs (gid_i < gid_j) of the list that pass the exact FP64 test, appended in any
-// order (one atomic per wavefront).
-// Staged blocks keep stage indices in the 16-bit lists (0xffff pads); the others
-// keep global slots in the 32-bit lists (-1 pads).
+// Pairs (gid_i < gid_j) of the pruned lists the step kernel walks that pass the
+// exact FP64 test, appended in any order (one atomic per wavefront).
+// Pruned blocks keep indices into their pruned stage in the 16-bit lists (0xffff
+// pads); the others keep global slots in the 32-bit lists (-1 pads).
 __device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, int chunk, int lane, int r) {
     const size_t at = (size_t)chunk * MAXNB * CHUNK + (size_t)r * CHUNK + lane;
     if (scnt >= 0) {
-        const int e = S.nl16[at];
-        return e < scnt ? S.stage[(size_t)blk * SMAX + e] : -1;
+        const int e = S.il16[at];
+        return e < scnt ? S.istage[(size_t)blk * SMAX + e] : -1;
     }
     return S.nl[at];
 }
@@ -1014,8 +1255,8 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
         pi = S.pos[i];
         ti = (int)pi.w;
         gi = S.gid[i];
-        rows = min(S.nlk[chunk], MAXNB);
-        scnt = S.scount[blk];
+        rows = min(S.ilk[chunk], MAXNB);
+        scnt = S.iscount[blk];
     }
     int mine = 0;
     for (int pass = 0; pass < 2; ++pass) {

@@ -45,8 +45,9 @@ struct HostSys {
     int64_t updates = 0;             // Voronoi cell updates (each also rebuilds the lists)
     int64_t rebuilds = 0;            // neighbour-list builds of any kind
     int64_t early = 0;               // list-only rebuilds forced by the skin between cell updates
-    bool have_stats = false, rebuilt_last = false;
-    double disp2 = 0.0, v2 = 0.0;
+    int64_t prunes = 0;              // prunes of the lists outside a build
+    bool have_stats = false, rebuilt_last = false, refreshed_last = false;
+    double disp2 = 0.0, v2 = 0.0, disp2p = 0.0;
     uint64_t drifts = 0;             // statistics passes since loading (the device's step counter)
     bool pending = false;            // staged: uploaded, cells not built yet
 };
@@ -79,6 +80,7 @@ struct rbc_ctx {
     SysScal *d_sc = nullptr;
     int32_t *d_maps = nullptr;
     int32_t *d_umaps = nullptr;       // block maps of the systems in the running cell update
+    int32_t *d_pmaps = nullptr;       // particle-block map of the systems pruned at this step
     const int32_t **d_lip = nullptr;
     SysScal *h_sc = nullptr;          // pinned mirror of the per-system scalars (read after a sync)
     StepStat *h_stat = nullptr, *d_stat = nullptr;   // published drift statistics: host / device view
@@ -157,6 +159,12 @@ bool valid_params(const rbc_params *p, std::string &why) {
     return true;
 }
 
+// Half-width of the pruned lists' buffer: params.inner_skin, or the full skin when
+// that is not in (0, skin) (the lists are then pruned only when they are built).
+double inner_skin(const rbc_params &p) {
+    return (p.inner_skin > 0.0 && p.inner_skin < p.skin) ? p.inner_skin : p.skin;
+}
+
 void make_dev_params(rbc_ctx *h) {
     const rbc_params &p = h->prm;
     DevParams &d = h->dprm;
@@ -168,12 +176,19 @@ void make_dev_params(rbc_ctx *h) {
         const double f = m - 1e-3 - p.skin;
         d.rf2f[a] = (float)(f * f);
     }
+    const double din = inner_skin(p);
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             d.rc2[a][b] = p.rc[a][b] * p.rc[a][b];
             double rl = p.rc[a][b] + 2.0 * p.skin;
             d.rl2[a][b] = rl * rl * (1.0 + 1e-12);
             d.rl2f[a][b] = std::nextafter((float)((rl + 1e-3) * (rl + 1e-3)), INFINITY);
+            const double ri = p.rc[a][b] + 2.0 * din + 1e-3;
+            d.rin2f[a][b] = std::nextafter((float)(ri * ri), INFINITY);
+            // the FP32 square of the FP32-rounded separation is within a relative 4e-7 of
+            // the exact square; a band ten times wider goes to the FP64 test
+            d.rc2lo[a][b] = std::nextafter((float)(d.rc2[a][b] * (1.0 - 4e-6)), 0.0f);
+            d.rc2hi[a][b] = std::nextafter((float)(d.rc2[a][b] * (1.0 + 4e-6)), INFINITY);
             search = std::max(search, rl);
         }
     d.rc_lipid = p.rc[0][0];
@@ -187,7 +202,6 @@ void make_dev_params(rbc_ctx *h) {
     for (int a = 0; a < 3; ++a) d.inv_mass[a] = 1.0 / p.mass[a];
     d.inv_inertia = 1.0 / p.inertia;
     d.cell_search = search;
-    d.skip_guard = p.skin - 1.1e-3;
     d.zeta = (int32_t)p.zeta;
     d.inv_w = 1.0 / (p.rc[0][0] - p.r_min);
     d.dudr_k = p.eps * p.zeta * M_PI / (p.rc[0][0] - p.r_min);
@@ -225,7 +239,7 @@ size_t layout(HostSys &s, char *base) {
     const int32_t k = s.k;
     SysDev &d = s.dev;
     d.pos = c.take<D4>(n); d.vel = c.take<D4>(n); d.ori = c.take<D4>(n); d.angv = c.take<D4>(n);
-    d.frc = c.take<D4>(n); d.trq = c.take<D4>(n); d.xb = c.take<D4>(n);
+    d.frc = c.take<D4>(n); d.trq = c.take<D4>(n); d.xb = c.take<F4>(n); d.xp = c.take<F4>(n);
     d.pos2 = c.take<D4>(n); d.vel2 = c.take<D4>(n); d.ori2 = c.take<D4>(n); d.angv2 = c.take<D4>(n);
     d.gid = c.take<int32_t>(n); d.gid2 = c.take<int32_t>(n); d.slot = c.take<int32_t>(n);
     d.owner = c.take<int32_t>(n);
@@ -251,6 +265,10 @@ size_t layout(HostSys &s, char *base) {
     const int64_t nblkp = (n + BLOCK - 1) / BLOCK;
     d.stage = c.take<int32_t>((size_t)nblkp * SMAX);
     d.scount = c.take<int32_t>(nblkp);
+    d.il16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK + 16 * CHUNK);   // + rows the step kernel may prefetch
+    d.ilk = c.take<int32_t>(s.nchunk);
+    d.istage = c.take<int32_t>((size_t)nblkp * SMAX);
+    d.iscount = c.take<int32_t>(nblkp);
     d.blkrows = c.take<int32_t>(nblkp);
     d.bred = c.take<double>((size_t)nblkp * BRED);
     d.tsum = c.take<int32_t>((size_t)std::max((k + SCAN_TILE - 1) / SCAN_TILE, (s.gcap + SCAN_TILE - 1) / SCAN_TILE) + 2);
@@ -411,6 +429,27 @@ void run_lists(rbc_ctx *h, const std::vector<int> &which) {
     for (int s : which) h->sys[s].rebuilds++;
 }
 
+// Prune the lists of the systems in `which` at their current positions (their lists
+// stay as built).  When every live system prunes, the full particle map serves.
+void run_prunes(rbc_ctx *h, const std::vector<int> &which) {
+    if (which.empty()) return;
+    LaunchCtx P = h->L;
+    int live = 0;
+    for (const auto &hs : h->sys) live += hs.live;
+    if ((int)which.size() != live) {
+        unsigned long long m[4] = {0, 0, 0, 0};
+        P.nblk_p = 0;
+        for (int s : which) {
+            m[s >> 6] |= 1ull << (s & 63);
+            P.nblk_p += (int32_t)((h->sys[s].n + BLOCK - 1) / BLOCK);
+        }
+        launch_mask_maps(h->L, m, h->d_pmaps);
+        P.maps.p = h->d_pmaps;
+    }
+    launch_prune(P);
+    for (int s : which) h->sys[s].prunes++;
+}
+
 // The cell-update launches for the systems whose rebuild flag is set (L carries
 // block maps restricted to them).
 void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd) {
@@ -443,6 +482,7 @@ void lists_body(const LaunchCtx &L) {
     launch_cell_pairs(L);
     launch_nlist(L);
     launch_finish_update(L);
+    launch_prune(L);
 }
 
 // The status and message of one slot's error bits.
@@ -572,6 +612,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     const bool graphs = h->graphs && !h->timing && ensure_graphs(h, dt);
     ensure_forces(h);
     const double skin = h->prm.skin;
+    const double din = inner_skin(h->prm);
     const int64_t K = h->prm.update_every;
     rbc_status out = RBC_OK;
     launch_kick_drift(h->L, dt);
@@ -584,8 +625,10 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         // this event completes
         hipEventRecord(h->step_ev[slot], h->st);
         // decide, from the previous step's statistics, which systems update their cells
-        // (every K steps) and which only rebuild their lists (the skin is running out)
-        std::vector<int> which, full, lists;
+        // (every K steps), which rebuild their lists (the skin is running out) and which
+        // prune them (the pruned lists' buffer is running out; a prune needs the full
+        // lists to still hold every pair within the pruned radius)
+        std::vector<int> which, full, lists, pruned;
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
             if (!hs.live) continue;
@@ -596,16 +639,23 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
                 continue;
             }
             if (hs.have_stats) {
-                double pred = (hs.rebuilt_last ? 0.0 : std::sqrt(hs.disp2)) + 2.0 * dt * std::sqrt(hs.v2);
-                if (pred > 0.9 * skin) {
-                    hs.early++;
-                    lists.push_back(s);
-                    which.push_back(s);
+                const double step_max = 2.0 * dt * std::sqrt(hs.v2);
+                const double pred_p = (hs.refreshed_last ? 0.0 : std::sqrt(hs.disp2p)) + step_max;
+                if (pred_p > 0.9 * din) {
+                    const double pred_b = (hs.rebuilt_last ? 0.0 : std::sqrt(hs.disp2)) + step_max;
+                    if (pred_b > 0.9 * (skin - din)) {
+                        hs.early++;
+                        lists.push_back(s);
+                        which.push_back(s);
+                    } else {
+                        pruned.push_back(s);
+                    }
                 }
             }
         }
         run_update(h, full, 0);
         run_lists(h, lists);
+        run_prunes(h, pruned);
         if (graphs) {
             hipGraphLaunch(last ? h->g_last : h->g_step, h->st);
         } else {
@@ -619,21 +669,29 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             HostSys &hs = h->sys[s];
             if (!hs.live) continue;
             const bool rebuilt = std::find(which.begin(), which.end(), s) != which.end();
-            double d2 = 0.0, v2 = 0.0;
+            const bool was_pruned = std::find(pruned.begin(), pruned.end(), s) != pruned.end();
+            double d2 = 0.0, v2 = 0.0, d2p = 0.0;
             if (hs.n > 0) {
                 const volatile StepStat &e = h->h_stat[(size_t)s * STAT_RING + hs.drifts % STAT_RING];
                 if (e.tag != hs.drifts + 1 && out == RBC_OK)
                     out = fail(h, RBC_ERR_HIP, "drift statistics out of sequence (slot " + std::to_string(s) + ")");
                 d2 = e.d2;
                 v2 = e.v2;
+                d2p = e.d2p;
                 hs.drifts++;
             }
-            if (!rebuilt && d2 > skin * skin && out == RBC_OK)
+            // the force of this step walked the pruned lists: they had to hold every pair in
+            // range, and a prune at this step needed the full lists to hold its radius
+            if (!rebuilt && !was_pruned && d2p > din * din && out == RBC_OK)
+                out = fail(h, RBC_ERR_SKIN, "a particle moved beyond the pruned lists' buffer before they were pruned again (slot " + std::to_string(s) + ")");
+            if (was_pruned && d2 > (skin - din) * (skin - din) && out == RBC_OK)
                 out = fail(h, RBC_ERR_SKIN, "a particle moved beyond the skin before its lists were rebuilt (slot " + std::to_string(s) + ")");
             hs.disp2 = d2;
+            hs.disp2p = d2p;
             hs.v2 = std::max(v2, hs.rebuilt_last ? 0.0 : hs.v2);
             hs.have_stats = true;
             hs.rebuilt_last = rebuilt;
+            hs.refreshed_last = rebuilt || was_pruned;
             hs.steps_total++;
         }
         if (h->timing && h->tcount >= (int)h->tb.size()) {   // the timing events are all in use
@@ -855,6 +913,7 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipMalloc(&h->d_sc, sizeof(SysScal) * max_slots) == hipSuccess &&
               hipMalloc(&h->d_maps, sizeof(int32_t) * 8 * (max_slots + 1)) == hipSuccess &&
               hipMalloc(&h->d_umaps, sizeof(int32_t) * 7 * (MAX_SLOTS + 1)) == hipSuccess &&
+              hipMalloc(&h->d_pmaps, sizeof(int32_t) * (MAX_SLOTS + 1)) == hipSuccess &&
               hipMalloc((void **)&h->d_lip, sizeof(void *) * max_slots) == hipSuccess &&
               hipHostMalloc((void **)&h->h_sc, sizeof(SysScal) * MAX_SLOTS, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void **)&h->h_stat, sizeof(StepStat) * MAX_SLOTS * STAT_RING,
@@ -919,6 +978,7 @@ rbc_status rbc_destroy(rbc_handle h) {
     if (h->d_sc) hipFree(h->d_sc);
     if (h->d_maps) hipFree(h->d_maps);
     if (h->d_umaps) hipFree(h->d_umaps);
+    if (h->d_pmaps) hipFree(h->d_pmaps);
     if (h->d_lip) hipFree(h->d_lip);
     if (h->h_sc) hipHostFree(h->h_sc);
     if (h->h_stat) hipHostFree(h->h_stat);
@@ -1116,6 +1176,7 @@ rbc_status rbc_stats(rbc_handle h, int64_t *out) {
     out[7] = hs.nlip;
     out[8] = hs.kl;
     out[9] = hs.updates;
+    out[10] = hs.prunes;
     return RBC_OK;
 }
 

@@ -21,7 +21,7 @@ constexpr int USTAGE = 2048;           // candidate particles staged in LDS whil
 constexpr float LIST_EXTENT = 4096.0f; // largest FP32 offset (sigma) allowed in that staging
 constexpr int CULLMAX = 256;           // candidate cells whose bounding spheres are staged for culling
 constexpr int SCAN_TILE = 2048;        // elements per block in the segmented scans
-constexpr int BRED = 8;                // doubles of per-block partial results
+constexpr int BRED = 12;               // doubles of per-block partial results (3 per chunk in a drift)
 
 // error bits in SysScal::err
 constexpr int ERR_NLIST = 1;          // a particle had more than MAXNB list neighbours
@@ -41,6 +41,7 @@ struct alignas(16) F4 {
 struct alignas(256) SysScal {
     unsigned long long maxdisp2;      // bits of the largest |x - x_build|^2 since the last build
     unsigned long long maxv2;         // bits of the largest |v|^2 used in a drift since the build
+    unsigned long long maxdisp2p;     // bits of the largest |x - x_prune|^2 since the last prune
     unsigned long long rmax;          // bits of the largest cell radius
     int32_t err;
     int32_t rebuild;                  // this system takes part in the running cell update
@@ -76,8 +77,8 @@ constexpr int SPLIT_MAX_BLOCKS = 32;
 struct alignas(32) StepStat {
     double d2;                        // largest |x - x_build|^2 since the last build
     double v2;                        // largest |v|^2 used in a drift since the build
+    double d2p;                       // largest |x - x_prune|^2 since the last prune
     unsigned long long tag;           // drift number + 1, written last (0: never written)
-    unsigned long long pad;
 };
 
 // One system (slot): sizes and device arrays.  Particle arrays are in cell-sorted
@@ -89,7 +90,9 @@ struct SysDev {
     int32_t nsrcp;                                  // protein seed sources after the lipid ids in `lip`
     int32_t split;                                  // the step kernel spreads each chunk's rows over four waves
     double box[3];
-    D4 *pos, *vel, *ori, *angv, *frc, *trq, *xb;   // pos.w = particle type
+    D4 *pos, *vel, *ori, *angv, *frc, *trq;         // pos.w = particle type
+    F4 *xb;                                         // positions at the last list build (FP32)
+    F4 *xp;                                         // positions at the last prune (FP32)
     D4 *pos2, *vel2, *ori2, *angv2;
     int32_t *gid, *gid2, *slot, *owner;
     uint64_t *key, *key2;
@@ -113,6 +116,9 @@ struct SysDev {
     int32_t *pairs;                                 // scratch for exporting the pair set
     int64_t pairs_cap;
     int32_t *stage, *scount;                        // per 256-particle block: staged slots (SMAX), count (-1: none)
+    uint16_t *il16;                                 // pruned lists: indices into the pruned stage (0xffff pads)
+    int32_t *ilk;                                   // per chunk: rows of the pruned list
+    int32_t *istage, *iscount;                      // per block: the pruned stage (SMAX), count (-1: use nl)
     int32_t *blkrows;                               // per block: largest list row count of the last build
     double *bred;                                   // per particle block: BRED partials (stats, bounding box)
     int32_t *tsum;                                  // segmented-scan tile sums
@@ -127,8 +133,9 @@ struct DevParams {
     float rl2f[3][3];      // (rc + 2 skin + 1e-3)^2 rounded up: list radius for FP32 offsets
     float rlmaxf[3];       // largest list radius (+ 1e-3) of a particle type, rounded up
     float rf2f[3];         // (largest rc of the type + skin)^2: list entries inside come first
-    double skip_guard;     // skin - 1.1e-3: while 2 x (largest displacement) stays below it, the
-                           // outer list rows (built beyond rc + skin) cannot hold a pair in range
+    float rin2f[3][3];     // (rc + 2 inner skin + 1e-3)^2 rounded up: pruned-list radius for FP32 offsets
+    float rc2lo[3][3];     // FP32 squared distances below this are inside fl(rc^2) in the exact test
+    float rc2hi[3][3];     // ... and at or above this outside it; between, the FP64 test decides
     double rc_lipid, r_min, eps, mu, st0, wca_eps, wca_sig2, k_bond;
     double inv_mass[3];
     double inv_inertia;
@@ -170,6 +177,20 @@ __device__ __forceinline__ int find_sys(const int32_t *off, int nsys, int b) {
         if (off[mid] <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Workgroups are dispatched to the eight XCDs in turn, and each XCD has its own L2.
+// Neighbouring particle blocks stage mostly the same partners, so runs of XCD_RUN
+// consecutive blocks are sent to one XCD: workgroup i, the (i / 8)-th on XCD i % 8,
+// takes block ((k / XCD_RUN) * 8 + x) * XCD_RUN + k % XCD_RUN with x = i % 8 and
+// k = i / 8.  A permutation of the grid's full groups of 8 XCD_RUN blocks (the
+// remaining tail keeps its order), so every block is still processed once.
+constexpr int XCD_RUN = 16;
+__device__ __forceinline__ int xcd_group_block(int i, int n) {
+    const int full = n - n % (8 * XCD_RUN);
+    if (i >= full) return i;
+    const int x = i & 7, k = i >> 3;
+    return ((k / XCD_RUN) * 8 + x) * XCD_RUN + k % XCD_RUN;
 }
 
 // Min-image difference and squared distance exactly as the neighbour-set
@@ -292,6 +313,8 @@ void launch_block_permute(const LaunchCtx &L);
 void launch_cell_bounds(const LaunchCtx &L);
 void launch_cell_pairs(const LaunchCtx &L);
 void launch_nlist(const LaunchCtx &L);
+void launch_prune(const LaunchCtx &L);                    // pruned lists of the systems in L's particle map
+void launch_mask_maps(const LaunchCtx &L, const unsigned long long m[4], int32_t *out);   // particle map of a mask
 void launch_finish_update(const LaunchCtx &L);
 void launch_pack(const LaunchCtx &L, int sys, const double *x, const double *n, const int32_t *type,
                  const double *v, const double *w, int count);

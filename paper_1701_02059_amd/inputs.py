@@ -59,6 +59,7 @@ class ModelParams:
     cell_target: int = 16
     update_every: int = 100
     skin: float = 0.3
+    inner_skin: float = 0.1       # pruned lists' buffer between list builds (see rbc_params.inner_skin)
     lloyd_iters: int = 10
     protein_cells: int = 0        # 1: protein beads get their own Voronoi cells (detached cytoskeleton)
     vol_k: float = 0.0            # harmonic volume constraint k_V (0: off)

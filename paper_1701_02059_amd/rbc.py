@@ -38,7 +38,7 @@ class RbcParams(C.Structure):
                 ("protein_cells", C.c_int32),
                 ("vol_k", C.c_double), ("vol_target", C.c_double), ("lipid_area", C.c_double),
                 ("kT", C.c_double), ("gamma", C.c_double), ("gamma_rot", C.c_double), ("seed", C.c_uint64),
-                ("quench_max", C.c_double), ("quench", C.c_int32)]
+                ("quench_max", C.c_double), ("quench", C.c_int32), ("inner_skin", C.c_double)]
 
 
 class RbcError(RuntimeError):
@@ -121,6 +121,7 @@ def make_params(mp, precision: int = RBC_FP64) -> RbcParams:
     p.lipid_area = float(mp.lipid_area)
     p.kT, p.gamma, p.gamma_rot, p.seed = float(mp.kT), float(mp.gamma), float(mp.gamma_rot), int(mp.seed)
     p.quench, p.quench_max = int(getattr(mp, "quench", 0)), float(getattr(mp, "quench_max", 0.05))
+    p.inner_skin = float(getattr(mp, "inner_skin", 0.0))
     return p
 
 
@@ -223,10 +224,10 @@ class Context:
         return out
 
     def stats(self) -> dict:
-        out = np.zeros(10, dtype=np.int64)
+        out = np.zeros(11, dtype=np.int64)
         _check(self._h, lib().rbc_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))))
         keys = ["steps", "rebuilds", "early_rebuilds", "cells", "max_list_rows", "max_cell_pairs", "n", "lipids",
-                "lipid_cells", "cell_updates"]
+                "lipid_cells", "cell_updates", "prunes"]
         return dict(zip(keys, (int(v) for v in out)))
 
     def cells(self):
