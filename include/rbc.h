@@ -164,6 +164,19 @@ rbc_status rbc_get_state(rbc_handle h, double *x, double *nrm, double *v, double
  * [host] ij: cap x 2.  *npairs receives the full count even when it exceeds cap. */
 rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs);
 
+/* rbc_get_pairs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pairs, sorted the same way, but staged in a static device array of 32 MiB that
+ * each GPU the library runs on holds until the process ends, instead of a buffer the
+ * library allocates.  It calls no hipMalloc, hipFree or other allocating routine.
+ * Limits: at most (32 MiB - 256 B) / 8 = 4,194,272 pairs; a larger set returns
+ * RBC_ERR_CAPACITY with *npairs unset.  [host] ij: cap x 2; the sorted pairs are
+ * written only when cap >= the count (otherwise nothing is written and *npairs
+ * receives the count).  Every call on one GPU shares that GPU's staging array, which
+ * keeps the last call's contents: calls that overlap on one GPU (from several
+ * threads or contexts) race and must be serialised by the caller. (sync) */
+rbc_status rbc_get_pairs_noalloc(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs);
+
 /* Energies of the current state (sync).  [host] out[7]: U (with U_V when the
  * volume constraint is on), W (pairs and bonds), kinetic energy (translational +
  * lipid rotational), total E = KE + U, |sum F|, |sum (r x F + tau)|, and the

@@ -17,6 +17,8 @@
 // velocity); the second half-kick is fused into the force kernel's epilogue.
 #include "rbc_dev.h"
 
+#include <mutex>
+
 namespace rbc {
 
 __device__ __forceinline__ int lane_id_f() { return threadIdx.x & (WAVE - 1); }
@@ -1244,7 +1246,7 @@ __device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, in
     return S.nl[at];
 }
 
-__global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
+__global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P, int32_t *out, int64_t cap, int32_t *count) {
     const SysDev &S = Sd[s];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < S.n;
@@ -1270,7 +1272,7 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
             tot = __shfl(ex, 63);
             ex -= mine;
             int wb = 0;
-            if (lane_id_f() == 0 && tot > 0) wb = atomicAdd(&S.sc->npairs, tot);
+            if (lane_id_f() == 0 && tot > 0) wb = atomicAdd(count, tot);
             base = __shfl(wb, 0) + ex;
         }
         int k = 0;
@@ -1283,9 +1285,9 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
             double dx, dy, dz;
             const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
             if (d2 < P.rc2[ti][(int)pj.w]) {
-                if (pass == 1 && (int64_t)(base + k) < S.pairs_cap) {
-                    S.pairs[2 * (base + k)] = gi;
-                    S.pairs[2 * (base + k) + 1] = gj;
+                if (pass == 1 && (int64_t)(base + k) < cap) {
+                    out[2 * (base + k)] = gi;
+                    out[2 * (base + k) + 1] = gj;
                 }
                 ++k;
             }
@@ -1294,9 +1296,47 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P) {
     }
 }
 
-void launch_export_pairs(const LaunchCtx &L, int sys, int count) {
+void launch_export_pairs(const LaunchCtx &L, int sys, int count, int32_t *out, int64_t cap, int32_t *counter) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_export_pairs, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, L.st, L.S, sys, L.prm);
+    hipLaunchKernelGGL(k_export_pairs, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, L.st, L.S, sys, L.prm, out,
+                       cap, counter);
+}
+
+// ------------------------------------------------------------------ allocation-free pair export
+
+// Staging for the pair export of rbc_get_pairs_noalloc, for callers that cannot
+// allocate device memory: a counter in the first word, then up to PAIR_SCRATCH_PAIRS
+// pairs from byte 256 on.  Each device holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns on that
+// device (pair_scratch_address), never through the array's name.
+constexpr int64_t PAIR_SCRATCH_BYTES = 32ll << 20;
+static __device__ __align__(256) int32_t scratch[PAIR_SCRATCH_BYTES / 4];
+
+__global__ void k_zero_counter(int32_t *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+hipError_t pair_scratch_address(int device, void **out) {
+    static std::mutex mtx;
+    static void *addr[64] = {};
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mtx);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;      // the caller makes the device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+void launch_zero_counter(const LaunchCtx &L, int32_t *p) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, L.st, p);
 }
 
 }  // namespace rbc

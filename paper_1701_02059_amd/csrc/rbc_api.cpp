@@ -81,6 +81,7 @@ struct rbc_ctx {
     int32_t *d_maps = nullptr;
     int32_t *d_umaps = nullptr;       // block maps of the systems in the running cell update
     int32_t *d_pmaps = nullptr;       // particle-block map of the systems pruned at this step
+    int32_t *pair_scratch = nullptr;  // this device's static staging of the allocation-free pair export
     const int32_t **d_lip = nullptr;
     SysScal *h_sc = nullptr;          // pinned mirror of the per-system scalars (read after a sync)
     StepStat *h_stat = nullptr, *d_stat = nullptr;   // published drift statistics: host / device view
@@ -922,6 +923,10 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
     if (ok) std::memset(h->h_stat, 0, sizeof(StepStat) * MAX_SLOTS * STAT_RING);
     for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->step_ev[q], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemset(h->d_sc, 0, sizeof(SysScal) * max_slots) == hipSuccess;
+    // the allocation-free pair export's staging on this device, looked up once here
+    void *ps = nullptr;
+    if (ok) ok = pair_scratch_address(h->device, &ps) == hipSuccess;
+    h->pair_scratch = (int32_t *)ps;
     if (ok) ok = refresh_tables(h) == RBC_OK;
     if (!ok) {
         rbc_destroy(h);
@@ -1103,7 +1108,7 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
         {
             Scope sc(h);
             HIPCHK(hipMemsetAsync(&h->d_sc[0].npairs, 0, sizeof(int32_t), h->st));
-            launch_export_pairs(h->L, 0, (int)hs.n);
+            launch_export_pairs(h->L, 0, (int)hs.n, hs.dev.pairs, hs.pairs_cap, &h->d_sc[0].npairs);
             HIPCHK(hipMemcpyAsync(&count, &h->d_sc[0].npairs, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
             HIPCHK(hipStreamSynchronize(h->st));
         }
@@ -1122,6 +1127,36 @@ rbc_status rbc_get_pairs(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs
         return RBC_OK;
     }
     return fail(h, RBC_ERR_CAPACITY, "pair export overflow");
+}
+
+rbc_status rbc_get_pairs_noalloc(rbc_handle h, int64_t cap, int32_t *ij, int64_t *npairs) {
+    if (!h || !npairs || cap < 0 || (cap > 0 && !ij)) return RBC_ERR_INVALID_ARG;
+    HostSys &hs = h->sys[0];
+    if (!hs.live) return fail(h, RBC_ERR_NOT_READY, "no system loaded");
+    if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
+    if (!h->pair_scratch) return fail(h, RBC_ERR_HIP, "no staging for the allocation-free export on this device");
+    int32_t *counter = h->pair_scratch;
+    int32_t *out = h->pair_scratch + 64;                 // pairs from byte 256
+    int32_t count = 0;
+    {
+        Scope sc(h);
+        launch_zero_counter(h->L, counter);
+        launch_export_pairs(h->L, 0, (int)hs.n, out, PAIR_SCRATCH_PAIRS, counter);
+        HIPCHK(hipMemcpyAsync(&count, counter, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+    }
+    if ((int64_t)count > PAIR_SCRATCH_PAIRS)
+        return fail(h, RBC_ERR_CAPACITY, std::to_string(count) + " pairs exceed the allocation-free export's " +
+                                             std::to_string(PAIR_SCRATCH_PAIRS));
+    *npairs = count;
+    if (cap < count || count == 0) return RBC_OK;        // a size query: nothing written
+    HIPCHK(hipMemcpy(ij, out, sizeof(int32_t) * 2 * (size_t)count, hipMemcpyDeviceToHost));
+    struct Pair {
+        int32_t i, j;
+    };
+    Pair *p = reinterpret_cast<Pair *>(ij);               // sorted in the caller's buffer, in place
+    std::sort(p, p + count, [](const Pair &a, const Pair &b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+    return RBC_OK;
 }
 
 static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {

@@ -297,7 +297,11 @@ void launch_volume_partials(const LaunchCtx &L);          // lipid sums of the c
 void launch_volume_reduce(const LaunchCtx &L);            // lipid sums -> V, volume force constants
 void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count);
 void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, int count);
-void launch_export_pairs(const LaunchCtx &L, int sys, int count);
+void launch_export_pairs(const LaunchCtx &L, int sys, int count, int32_t *out, int64_t cap, int32_t *counter);
+// the allocation-free export's staging: a counter word, then pairs from byte 256
+constexpr int64_t PAIR_SCRATCH_PAIRS = ((32ll << 20) - 256) / 8;
+hipError_t pair_scratch_address(int device, void **out);   // this device's copy (it must be current)
+void launch_zero_counter(const LaunchCtx &L, int32_t *p);
 // cell update kernels (each predicated on SysScal::rebuild)
 void launch_set_rebuild(const LaunchCtx &L, const unsigned long long m[4]);
 void launch_restrict_maps(const LaunchCtx &L, int32_t *out);   // 7 x (nsys+1) prefix maps of the rebuilding systems

@@ -26,6 +26,7 @@ FUNCTIONS = [
     "rbc_status_string", "rbc_last_error", "rbc_ensemble_create", "rbc_ensemble_footprint", "rbc_ensemble_admit",
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
     "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs", "rbc_ensemble_stage", "rbc_ensemble_commit",
+    "rbc_get_pairs_noalloc",
 ]
 
 
@@ -72,6 +73,7 @@ def lib():
             "rbc_step": [h, C.c_int64, C.c_double],
             "rbc_get_state": [h, vp, vp, vp, vp],
             "rbc_get_pairs": [h, C.c_int64, ip, i64p],
+            "rbc_get_pairs_noalloc": [h, C.c_int64, ip, i64p],
             "rbc_energy": [h, dp],
             "rbc_stats": [h, i64p],
             "rbc_get_cells": [h, ip, dp],
@@ -216,6 +218,15 @@ class Context:
         out = np.zeros((max(1, cnt.value), 2), dtype=np.int32)
         _check(self._h, lib().rbc_get_pairs(self._h, cnt.value, out.ctypes.data_as(C.POINTER(C.c_int32)),
                                             C.byref(cnt)))
+        return out[:cnt.value]
+
+    def get_pairs_noalloc(self) -> np.ndarray:
+        """As get_pairs, through the allocation-free export (rbc_get_pairs_noalloc)."""
+        cnt = C.c_int64(0)
+        _check(self._h, lib().rbc_get_pairs_noalloc(self._h, 0, None, C.byref(cnt)))
+        out = np.zeros((max(1, cnt.value), 2), dtype=np.int32)
+        _check(self._h, lib().rbc_get_pairs_noalloc(self._h, cnt.value, out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                    C.byref(cnt)))
         return out[:cnt.value]
 
     def energy(self) -> np.ndarray:
