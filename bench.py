@@ -31,10 +31,11 @@ DT = 0.01
 # Algorithmic work of the timed force kernel, which also applies the closing
 # half-kick, the next opening half-kick and the drift.  Flops: operation counts
 # of the pair laws as written, once per unordered pair (add/sub/mul 1, FMA 2,
-# sqrt/rsqrt/sin/cos/div 1).
-FLOPS_LIPID_PAIR = 147      # per unordered lipid pair: F_i, F_j, tau_i, tau_j, U, W and the distance test
-FLOPS_WCA_PAIR = 37         # per unordered pair with a protein bead
-FLOPS_BOND = 28             # per bond
+# sqrt/rsqrt/sin/cos/div 1), without the energy and virial terms, which the timed
+# kernel does not compute.
+FLOPS_LIPID_PAIR = 139      # per unordered lipid pair: F_i, F_j, tau_i, tau_j and the distance test
+FLOPS_WCA_PAIR = 29         # per unordered pair with a protein bead
+FLOPS_BOND = 19             # per bond
 # Bytes: the state read and written once per step.  Lipid: read x (24) + type (1) + FP32 n
 # for the partner stage (12) + v, omega, n (72); write x, v, n, omega (96) + FP32 n (12).
 # Protein bead: read x (24) + type (1) + v (24); write x, v (48).
@@ -46,8 +47,8 @@ PEAK_HBM = 8000.0           # GB/s
 # HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
 # skin 0.5: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
-FORCE_TRAFFIC = {"sources_sha256": "76155b89d5fd69fd", "bytes": 2521082635,
-                 "fetch_kib": 955267, "write_kib": 551460,
+FORCE_TRAFFIC = {"sources_sha256": "76155b89d5fd69fd", "skin": 0.5, "inner_skin": None,
+                 "bytes": 2521082635, "fetch_kib": 955267, "write_kib": 551460,
                  "valu_insts": 278759823}   # SQ_INSTS_VALU per launch (wavefront instructions)
 CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
@@ -93,16 +94,21 @@ def timed_run(R, mp, system, precision, steps, warmup, label):
     avg_ms, launches = ctx.force_timing(False)
     st1 = ctx.stats()
     e = ctx.energy()
-    out = {"seconds": t1 - t0, "ms_per_step": (t1 - t0) * 1e3 / steps,
+    ms = (t1 - t0) * 1e3 / steps
+    out = {"seconds": t1 - t0, "steps": steps, "ms_per_step": ms,
            "particle_steps_per_s": system.N * steps / (t1 - t0),
            "force_ms": avg_ms, "force_launches": launches,
+           # everything else a step pays for, amortised: cell updates, list builds,
+           # prunes, the drift statistics and the host loop
+           "other_ms_per_step": ms - avg_ms,
            "cell_updates": st1["cell_updates"] - st0["cell_updates"],
            "list_rebuilds": st1["rebuilds"] - st0["rebuilds"],
            "early_rebuilds": st1["early_rebuilds"] - st0["early_rebuilds"],
+           "prunes": st1["prunes"] - st0["prunes"],
            "max_list_rows": st1["max_list_rows"], "energy": e.tolist()}
     log(f"[{label}] {steps} steps in {t1 - t0:.3f} s -> {out['particle_steps_per_s']:.4g} particle-steps/s, "
         f"force kernel {avg_ms * 1e3:.1f} us avg over {launches} launches, {out['cell_updates']} cell updates, "
-        f"{out['list_rebuilds']} list builds")
+        f"{out['list_rebuilds']} list builds, {out['prunes']} prunes")
     return ctx, out
 
 
@@ -122,20 +128,72 @@ def _oracle_steps(system, mp, threads):
     return per_step, t2 - t0
 
 
+def host_cpu():
+    """Model name and usable core count of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(system, mp):
-    """The FP64 oracle on this host, on all cores (the full cell) and on one core (the
-    499,952-particle cell), in particle-steps/s."""
-    from paper_1701_02059_amd import inputs as I
+    """The FP64 oracle on this host: on all usable cores on the full cell, and on one core
+    on an eighth of the same cell (the particles of smallest x, an open cap of the
+    membrane with the same local density), in particle-steps/s."""
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     per_step, spent = _oracle_steps(system, mp, threads)
-    small = I.config("rbc500k")
-    per1, spent1 = _oracle_steps(small, mp, 1)
+    cut = np.sort(system.x[:, 0])[system.N // 8]
+    piece = system.subset(np.flatnonzero(system.x[:, 0] < cut))
+    per1, spent1 = _oracle_steps(piece, mp, 1)
     return {"value": system.N / per_step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"2 velocity-Verlet steps of the full {system.N:,}-particle cell (3-step minus 1-step run, "
-                      f"{spent:.1f} s of CPU work)", "seconds_per_step": per_step,
-            "one_core": {"value": small.N / per1, "unit": "particle-steps/s", "cores": 1,
-                         "sample": f"2 steps of the {small.N:,}-particle cell (3-step minus 1-step run, "
-                                   f"{spent1:.1f} s)"}}
+                      f"{spent:.1f} s of CPU work)", "seconds_per_step": per_step, "host": host_cpu(),
+            "one_core": {"value": piece.N / per1, "unit": "particle-steps/s", "cores": 1,
+                         "sample": f"2 steps of the {piece.N:,} particles of smallest x of the same cell (an "
+                                   f"eighth; 3-step minus 1-step run, {spent1:.1f} s)"}}
+
+
+def config_leg(R, mp, system, steps, frames, oracle_steps, label):
+    """A plain-FP64 workload: GPU throughput over `steps` timed steps, the NVE energy
+    drift over the same number of steps sampled at `frames` frames, and the FP64
+    oracle's rate on this host over `oracle_steps` steps."""
+    from oracle import oracle as O
+    ctx, r = timed_run(R, mp, system, R.RBC_FP64, steps, 0, label)
+    ctx.close()
+    r.pop("energy", None)
+    ctx = R.Context(mp, R.RBC_FP64)
+    ctx.set_system(system)
+    e = [ctx.energy()[3]]
+    for _ in range(frames):
+        ctx.step(steps // frames, DT)
+        e.append(ctx.energy()[3])
+    ctx.close()
+    e = np.array(e)
+    r["nve"] = {"E0": float(e[0]), "max_abs_dE": float(np.max(np.abs(e - e[0]))),
+                "max_abs_dE_per_particle": float(np.max(np.abs(e - e[0])) / system.N),
+                "drift_per_particle_per_1e4_steps": float((e[-1] - e[0]) / system.N * 1e4 / steps),
+                "frames": frames + 1}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    p = O.params_for(system, mp)
+    t0 = time.perf_counter()
+    O.vv_run(p, system, DT, oracle_steps, nthreads=threads)
+    t1 = time.perf_counter()
+    r["oracle"] = {"value": system.N * oracle_steps / (t1 - t0), "unit": "particle-steps/s", "cores": threads,
+                   "sample": f"{oracle_steps} velocity-Verlet steps (with the initial force evaluation), "
+                             f"{t1 - t0:.1f} s"}
+    r["particles"] = system.N
+    log(f"[{label}] nve {r['nve']} oracle {r['oracle']}")
+    return r
 
 
 def detached_run(R, mp, workload, steps, warmup):
@@ -231,8 +289,11 @@ def main():
     ap.add_argument("--detached-steps", type=int, default=500)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
-    ap.add_argument("--skin", type=float, default=0.5,
-                    help="Verlet skin (sigma); 0.5 is the measured optimum for the membrane workloads")
+    ap.add_argument("--skin", type=float, default=0.6,
+                    help="Verlet skin of the full lists (sigma); measured optimum for the whole cell")
+    ap.add_argument("--inner-skin", type=float, default=0.15,
+                    help="buffer of the pruned lists the step kernel walks (sigma)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the FP64 patch and vesicle legs")
     ap.add_argument("--cell-target", type=int, default=16, help="mean lipids per Voronoi cell")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM-counter calibration)")
@@ -248,12 +309,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     R.lib()
-    mp = I.ModelParams(skin=args.skin, cell_target=args.cell_target)
+    mp = I.ModelParams(skin=args.skin, inner_skin=args.inner_skin, cell_target=args.cell_target)
     t0 = time.perf_counter()
     system = I.config(args.workload)
     log(f"[gen] {args.workload}: N={system.N:,} {system.counts()} in {time.perf_counter() - t0:.1f} s")
 
-    ctx, mixed = timed_run(R, mp, system, R.RBC_MIXED, args.steps, args.warmup, "mixed")
+    # the timed window covers at least two Voronoi update periods, so the rate includes
+    # the amortised cell updates, list builds and prunes
+    steps = max(args.steps, 2 * mp.update_every)
+    ctx, mixed = timed_run(R, mp, system, R.RBC_MIXED, steps, args.warmup, "mixed")
     n_ll, n_wca = pair_counts(ctx, system)
     n_bond = int(system.bonds.shape[0])
     ctx.close()
@@ -269,7 +333,7 @@ def main():
         bound, achieved, peak, unit = "alu", flops / t_force / 1e12, PEAK_FP32, "TFLOP/s"
     digest = kernel_sources_digest()
     counters_valid = (FORCE_TRAFFIC["sources_sha256"] == digest and args.workload == "rbc4m" and
-                      args.skin == 0.5)
+                      args.skin == FORCE_TRAFFIC["skin"] and args.inner_skin == FORCE_TRAFFIC["inner_skin"])
     traffic = FORCE_TRAFFIC["bytes"] if counters_valid else None
     # a wavefront VALU instruction occupies a 16-lane SIMD for 4 cycles
     valu_busy = (FORCE_TRAFFIC["valu_insts"] * 4 / (t_force * CLOCK_GHZ * 1e9 * CU_COUNT * SIMDS_PER_CU)
@@ -308,6 +372,11 @@ def main():
     if not args.no_detached:
         detached = detached_run(R, mp, args.workload, args.detached_steps, min(args.warmup, 20))
 
+    configs = None
+    if not args.no_configs:
+        configs = {"patch_fp64": config_leg(R, mp, I.config("patch"), 100, 10, 100, "patch fp64"),
+                   "vesicle_fp64": config_leg(R, mp, I.config("vesicle"), 1000, 10, 100, "vesicle fp64")}
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(system, mp)
@@ -315,7 +384,7 @@ def main():
 
     serving = None
     if not args.no_serving:
-        smp = I.ModelParams(skin=args.skin)
+        smp = I.ModelParams(skin=args.skin, inner_skin=args.inner_skin)
         serving = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps)
         serving["saturated"] = serving_run(R, smp, args.serving_requests, 20.0, args.serving_steps, saturated=True)
         # the same arrivals with the step replayed as a HIP graph (direct launches are the default)
@@ -337,7 +406,8 @@ def main():
         "value": mixed["particle_steps_per_s"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
+        "steps_requested": args.steps,
         "warmup": args.warmup,
         "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
@@ -348,12 +418,13 @@ def main():
         "config": {"workload": f"whole-RBC biconcave cell ({args.workload}), {system.N:,} particles: "
                                f"{system.counts()['L']:,} lipids, {system.counts()['J']:,} junctions, "
                                f"{system.counts()['S']:,} spectrin beads; dt={DT}, NVE, cells updated every "
-                               f"{mp.update_every} steps, skin {mp.skin}",
+                               f"{mp.update_every} steps, skin {mp.skin}, pruned-list buffer {mp.inner_skin}",
                    "particles": system.N, "precision": "mixed", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": fp64,
         "mixed": mixed,
+        "configs": configs,
         "serving": serving,
         "detached": detached,
         "volume_and_thermostat": ext,

@@ -86,7 +86,7 @@ typedef struct {
                                                    separate set of cells, ceil(N_P / cell_target) of
                                                    them (a detached cytoskeleton) -- Force Evaluation
                                                    section */
-    /* Harmonic volume constraint (the Results section's whole-cell fluctuation run
+    /* Harmonic volume constraint (the Validation and Benchmark section's whole-cell fluctuation run
      * keeps the cell's surface-to-volume ratio with one; its form is a reading):
      * U_V = vol_k/2 (V - V0)^2 / V0 with V = lipid_area/3 sum over lipids of
      * (x_i - xbar).n_i, xbar the lipid centroid (divergence theorem; lipid
@@ -202,6 +202,15 @@ rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds);
  * when timing is enabled), and the number of launches timed. */
 rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_t *launches);
 
+/* Per-step timing of the last rbc_step / rbc_ensemble_step call made while step
+ * timing was on: [host] ms[q] (at most cap) the GPU interval of step q, from the end
+ * of the previous step's launches (for q = 0, the start of the call) to the end of
+ * its own, cell updates, list builds and prunes of that step included; *count the
+ * number of steps; *gap_ms (nullable) the time from the end of the previous timed
+ * call to the start of the last one (-1 when there is none).  enable turns the
+ * timing (an event per step) on or off for later calls. */
+rbc_status rbc_step_times(rbc_handle h, int32_t enable, int64_t cap, double *ms, int64_t *count, double *gap_ms);
+
 /* Replay the step's fixed launch sequence (the force kernel with its fused drift
  * and the drift statistics) as a HIP graph captured once per system table and time
  * step (enable = 1), or launch every kernel directly (0).  Cell updates always
@@ -215,7 +224,9 @@ rbc_status rbc_set_graphs(rbc_handle h, int32_t enable);
  * which: 0 owner (n, slot order), 1 cell start (k+1), 2 cell count (k), 3 cell-pair
  * row start (k+1), 4 cell-pair entries (row start[k]), 5 seed-grid start (cells+1),
  * 6 seeds in grid order (k), 7 centroids with radius (k x 4 doubles), 8 list rows per
- * 64-particle chunk, 9 staged count per 256-particle block, 10 caller id per slot (n).
+ * 64-particle chunk, 9 staged count per 256-particle block, 10 caller id per slot (n),
+ * 11 segmented-scan tile sums, 12 pruned stage count per 256-particle block (-1: the
+ * block keeps its full 32-bit lists), 13 pruned-list rows per 64-particle chunk.
  * Integer arrays are int32.  [host] out receives at most cap bytes; *bytes the full size. */
 rbc_status rbc_debug_array(rbc_handle h, int32_t which, int64_t cap, void *out, int64_t *bytes);
 
@@ -246,8 +257,8 @@ rbc_status rbc_ensemble_admit(rbc_handle h, int64_t n, const double *x, const do
  * rbc_ensemble_admit does (same arguments, same errors, *slot receives the slot;
  * the input arrays may be released on return) but leaves its cell build pending.
  * rbc_ensemble_commit then builds the cells of every pending slot in one set of
- * launches: the seeding, Lloyd iterations and reordering of the Voronoi
- * Tessellation section, then the cell pairs and lists of the Force Evaluation
+ * launches: the seeding, Lloyd iterations and reordering of the Spatial
+ * Searching Algorithm section, then the cell pairs and lists of the Force Evaluation
  * section.  Each system's result equals that of rbc_ensemble_admit.  A slot whose
  * build fails (capacity, non-finite input) is released and its index written to
  * failed[0..min(*nfailed, cap)); rbc_last_error holds the first failure's message,
@@ -267,6 +278,17 @@ rbc_status rbc_ensemble_get_state(rbc_handle h, int32_t slot, double *x, double 
 rbc_status rbc_ensemble_energy(rbc_handle h, int32_t slot, double *out);
 /* Free a slot and its memory. */
 rbc_status rbc_ensemble_retire(rbc_handle h, int32_t slot);
+/* Slots frozen by an error (ensemble contexts).  When a slot's lists overflow
+ * (RBC_ERR_CAPACITY), its state turns non-finite (RBC_ERR_NONFINITE) or a particle
+ * outruns the skin (RBC_ERR_SKIN) during rbc_ensemble_step, that call returns the
+ * first such status, every other live slot has still advanced nsteps, and the failed
+ * slot is frozen: it keeps its slot and memory but takes no further part in any
+ * launch, and its state and energy calls return its status, until it is retired.  A
+ * retry cannot help these errors (an overflow is fixed by the positions, which the
+ * steps with truncated lists already changed), so the library isolates the slot
+ * instead.  [host] slots, status: the failed slots and their statuses, at most cap;
+ * *count receives the full number. */
+rbc_status rbc_ensemble_failed(rbc_handle h, int64_t cap, int32_t *slots, int32_t *status, int64_t *count);
 /* [host] out[4]: live slots, device bytes in use, budget, steps done by the ensemble. */
 rbc_status rbc_ensemble_info(rbc_handle h, int64_t *out);
 

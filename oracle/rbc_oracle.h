@@ -114,7 +114,7 @@ int orc_vv_run(const orc_params *p, int64_t n, double *x, double *v, double *nrm
                double dt, int64_t nsteps, double *energies, int nthreads);
 
 /* ---- Beyond the conservative model: a harmonic volume constraint (the
- * whole-cell fluctuation run of the Results section keeps the cell's
+ * whole-cell fluctuation run of the Validation and Benchmark section keeps the cell's
  * surface-to-volume ratio with one) and a Langevin thermostat.  The paper
  * states neither form; these are readings. */
 typedef struct {

@@ -50,7 +50,12 @@ struct HostSys {
     double disp2 = 0.0, v2 = 0.0, disp2p = 0.0;
     uint64_t drifts = 0;             // statistics passes since loading (the device's step counter)
     bool pending = false;            // staged: uploaded, cells not built yet
+    rbc_status failed = RBC_OK;      // ensemble slot frozen by an error (held until retired)
+    std::string why;                 // its message
 };
+
+// A slot whose system takes part in launches: live, and not frozen by an error.
+bool runs(const HostSys &hs) { return hs.live && hs.failed == RBC_OK; }
 
 struct Carve {
     char *base;
@@ -100,6 +105,13 @@ struct rbc_ctx {
     int64_t graph_version = -1;
     double graph_dt = 0.0;
     hipGraphExec_t g_step = nullptr, g_last = nullptr;
+    // per-step timing (events at the end of every step of a call)
+    bool step_timing = false;
+    std::vector<hipEvent_t> ev_step;
+    hipEvent_t ev_call0 = nullptr, ev_prev_end = nullptr, ev_prev_end_last = nullptr;
+    bool have_prev_end = false;
+    std::vector<double> step_ms;      // the last call's step intervals
+    double gap_ms = -1.0;             // from the previous call's last step to the last call's start
     // force-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tb, te;
@@ -306,6 +318,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
     for (int s = 0; s < h->max_slots; ++s)
         if (h->sys[s].live) top = s + 1;
     h->nsys = std::max(top, 1);
+    // frozen slots keep their memory but get an empty descriptor: no kernel touches them
     const int ns = h->nsys;
     std::vector<SysDev> tab(ns);
     std::vector<const int32_t *> lips(ns, nullptr);
@@ -315,22 +328,23 @@ rbc_status refresh_tables(rbc_ctx *h) {
     for (int s = 0; s < ns; ++s) {
         HostSys &hs = h->sys[s];
         SysDev d{};
-        if (hs.live) {
+        if (runs(hs)) {
             d = hs.dev;
             lips[s] = hs.lip;
         }
         d.sc = h->d_sc + s;
         d.hstat = h->d_stat + (size_t)s * STAT_RING;
         tab[s] = d;
-        const int64_t n = hs.live ? hs.n : 0;
-        const int32_t k = hs.live ? hs.k : 0;
+        const bool on = runs(hs);
+        const int64_t n = on ? hs.n : 0;
+        const int32_t k = on ? hs.k : 0;
         mp[s + 1] = mp[s] + (int32_t)((n + BLOCK - 1) / BLOCK);
         mc[s + 1] = mc[s] + (k + BLOCK - 1) / BLOCK;
-        mg[s + 1] = mg[s] + (hs.live ? (hs.gcap + BLOCK - 1) / BLOCK : 0);
-        mtp[s + 1] = mtp[s] + (hs.live ? hs.ntile_p : 0);
-        mts[s + 1] = mts[s] + (hs.live ? hs.ntile_s : 0);
+        mg[s + 1] = mg[s] + (on ? (hs.gcap + BLOCK - 1) / BLOCK : 0);
+        mtp[s + 1] = mtp[s] + (on ? hs.ntile_p : 0);
+        mts[s + 1] = mts[s] + (on ? hs.ntile_s : 0);
         msc[s + 1] = msc[s] + (k + SCAN_TILE - 1) / SCAN_TILE;
-        msg[s + 1] = msg[s] + (hs.live ? (hs.gcap + SCAN_TILE - 1) / SCAN_TILE : 0);
+        msg[s + 1] = msg[s] + (on ? (hs.gcap + SCAN_TILE - 1) / SCAN_TILE : 0);
         mf[s + 1] = mf[s] + (mp[s + 1] - mp[s]) * (d.split ? 4 : 1);
     }
     HIPCHK(hipMemcpyAsync(h->d_sys, tab.data(), sizeof(SysDev) * ns, hipMemcpyHostToDevice, h->st));
@@ -366,7 +380,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
 
 bool any_live(const rbc_ctx *h) {
     for (const auto &s : h->sys)
-        if (s.live) return true;
+        if (runs(s)) return true;
     return false;
 }
 
@@ -497,11 +511,37 @@ rbc_status slot_error(rbc_ctx *h, int s, int e) {
 
 rbc_status read_errors(rbc_ctx *h, const SysScal *sc) {
     for (int s = 0; s < h->nsys; ++s) {
-        if (!h->sys[s].live) continue;
+        if (!runs(h->sys[s])) continue;
         const rbc_status r = slot_error(h, s, sc[s].err);
         if (r != RBC_OK) return r;
     }
     return RBC_OK;
+}
+
+// Ensemble contexts: after a synchronised step call, every slot whose error bits are set
+// (or that the host loop found in error) is frozen -- it keeps its memory and its slot
+// but leaves every launch -- so that the other slots go on.  Returns the first status.
+rbc_status freeze_failed(rbc_ctx *h, const std::vector<std::pair<int, std::string>> &host_err) {
+    rbc_status first = RBC_OK;
+    std::string first_why;
+    bool changed = false;
+    auto freeze = [&](int s, rbc_status r, const std::string &why) {
+        HostSys &hs = h->sys[s];
+        if (!runs(hs)) return;
+        hs.failed = r;
+        hs.why = why;
+        changed = true;
+        if (first == RBC_OK) { first = r; first_why = why; }
+    };
+    for (int s = 0; s < h->nsys; ++s) {
+        if (!runs(h->sys[s])) continue;
+        const rbc_status r = slot_error(h, s, h->h_sc[s].err);
+        if (r != RBC_OK) freeze(s, r, h->err);
+    }
+    for (const auto &e : host_err) freeze(e.first, RBC_ERR_SKIN, e.second);
+    if (changed) refresh_tables(h);
+    if (first != RBC_OK) h->err = first_why;
+    return first;
 }
 
 bool any_pending(const rbc_ctx *h) {
@@ -616,6 +656,20 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
     const double din = inner_skin(h->prm);
     const int64_t K = h->prm.update_every;
     rbc_status out = RBC_OK;
+    std::vector<std::pair<int, std::string>> slot_err;   // ensembles: per-slot errors of the host loop
+    auto host_fail = [&](int s, rbc_status r, const std::string &msg) {
+        if (h->ensemble) slot_err.emplace_back(s, msg);
+        else if (out == RBC_OK) out = fail(h, r, msg);
+    };
+    const bool timed = h->step_timing;
+    if (timed) {
+        while ((int64_t)h->ev_step.size() < nsteps) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return fail(h, RBC_ERR_HIP, "hipEventCreate");
+            h->ev_step.push_back(e);
+        }
+        hipEventRecord(h->ev_call0, h->st);
+    }
     launch_kick_drift(h->L, dt);
     h->vol_fresh = true;              // every drift also writes the volume's lipid sums
     for (int64_t st = 0; st < nsteps; ++st) {
@@ -632,7 +686,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         std::vector<int> which, full, lists, pruned;
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
-            if (!hs.live) continue;
+            if (!runs(hs)) continue;
             hs.steps_since++;
             if (hs.steps_since >= K) {
                 full.push_back(s);
@@ -664,11 +718,12 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             if (!last) launch_drift_stats_swap(h->L);
         }
         if (!last) swap_drift_buffers(h);
+        if (timed) hipEventRecord(h->ev_step[st], h->st);
         // while the force runs, read this step's drift statistics
         hipEventSynchronize(h->step_ev[slot]);
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
-            if (!hs.live) continue;
+            if (!runs(hs)) continue;
             const bool rebuilt = std::find(which.begin(), which.end(), s) != which.end();
             const bool was_pruned = std::find(pruned.begin(), pruned.end(), s) != pruned.end();
             double d2 = 0.0, v2 = 0.0, d2p = 0.0;
@@ -683,10 +738,10 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             }
             // the force of this step walked the pruned lists: they had to hold every pair in
             // range, and a prune at this step needed the full lists to hold its radius
-            if (!rebuilt && !was_pruned && d2p > din * din && out == RBC_OK)
-                out = fail(h, RBC_ERR_SKIN, "a particle moved beyond the pruned lists' buffer before they were pruned again (slot " + std::to_string(s) + ")");
-            if (was_pruned && d2 > (skin - din) * (skin - din) && out == RBC_OK)
-                out = fail(h, RBC_ERR_SKIN, "a particle moved beyond the skin before its lists were rebuilt (slot " + std::to_string(s) + ")");
+            if (!rebuilt && !was_pruned && d2p > din * din)
+                host_fail(s, RBC_ERR_SKIN, "a particle moved beyond the pruned lists' buffer before they were pruned again (slot " + std::to_string(s) + ")");
+            if (was_pruned && d2 > (skin - din) * (skin - din))
+                host_fail(s, RBC_ERR_SKIN, "a particle moved beyond the skin before its lists were rebuilt (slot " + std::to_string(s) + ")");
             hs.disp2 = d2;
             hs.disp2p = d2p;
             hs.v2 = std::max(v2, hs.rebuilt_last ? 0.0 : hs.v2);
@@ -701,8 +756,32 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         }
     }
     h->ens_steps += nsteps;
-    rbc_status e = sync_and_check(h);
+    if (timed) hipEventRecord(h->ev_prev_end, h->st);
+    rbc_status e;
+    if (h->ensemble) {
+        // one slot's error freezes that slot only; the others have advanced nsteps
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess) return fail(h, RBC_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(le));
+        HIPCHK(hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(SysScal) * h->nsys, hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        e = freeze_failed(h, slot_err);
+    } else {
+        e = sync_and_check(h);
+    }
     harvest_timing(h);
+    if (timed) {
+        h->step_ms.assign((size_t)nsteps, 0.0);
+        for (int64_t st = 0; st < nsteps; ++st) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, st == 0 ? h->ev_call0 : h->ev_step[st - 1], h->ev_step[st]);
+            h->step_ms[st] = ms;
+        }
+        float gap = -1.f;
+        if (h->have_prev_end && hipEventElapsedTime(&gap, h->ev_prev_end_last, h->ev_call0) != hipSuccess) gap = -1.f;
+        h->gap_ms = gap;
+        std::swap(h->ev_prev_end, h->ev_prev_end_last);   // this call's end is the next call's reference
+        h->have_prev_end = true;
+    }
     if (e != RBC_OK) return e;
     return out;
 }
@@ -769,6 +848,13 @@ rbc_status stage(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
         hipFree(mem);
         return fail(h, RBC_ERR_HIP, "hipMemset of a new system failed");
     }
+    // from here on every error path must free the allocation: the slot does not own it yet
+    struct FreeOnError {
+        void *p;
+        ~FreeOnError() {
+            if (p) hipFree(p);
+        }
+    } guard{mem};
     fresh.mem = mem;
     fresh.bytes = bytes;
     layout(fresh, (char *)mem);
@@ -812,6 +898,7 @@ rbc_status stage(rbc_ctx *h, int32_t slot, int64_t n, const double *x, const dou
     HIPCHK(hipMemcpy(h->d_sc + slot, &zero, sizeof(SysScal), hipMemcpyHostToDevice));
     std::memset(h->h_stat + (size_t)slot * STAT_RING, 0, sizeof(StepStat) * STAT_RING);
     hs = fresh;
+    guard.p = nullptr;                     // the slot owns the allocation now (release() frees it)
     h->vol_fresh = false;
     h->used += (int64_t)bytes;
     hs.pending = true;
@@ -922,6 +1009,8 @@ rbc_status create(const rbc_params *params, void *stream, int32_t max_slots, int
               hipHostGetDevicePointer((void **)&h->d_stat, h->h_stat, 0) == hipSuccess;
     if (ok) std::memset(h->h_stat, 0, sizeof(StepStat) * MAX_SLOTS * STAT_RING);
     for (int q = 0; ok && q < RING; ++q) ok = hipEventCreateWithFlags(&h->step_ev[q], hipEventDisableTiming) == hipSuccess;
+    if (ok) ok = hipEventCreate(&h->ev_call0) == hipSuccess && hipEventCreate(&h->ev_prev_end) == hipSuccess &&
+                 hipEventCreate(&h->ev_prev_end_last) == hipSuccess;
     if (ok) ok = hipMemset(h->d_sc, 0, sizeof(SysScal) * max_slots) == hipSuccess;
     // the allocation-free pair export's staging on this device, looked up once here
     void *ps = nullptr;
@@ -979,6 +1068,9 @@ rbc_status rbc_destroy(rbc_handle h) {
     for (auto e : h->tb) hipEventDestroy(e);
     for (auto e : h->te) hipEventDestroy(e);
     for (int q = 0; q < RING; ++q) if (h->step_ev[q]) hipEventDestroy(h->step_ev[q]);
+    for (auto e : h->ev_step) hipEventDestroy(e);
+    for (hipEvent_t e : {h->ev_call0, h->ev_prev_end, h->ev_prev_end_last})
+        if (e) hipEventDestroy(e);
     if (h->d_sys) hipFree(h->d_sys);
     if (h->d_sc) hipFree(h->d_sc);
     if (h->d_maps) hipFree(h->d_maps);
@@ -1013,7 +1105,7 @@ rbc_status rbc_update_cells(rbc_handle h, int32_t lloyd_iters) {
     if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     std::vector<int> which;
     for (int s = 0; s < h->nsys; ++s)
-        if (h->sys[s].live) which.push_back(s);
+        if (runs(h->sys[s])) which.push_back(s);
     {
         Scope sc(h);
         run_update(h, which, lloyd_iters);
@@ -1071,6 +1163,7 @@ rbc_status rbc_set_graphs(rbc_handle h, int32_t enable) {
 
 static rbc_status state_slot(rbc_handle h, int32_t slot, double *x, double *nrm, double *v, double *w) {
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
+    if (h->sys[slot].failed != RBC_OK) return fail(h, h->sys[slot].failed, "slot failed: " + h->sys[slot].why);
     Scope sc(h);
     launch_scatter_state(h->L, slot, x, nrm, v, w, (int)h->sys[slot].n);
     return RBC_OK;
@@ -1161,6 +1254,7 @@ rbc_status rbc_get_pairs_noalloc(rbc_handle h, int64_t cap, int32_t *ij, int64_t
 
 static rbc_status energy_slot(rbc_handle h, int32_t slot, double *out) {
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
+    if (h->sys[slot].failed != RBC_OK) return fail(h, h->sys[slot].failed, "slot failed: " + h->sys[slot].why);
     if (any_pending(h)) return fail(h, RBC_ERR_NOT_READY, "staged systems wait for rbc_ensemble_commit");
     {
         Scope sc(h);
@@ -1285,6 +1379,8 @@ rbc_status rbc_debug_array(rbc_handle h, int32_t which, int64_t cap, void *out, 
         case 9: src = d.scount; nb = 4 * ((hs.n + BLOCK - 1) / BLOCK); break;
         case 10: src = d.gid; nb = 4 * hs.n; break;
         case 11: src = d.tsum; nb = 4 * (int64_t)(std::max((hs.k + SCAN_TILE - 1) / SCAN_TILE, (hs.gcap + SCAN_TILE - 1) / SCAN_TILE) + 2); break;
+        case 12: src = d.iscount; nb = 4 * ((hs.n + BLOCK - 1) / BLOCK); break;
+        case 13: src = d.ilk; nb = 4 * (int64_t)hs.nchunk; break;
         default: return fail(h, RBC_ERR_INVALID_ARG, "unknown array");
     }
     *bytes = nb;
@@ -1349,6 +1445,34 @@ rbc_status rbc_ensemble_retire(rbc_handle h, int32_t slot) {
     if (!h) return RBC_ERR_INVALID_ARG;
     if (slot < 0 || slot >= h->max_slots || !h->sys[slot].live) return fail(h, RBC_ERR_NOT_READY, "slot not live");
     release(h, slot);
+    return RBC_OK;
+}
+
+rbc_status rbc_ensemble_failed(rbc_handle h, int64_t cap, int32_t *slots, int32_t *status, int64_t *count) {
+    if (!h || !count || cap < 0 || (cap > 0 && (!slots || !status))) return RBC_ERR_INVALID_ARG;
+    int64_t c = 0;
+    for (int s = 0; s < h->max_slots; ++s) {
+        const HostSys &hs = h->sys[s];
+        if (!hs.live || hs.failed == RBC_OK) continue;
+        if (c < cap) {
+            slots[c] = s;
+            status[c] = (int32_t)hs.failed;
+        }
+        ++c;
+    }
+    *count = c;
+    return RBC_OK;
+}
+
+rbc_status rbc_step_times(rbc_handle h, int32_t enable, int64_t cap, double *ms, int64_t *count, double *gap_ms) {
+    if (!h || !count || cap < 0 || (cap > 0 && !ms)) return RBC_ERR_INVALID_ARG;
+    const int64_t n = (int64_t)h->step_ms.size();
+    for (int64_t q = 0; q < std::min(cap, n); ++q) ms[q] = h->step_ms[q];
+    *count = n;
+    if (gap_ms) *gap_ms = h->gap_ms;
+    const bool on = enable != 0;
+    if (on && !h->step_timing) h->have_prev_end = false;   // gaps count from the first timed call
+    h->step_timing = on;
     return RBC_OK;
 }
 

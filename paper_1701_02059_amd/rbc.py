@@ -26,7 +26,7 @@ FUNCTIONS = [
     "rbc_status_string", "rbc_last_error", "rbc_ensemble_create", "rbc_ensemble_footprint", "rbc_ensemble_admit",
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
     "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs", "rbc_ensemble_stage", "rbc_ensemble_commit",
-    "rbc_get_pairs_noalloc",
+    "rbc_get_pairs_noalloc", "rbc_ensemble_failed", "rbc_step_times",
 ]
 
 
@@ -74,6 +74,8 @@ def lib():
             "rbc_get_state": [h, vp, vp, vp, vp],
             "rbc_get_pairs": [h, C.c_int64, ip, i64p],
             "rbc_get_pairs_noalloc": [h, C.c_int64, ip, i64p],
+            "rbc_ensemble_failed": [h, C.c_int64, ip, ip, i64p],
+            "rbc_step_times": [h, C.c_int32, C.c_int64, dp, i64p, dp],
             "rbc_energy": [h, dp],
             "rbc_stats": [h, i64p],
             "rbc_get_cells": [h, ip, dp],
@@ -163,6 +165,17 @@ class _Uploaded:
         self.r0 = torch.as_tensor(np.ascontiguousarray(system.r0), **f64) if self.nbond else None
         self.box = (C.c_double * 3)(*[float(v) for v in system.box])
         self.per = (C.c_int32 * 3)(*[int(v) for v in system.periodic])
+
+
+def _step_times(h, enable):
+    n = C.c_int64(0)
+    gap = C.c_double(-1.0)
+    _check(h, lib().rbc_step_times(h, int(bool(enable)), 0, None, C.byref(n), C.byref(gap)))
+    ms = np.zeros(max(1, n.value))
+    # the second call returns the same record (the timing switch is already set)
+    _check(h, lib().rbc_step_times(h, int(bool(enable)), n.value, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.byref(n), C.byref(gap)))
+    return ms[:n.value], gap.value
 
 
 class Context:
@@ -261,6 +274,10 @@ class Context:
 
     def set_graphs(self, enable: bool = True):
         _check(self._h, lib().rbc_set_graphs(self._h, int(bool(enable))))
+
+    def step_times(self, enable: bool = True):
+        """As Ensemble.step_times."""
+        return _step_times(self._h, enable)
 
     def force_timing(self, enable: bool = True):
         avg = C.c_double(0.0)
@@ -361,6 +378,21 @@ class Ensemble:
     def retire(self, slot: int):
         _check(self._h, lib().rbc_ensemble_retire(self._h, int(slot)))
         self.sizes.pop(slot, None)
+
+    def failed(self) -> dict:
+        """Slots frozen by an error: {slot: status}."""
+        n = C.c_int64(0)
+        _check(self._h, lib().rbc_ensemble_failed(self._h, 0, None, None, C.byref(n)))
+        slots = np.zeros(max(1, n.value), dtype=np.int32)
+        st = np.zeros(max(1, n.value), dtype=np.int32)
+        _check(self._h, lib().rbc_ensemble_failed(self._h, n.value, slots.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  st.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+        return {int(slots[q]): int(st[q]) for q in range(n.value)}
+
+    def step_times(self, enable: bool = True):
+        """Per-step GPU intervals (ms) of the last step call and the gap (ms) since the
+        previous timed call (-1: none); turns step timing on or off for later calls."""
+        return _step_times(self._h, enable)
 
     def info(self) -> dict:
         out = np.zeros(4, dtype=np.int64)

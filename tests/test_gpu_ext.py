@@ -1,7 +1,7 @@
 """Harmonic volume constraint and Langevin thermostat, GPU path vs the FP64 oracle
 through the C ABI.
 
-The volume term (the Results section's whole-cell run keeps the cell's
+The volume term (the Validation and Benchmark section's whole-cell run keeps the cell's
 surface-to-volume ratio with one) is checked as a force at both precision
 bounds; the thermostat through FP64 trajectories against the oracle's (same
 Philox draws on both sides), call-chunking neutrality, batch independence and

@@ -1,12 +1,13 @@
 """Parity at full workload sizes, in the launch configuration the benchmark times.
 
 * Whole cell, 3,999,952 particles (3.6M lipids on the Evans-Fung biconcave
-  surface, 16,000 junctions, 383,952 spectrin beads): mixed precision with
-  velocity-Verlet steps and Voronoi cell updates (every 100 steps or earlier on
-  the skin), then the complete neighbour-pair set against the oracle's
-  uniform-grid enumeration bit for bit, and the forces and torques of sampled
-  particles against the oracle's brute-force sum over all N particles.  The same
-  in FP64 mode at the FP64 bound.
+  surface, 16,000 junctions, 383,952 spectrin beads), with the benchmark's skins:
+  - mixed precision, velocity-Verlet steps with Voronoi cell updates, list builds
+    and prunes: the complete neighbour-pair set against the oracle's uniform-grid
+    enumeration bit for bit, and the forces and torques of every particle against
+    the oracle's at frames 0, 100 and 200 (relative RMS and per-particle error);
+  - FP64 mode: every particle's force and torque at a frame after 12 steps, at the
+    FP64 bound.
 * Long run, 499,952-particle cell: 20,000 mixed-precision steps with the force
   and torque error against the full FP64 oracle on every 1,000th frame, and the
   energy drift per 10^4 steps.
@@ -20,14 +21,14 @@ import pytest
 
 from oracle import oracle as O
 from paper_1701_02059_amd import inputs as I
-from tests.gpu_common import rel_err, to_np
+from tests.gpu_common import PP_FP64_TOL, PP_MIXED_TOL, check_forces, pp_err, rel_err, to_np
 
 pytestmark = pytest.mark.gpu
 
 DT = 0.01
 FP64_TOL = 1e-10
 MIXED_TOL = 1e-5
-SKIN = 0.5          # the benchmark's Verlet skin for the whole-cell workload
+SKIN, INNER = 0.6, 0.15   # the benchmark's skins for the whole-cell workload
 
 
 @pytest.fixture(scope="module")
@@ -44,50 +45,59 @@ def cell():
     return I.config("rbc4m")
 
 
-def _sample(system, seed=7):
-    """Sampled particles: lipids, spectrin beads and every 40th junction, plus the
-    first and last ids (ragged ends of the id range)."""
-    rng = np.random.default_rng(seed)
-    t = system.type
-    lip = rng.choice(np.flatnonzero(t == 0), 1200, replace=False)
-    spec = rng.choice(np.flatnonzero(t == 1), 300, replace=False)
-    junc = np.flatnonzero(t == 2)[::40]
-    idx = np.unique(np.concatenate([lip, spec, junc, [0, system.N - 1]]))
-    return idx.astype(np.int64)
-
-
 def _state(ctx, system):
     x, n, v, w = (to_np(a) for a in ctx.get_state())
     return dataclasses.replace(system, x=x, n=n, v=v, w=w)
 
 
-def test_rbc4m_pairs_and_sampled_forces_mixed(R, mp, cell):
-    mp = dataclasses.replace(mp, skin=SKIN)
+def test_rbc4m_pairs_mixed(R, mp, cell):
+    mp = dataclasses.replace(mp, skin=SKIN, inner_skin=INNER)
     c = R.Context(mp, R.RBC_MIXED)
     c.set_system(cell)
     c.step(40, DT)
     st = c.stats()
-    assert st["steps"] == 40 and st["rebuilds"] >= 2, st
+    assert st["steps"] == 40 and st["prunes"] >= 2, st
     s = _state(c, cell)
     p = O.params_for(cell, mp)
     got = c.get_pairs()
     ref = O.pairs(p, s.x, s.type, "grid")
     assert got.shape == ref.shape, (got.shape, ref.shape)
     assert np.array_equal(got, ref)
-    del got, ref
-    F, T = (to_np(a) for a in c.forces())
     c.close()
-    idx = _sample(cell)
-    F0, T0 = O.forces_subset(p, s, idx)
-    eF = rel_err(F[idx], F0)
-    eT = rel_err(T[idx], T0)
-    print(f"rbc4m mixed, {idx.size} sampled particles: e_F {eF:.3e}  e_tau {eT:.3e}")
-    assert eF < MIXED_TOL and eT < MIXED_TOL, (eF, eT)
-    assert np.all(T[idx][s.type[idx] != 0] == 0.0)
 
 
-def test_rbc4m_sampled_forces_fp64(R, mp, cell):
-    mp = dataclasses.replace(mp, skin=SKIN)
+def test_rbc4m_full_frames_mixed(R, mp, cell):
+    """Every particle's force and torque against the oracle at frames 0, 100 and 200
+    of a mixed-precision run (one cell update and several list builds and prunes in
+    between)."""
+    mp = dataclasses.replace(mp, skin=SKIN, inner_skin=INNER)
+    c = R.Context(mp, R.RBC_MIXED)
+    c.set_system(cell)
+    p = O.params_for(cell, mp)
+    lip = cell.type == 0
+    rep = []
+    for frame in range(3):
+        if frame:
+            c.step(100, DT)
+        s = _state(c, cell)
+        F, T = (to_np(a) for a in c.forces())
+        F0, T0, U0, _ = O.forces(p, s)
+        eF, qF = check_forces(F, F0, MIXED_TOL, PP_MIXED_TOL, f"rbc4m mixed frame {100 * frame} F")
+        eT, qT = check_forces(T[lip], T0[lip], MIXED_TOL, PP_MIXED_TOL, f"rbc4m mixed frame {100 * frame} tau")
+        assert np.all(T[~lip] == 0.0)
+        rep.append({"step": 100 * frame, "e_F": eF, "pp_F": qF, "e_tau": eT, "pp_tau": qT})
+    st = c.stats()
+    c.close()
+    assert st["steps"] == 200 and st["cell_updates"] >= 2, st
+    out = os.environ.get("RBC_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "rbc4m_full_frames_mixed.json"), "w") as fh:
+            json.dump({"frames": rep, "stats": st}, fh, indent=1)
+
+
+def test_rbc4m_full_frame_fp64(R, mp, cell):
+    mp = dataclasses.replace(mp, skin=SKIN, inner_skin=INNER)
     c = R.Context(mp, R.RBC_FP64)
     c.set_system(cell)
     c.step(12, DT)
@@ -95,15 +105,10 @@ def test_rbc4m_sampled_forces_fp64(R, mp, cell):
     F, T = (to_np(a) for a in c.forces())
     c.close()
     p = O.params_for(cell, mp)
-    idx = _sample(cell, seed=8)
-    F0, T0 = O.forces_subset(p, s, idx)
-    eF = rel_err(F[idx], F0)
-    eT = rel_err(T[idx], T0)
-    print(f"rbc4m fp64, {idx.size} sampled particles: e_F {eF:.3e}  e_tau {eT:.3e}")
-    assert eF < FP64_TOL and eT < FP64_TOL, (eF, eT)
-    # per particle too, against the sample's RMS force
-    scale = np.sqrt(np.mean(np.sum(F0 ** 2, axis=1)))
-    assert np.abs(F[idx] - F0).max() < 1e-9 * scale
+    F0, T0, _, _ = O.forces(p, s)
+    lip = cell.type == 0
+    check_forces(F, F0, FP64_TOL, PP_FP64_TOL, "rbc4m fp64 F")
+    check_forces(T[lip], T0[lip], FP64_TOL, PP_FP64_TOL, "rbc4m fp64 tau")
 
 
 def test_rbc500k_long_run_mixed(R, mp):
@@ -122,16 +127,19 @@ def test_rbc500k_long_run_mixed(R, mp):
         F, T = (to_np(a) for a in c.forces())
         F0, T0, U0, _ = O.forces(p, s)
         frames.append({"step": f * every, "E": float(e[3]), "U": float(e[0]), "U_oracle": float(U0),
-                       "e_F": rel_err(F, F0), "e_tau": rel_err(T[lip], T0[lip])})
+                       "e_F": rel_err(F, F0), "e_tau": rel_err(T[lip], T0[lip]),
+                       "pp_F": pp_err(F, F0), "pp_tau": pp_err(T[lip], T0[lip])})
     st = c.stats()
     c.close()
     E = np.array([fr["E"] for fr in frames])
     drift = (E[-1] - E[0]) / s0.N / (steps / 1e4)
     worst = max(max(fr["e_F"], fr["e_tau"]) for fr in frames)
+    worst_pp = max(max(fr["pp_F"], fr["pp_tau"]) for fr in frames)
     report = {"workload": "rbc500k", "particles": s0.N, "steps": steps, "dt": DT,
               "energy_drift_per_particle_per_1e4_steps": drift,
               "max_abs_energy_change_per_particle": float(np.abs(E - E[0]).max() / s0.N),
-              "worst_force_error": worst, "cell_updates": st["cell_updates"],
+              "worst_force_error": worst, "worst_per_particle_error": worst_pp,
+              "cell_updates": st["cell_updates"],
               "list_rebuilds": st["rebuilds"], "frames": frames}
     print(json.dumps({k: v for k, v in report.items() if k != "frames"}))
     out = os.environ.get("RBC_REPORT_DIR")
@@ -140,6 +148,7 @@ def test_rbc500k_long_run_mixed(R, mp):
         with open(os.path.join(out, "long_run_rbc500k.json"), "w") as fh:
             json.dump(report, fh, indent=1)
     assert worst < MIXED_TOL, worst
+    assert worst_pp < PP_MIXED_TOL, worst_pp
     for fr in frames:
         assert fr["U"] == pytest.approx(fr["U_oracle"], rel=MIXED_TOL)
     # NVE: energy per particle stays within a small fraction of kT = 0.22 over 2e4 steps

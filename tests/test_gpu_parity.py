@@ -6,12 +6,14 @@ arithmetic) within 1e-5 relative RMS.  Sizes: the 2,704-particle flat patch
 and the 124,952-particle vesicle, which span many 64-particle chunks and end
 on a ragged chunk.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1701_02059_amd import inputs as I
-from tests.gpu_common import rel_err, to_np
+from tests.gpu_common import PP_FP64_TOL, PP_MIXED_TOL, check_forces, rel_err, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -65,8 +67,8 @@ def test_forces_fp64(R, mp, name, patch, ves):
     c = _ctx(R, mp, s, R.RBC_FP64)
     F, T, E = c.forces(energy=True)
     F, T, E = to_np(F), to_np(T), to_np(E)
-    assert rel_err(F, F0) < FP64_TOL
-    assert rel_err(T, T0) < FP64_TOL
+    check_forces(F, F0, FP64_TOL, PP_FP64_TOL, f"{name} fp64 F")
+    check_forces(T, T0, FP64_TOL, PP_FP64_TOL, f"{name} fp64 tau")
     assert E[0] == pytest.approx(U0, rel=FP64_TOL)
     assert E[1] == pytest.approx(W0, rel=FP64_TOL)
     c.close()
@@ -80,8 +82,8 @@ def test_forces_mixed(R, mp, name, patch, ves):
     c = _ctx(R, mp, s, R.RBC_MIXED)
     F, T, E = c.forces(energy=True)
     F, T, E = to_np(F), to_np(T), to_np(E)
-    eF, eT = rel_err(F, F0), rel_err(T, T0)
-    assert eF < MIXED_TOL and eT < MIXED_TOL, (eF, eT)
+    check_forces(F, F0, MIXED_TOL, PP_MIXED_TOL, f"{name} mixed F")
+    check_forces(T, T0, MIXED_TOL, PP_MIXED_TOL, f"{name} mixed tau")
     assert E[0] == pytest.approx(U0, rel=MIXED_TOL)
     c.close()
 
@@ -243,6 +245,30 @@ def test_ensemble_alone_equals_mix(R, mp):
         assert np.array_equal(a, b)
     for a, b in zip(alone[2], got2):
         assert np.array_equal(a, b)
+
+
+def test_ensemble_slots_match_the_oracle(R, mp):
+    """The batched path against the oracle directly: three systems of different kinds
+    and sizes stepped together in one FP64 ensemble; each slot's trajectory and energy
+    record equal the oracle's velocity-Verlet run of that system alone."""
+    systems = [I.build_request({"kind": "patch", "nL": 2500, "seed": 21}),
+               I.build_request({"kind": "vesicle", "nL": 3000, "seed": 22}),
+               I.config("patch")]
+    e = R.Ensemble(mp, R.RBC_FP64, max_slots=4)
+    slots = [e.admit(s) for s in systems]
+    e.step(25, 0.01)
+    for s, slot in zip(systems, slots):
+        p = O.params_for(s, mp)
+        x0, v0, n0, w0, en = O.vv_run(p, s, 0.01, 25)
+        x, n, v, w = (to_np(t) for t in e.get_state(slot))
+        assert np.abs(x - x0).max() < 1e-9
+        assert np.abs(v - v0).max() < 1e-8
+        assert np.abs(n - n0).max() < 1e-9
+        rec = e.energy(slot)
+        F0, T0, U0, W0 = O.forces(p, dataclasses.replace(s, x=x0, n=n0, v=v0, w=w0))
+        assert rec[0] == pytest.approx(U0, rel=1e-9)
+        assert rec[3] == pytest.approx(en[-1, 2], rel=1e-9)
+    e.close()
 
 
 def test_ensemble_graph_replay_matches_eager(R, mp):
@@ -483,18 +509,23 @@ def _dense_cloud(n_side=14, spacing=1.36, seed=11):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_dense_3d_cloud_unstaged_blocks(R, mp, prec):
-    """All three stage layouts at once: blocks whose partners fit the 800 LDS entries,
-    blocks with 801-1024 partners (the entries past 800 read from global memory) and
-    blocks past 1024 (global slots in 32-bit lists)."""
+    """All three stage layouts of the step kernel at once: blocks whose pruned partners
+    fit its LDS stage (640 entries in mixed mode, 800 in FP64), blocks with more (the
+    entries past the LDS part read from global memory) and blocks whose full lists
+    outgrew a stage (global slots in 32-bit lists)."""
     s = _dense_cloud()
     p = O.params_for(s, mp)
     F0, T0, U0, W0 = O.forces(p, s)
-    c = _ctx(R, mp, s, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
-    sc = c.debug_array(9).view(np.int32)
-    assert (sc < 0).any() and ((sc > 800) & (sc <= 1024)).any() and ((sc >= 0) & (sc <= 800)).any(), sc
+    # FP64 holds 800 entries in LDS: unpruned lists (inner skin = skin) overflow it
+    m = dataclasses.replace(mp, inner_skin=mp.skin) if prec == "fp64" else mp
+    c = _ctx(R, m, s, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
+    sc = c.debug_array(12).view(np.int32)          # pruned stage count per block (-1: none)
+    lds = 800 if prec == "fp64" else 640
+    assert (sc < 0).any() and (sc > lds).any() and ((sc >= 0) & (sc <= lds)).any(), sc
     F, T = (to_np(t) for t in c.forces())
     tol = FP64_TOL if prec == "fp64" else MIXED_TOL
-    assert rel_err(F, F0) < tol and rel_err(T, T0) < tol
+    check_forces(F, F0, tol, PP_FP64_TOL if tol == FP64_TOL else PP_MIXED_TOL, "F")
+    check_forces(T, T0, tol, PP_FP64_TOL if tol == FP64_TOL else PP_MIXED_TOL, "tau")
     assert np.array_equal(c.get_pairs(), O.pairs(p, s.x, s.type))
     c.close()
 
@@ -510,6 +541,7 @@ def test_forces_nondefault_constants(R, prec, ves):
     c = _ctx(R, mp2, sub, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
     F, T, E = (to_np(t) for t in c.forces(energy=True))
     tol = FP64_TOL if prec == "fp64" else MIXED_TOL
-    assert rel_err(F, F0) < tol and rel_err(T, T0) < tol
+    check_forces(F, F0, tol, PP_FP64_TOL if tol == FP64_TOL else PP_MIXED_TOL, "F")
+    check_forces(T, T0, tol, PP_FP64_TOL if tol == FP64_TOL else PP_MIXED_TOL, "tau")
     assert E[0] == pytest.approx(U0, rel=tol)
     c.close()

@@ -1,7 +1,7 @@
 """Oracle pins for the volume constraint and the Langevin thermostat.
 
 The paper applies a harmonic volume constraint in its whole-cell fluctuation run
-(Results section) without giving its form, and names no thermostat; the forms
+(Validation and Benchmark section) without giving its form, and names no thermostat; the forms
 here are readings.  What pins them besides themselves: the generator's
 published known-answer vectors, closed-form and quadrature volumes, finite
 differences of the volume energy, conservation laws, and equipartition.

@@ -158,10 +158,113 @@ def test_two_phase_admission_batches_arrivals():
     assert all(r.admitted is not None for r in st.results)
 
 
-def test_two_phase_failed_build_raises():
+def test_two_phase_failed_build_is_recorded_and_the_rest_complete():
     reqs = [{"id": i, "arrival": 0.0, "steps": 10} for i in range(3)]
     systems = {i: FakeSys(1000 + i) for i in range(3)}
     clk = Clock()
     ex = TwoPhaseExec(clk, 4, 10 ** 12, refuse={1001})
+    st = serving.serve(reqs, systems, ex, chunk=10, clock=clk, sleep=clk.sleep, keep_state={0, 2})
+    by = {r.req_id: r for r in st.results}
+    assert by[1].error == "cell build failed" and by[1].state is None
+    assert by[0].error is None and by[0].state == 10
+    assert by[2].error is None and by[2].state == 10
+    assert st.summary()["failed"] == 1
+    assert ex.used == 0 and all(s is None for s in ex.slots)
+
+
+class FreezingExec(MockExec):
+    """Freezes the slot of the system of size `bad` at its first step call, the way the
+    HIP ensemble freezes a slot whose lists overflow: the call raises, the other slots
+    have advanced, and failed() lists the frozen slot until it is retired."""
+
+    def __init__(self, clock, slots, budget, bad):
+        super().__init__(clock, slots, budget)
+        self.bad = bad
+        self.frozen = {}
+
+    def step(self, n, dt):
+        tot = sum(s.N for s in self.slots if s is not None)
+        self.clock.t += n * (2e-5 + tot * 1e-9)
+        for k, s in enumerate(self.slots):
+            if s is None or k in self.frozen:
+                continue
+            if s.N == self.bad:
+                self.frozen[k] = 5
+            else:
+                self.steps[k] += n
+        if self.frozen:
+            raise RuntimeError("capacity exceeded (slot frozen)")
+
+    def failed(self):
+        return dict(self.frozen)
+
+    def retire(self, k):
+        self.frozen.pop(k, None)
+        super().retire(k)
+
+
+def test_a_slot_failing_during_a_step_is_retired_and_the_rest_complete():
+    reqs = [{"id": i, "arrival": 0.001 * i, "steps": 40} for i in range(6)]
+    systems = {i: FakeSys(3000 + i) for i in range(6)}
+    clk = Clock()
+    ex = FreezingExec(clk, 4, 10 ** 12, bad=3002)
+    st = serving.serve(reqs, systems, ex, chunk=10, clock=clk, sleep=clk.sleep, keep_state=set(range(6)))
+    by = {r.req_id: r for r in st.results}
+    assert len(by) == 6
+    assert by[2].error is not None and "failed during a step" in by[2].error
+    assert all(by[i].error is None and by[i].state == 40 for i in (0, 1, 3, 4, 5))
+    assert ex.used == 0 and all(s is None for s in ex.slots)
+
+
+def test_a_step_error_without_a_frozen_slot_still_raises():
+    class Broken(MockExec):
+        def step(self, n, dt):
+            raise RuntimeError("device lost")
+
+        def failed(self):
+            return {}
+
+    reqs = [{"id": 0, "arrival": 0.0, "steps": 10}]
+    clk = Clock()
     with pytest.raises(RuntimeError):
-        serving.serve(reqs, systems, ex, chunk=10, clock=clk, sleep=clk.sleep)
+        serving.serve(reqs, {0: FakeSys(1000)}, Broken(clk, 2, 10 ** 12), clock=clk, sleep=clk.sleep)
+
+
+def test_requests_without_steps_are_refused():
+    reqs = [{"id": 0, "arrival": 0.0, "steps": 0}, {"id": 1, "arrival": 0.0, "steps": -3},
+            {"id": 2, "arrival": 0.0, "steps": 5}]
+    systems = {i: FakeSys(1000) for i in range(3)}
+    clk = Clock()
+    ex = MockExec(clk, 4, 10 ** 12)
+    st = serving.serve(reqs, systems, ex, chunk=10, clock=clk, sleep=clk.sleep, keep_state={2})
+    by = {r.req_id: r for r in st.results}
+    assert by[0].error and by[1].error and by[2].error is None and by[2].state == 5
+    assert [ev[0] for ev in ex.log] == ["admit", "retire"]          # only the valid request was admitted
+
+
+class TimedExec(MockExec):
+    """Reports per-step times like the HIP ensemble's step_times: step q of a call
+    takes q + 1 ms, and every call after the first follows a 10 ms gap."""
+
+    def __init__(self, clock, slots, budget):
+        super().__init__(clock, slots, budget)
+        self.last = (np.zeros(0), -1.0)
+        self.ncalls = 0
+
+    def step(self, n, dt):
+        super().step(n, dt)
+        self.last = (np.arange(1, n + 1, dtype=np.float64), 10.0 if self.ncalls else -1.0)
+        self.ncalls += 1
+
+    def step_times(self, enable=True):
+        return self.last
+
+
+def test_step_latency_comes_from_per_step_times_and_carries_gaps():
+    reqs = [{"id": 0, "arrival": 0.0, "steps": 6}]
+    clk = Clock()
+    ex = TimedExec(clk, 2, 10 ** 12)
+    st = serving.serve(reqs, {0: FakeSys(1000)}, ex, chunk=3, clock=clk, sleep=clk.sleep)
+    # two calls of 3 steps: 1, 2, 3 ms, then 1 + 10 (the gap), 2, 3 ms
+    assert np.allclose(np.sort(st.step_latency * 1e3), np.sort([1, 2, 3, 11, 2, 3]))
+    assert st.call_latency.size == 6
