@@ -26,6 +26,10 @@ using namespace rbc;
 namespace {
 
 constexpr int RING = 8;
+// Systems this large decide list rebuilds and prunes from the statistics of the drift to
+// the current positions (exact); the margin covers the FP32 reference positions.
+constexpr int64_t EXACT_MIN_N = 1 << 20;
+constexpr double EXACT_MARGIN = 2e-4;
 
 struct HostSys {
     bool live = false;
@@ -48,6 +52,7 @@ struct HostSys {
     int64_t prunes = 0;              // prunes of the lists outside a build
     bool have_stats = false, rebuilt_last = false, refreshed_last = false;
     double disp2 = 0.0, v2 = 0.0, disp2p = 0.0;
+    double cur_d2 = 0.0, cur_v2 = 0.0, cur_d2p = 0.0;   // the latest drift statistics read
     uint64_t drifts = 0;             // statistics passes since loading (the device's step counter)
     bool pending = false;            // staged: uploaded, cells not built yet
     rbc_status failed = RBC_OK;      // ensemble slot frozen by an error (held until retired)
@@ -670,6 +675,25 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         }
         hipEventRecord(h->ev_call0, h->st);
     }
+    bool exact_any = false;
+    for (const auto &hs : h->sys)
+        if (runs(hs) && hs.n >= EXACT_MIN_N) exact_any = true;
+    // the statistics of the latest drift of every running system, from the pinned ring
+    auto read_stats = [&]() {
+        for (int s = 0; s < h->nsys; ++s) {
+            HostSys &hs = h->sys[s];
+            if (!runs(hs)) continue;
+            hs.cur_d2 = hs.cur_v2 = hs.cur_d2p = 0.0;
+            if (hs.n == 0) continue;
+            const volatile StepStat &e = h->h_stat[(size_t)s * STAT_RING + hs.drifts % STAT_RING];
+            if (e.tag != hs.drifts + 1 && out == RBC_OK)
+                out = fail(h, RBC_ERR_HIP, "drift statistics out of sequence (slot " + std::to_string(s) + ")");
+            hs.cur_d2 = e.d2;
+            hs.cur_v2 = e.v2;
+            hs.cur_d2p = e.d2p;
+            hs.drifts++;
+        }
+    };
     launch_kick_drift(h->L, dt);
     h->vol_fresh = true;              // every drift also writes the volume's lipid sums
     for (int64_t st = 0; st < nsteps; ++st) {
@@ -679,10 +703,20 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         // the statistics of the drift to this step's positions are published when
         // this event completes
         hipEventRecord(h->step_ev[slot], h->st);
-        // decide, from the previous step's statistics, which systems update their cells
-        // (every K steps), which rebuild their lists (the skin is running out) and which
-        // prune them (the pruned lists' buffer is running out; a prune needs the full
-        // lists to still hold every pair within the pruned radius)
+        // Systems of at least EXACT_MIN_N particles decide from the statistics of the drift
+        // to this step's positions: the host waits for them (the GPU idles for the host's
+        // reaction time, small beside such a system's step).  Smaller systems decide from
+        // the previous step's statistics plus a bound on one more drift, while this step's
+        // force runs.  A system's rule depends on its own size only, so its trajectory does
+        // not depend on its batch.
+        if (exact_any) {
+            hipEventSynchronize(h->step_ev[slot]);
+            read_stats();
+        }
+        // decide which systems update their cells (every K steps), which rebuild their
+        // lists (the skin is running out) and which prune them (the pruned lists' buffer
+        // is running out; a prune needs the full lists to still hold every pair within
+        // the pruned radius)
         std::vector<int> which, full, lists, pruned;
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
@@ -693,19 +727,28 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
                 which.push_back(s);
                 continue;
             }
-            if (hs.have_stats) {
+            bool prune = false, rebuild = false;
+            if (hs.n >= EXACT_MIN_N) {
+                // exact displacements at this step's positions (FP32 references: margin)
+                if (std::sqrt(hs.cur_d2p) > din - EXACT_MARGIN) {
+                    prune = true;
+                    rebuild = std::sqrt(hs.cur_d2) > skin - din - EXACT_MARGIN;
+                }
+            } else if (hs.have_stats) {
                 const double step_max = 2.0 * dt * std::sqrt(hs.v2);
                 const double pred_p = (hs.refreshed_last ? 0.0 : std::sqrt(hs.disp2p)) + step_max;
                 if (pred_p > 0.9 * din) {
+                    prune = true;
                     const double pred_b = (hs.rebuilt_last ? 0.0 : std::sqrt(hs.disp2)) + step_max;
-                    if (pred_b > 0.9 * (skin - din)) {
-                        hs.early++;
-                        lists.push_back(s);
-                        which.push_back(s);
-                    } else {
-                        pruned.push_back(s);
-                    }
+                    rebuild = pred_b > 0.9 * (skin - din);
                 }
+            }
+            if (rebuild) {
+                hs.early++;
+                lists.push_back(s);
+                which.push_back(s);
+            } else if (prune) {
+                pruned.push_back(s);
             }
         }
         run_update(h, full, 0);
@@ -719,23 +762,18 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         }
         if (!last) swap_drift_buffers(h);
         if (timed) hipEventRecord(h->ev_step[st], h->st);
-        // while the force runs, read this step's drift statistics
-        hipEventSynchronize(h->step_ev[slot]);
+        // while the force runs, read this step's drift statistics (already read above when
+        // some system decides from them)
+        if (!exact_any) {
+            hipEventSynchronize(h->step_ev[slot]);
+            read_stats();
+        }
         for (int s = 0; s < h->nsys; ++s) {
             HostSys &hs = h->sys[s];
             if (!runs(hs)) continue;
             const bool rebuilt = std::find(which.begin(), which.end(), s) != which.end();
             const bool was_pruned = std::find(pruned.begin(), pruned.end(), s) != pruned.end();
-            double d2 = 0.0, v2 = 0.0, d2p = 0.0;
-            if (hs.n > 0) {
-                const volatile StepStat &e = h->h_stat[(size_t)s * STAT_RING + hs.drifts % STAT_RING];
-                if (e.tag != hs.drifts + 1 && out == RBC_OK)
-                    out = fail(h, RBC_ERR_HIP, "drift statistics out of sequence (slot " + std::to_string(s) + ")");
-                d2 = e.d2;
-                v2 = e.v2;
-                d2p = e.d2p;
-                hs.drifts++;
-            }
+            const double d2 = hs.cur_d2, v2 = hs.cur_v2, d2p = hs.cur_d2p;
             // the force of this step walked the pruned lists: they had to hold every pair in
             // range, and a prune at this step needed the full lists to hold its radius
             if (!rebuilt && !was_pruned && d2p > din * din)
