@@ -1236,47 +1236,60 @@ __device__ __forceinline__ int union_cell(const int *ofs, int nsc, int u) {
     return lo;
 }
 
+// Smallest and largest coordinates of each wavefront's particles (FP32 offsets;
+// lanes without a particle pass +inf and -inf), in s_b[6 w .. 6 w + 5].
+__device__ __forceinline__ void chunk_box(const float lo_in[3], const float hi_in[3], float *s_b) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float mn[3] = {lo_in[0], lo_in[1], lo_in[2]}, mx[3] = {hi_in[0], hi_in[1], hi_in[2]};
+    for (int off = 32; off > 0; off >>= 1)
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], off));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off));
+        }
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+            s_b[w * 6 + a] = mn[a];
+            s_b[w * 6 + 3 + a] = mx[a];
+        }
+}
+
 // One block per 256 consecutive cell-sorted particles (four 64-particle chunks).
-// Candidates: the cell-pair entries of the block's (consecutive) cells, sorted
-// and deduplicated in LDS; their particles form the block's candidate union.
-// Pass 1: each lane collects every partner within the list radius (rc + 2 skin of
-// the pair's types) by scanning the particles of every cell paired with its cell;
-// column `lane` of the chunk's ELL block holds them.  When the union fits in LDS
-// its positions are staged there as FP32 offsets from the block's first particle
-// (with slot and type packed in w) and the test runs in FP32 against the list
-// radius widened by 1e-3 sigma, which bounds the offsets' rounding (offsets are
-// limited to 4096 sigma), so the list stays a superset of the FP64 one; the force
-// kernel applies the exact FP64 test to every entry.  Otherwise the test runs on
-// FP64 positions from global memory.
-// Pass 2: partners are marked in a bitmap over the union, a prefix popcount
-// numbers them, the block's stage list receives their slots and the 16-bit lists
-// hold stage indices (0xffff pads).  Blocks whose partners do not fit the stage
-// keep 32-bit lists of global slots (stage count -1).
+// Candidates: the cell-pair entries of the block's (consecutive) cells, sorted and
+// deduplicated in LDS; their particles, in cell order, form the block's candidate
+// union.  The union's particles within the largest list radius of the bounding box of
+// the block's own particles form the block's stage (a superset of its partners), held
+// in LDS as FP32 offsets from the block's first particle with slot and type packed in
+// w, cell by cell.  Each lane then collects every partner within the list radius (rc +
+// 2 skin of the pair's types) by scanning the staged particles of the cells paired
+// with its own cell, after culling each cell by its bounding sphere.  The test runs in
+// FP32 against the list radius widened by 1e-3 sigma, which bounds the offsets'
+// rounding (offsets are limited to 4096 sigma), so the list is a superset of the FP64
+// one; the step kernel decides every pair exactly.  The 16-bit lists hold stage
+// indices (0xffff pads), in candidate order.  Blocks whose stage does not fit keep
+// 32-bit lists of global slots (stage count -1), built on FP64 positions.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_nlist(const SysDev *Sd, Maps L_maps, DevParams P) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
     __shared__ int s_cand[CANDMAX];
     __shared__ int s_ofs[CANDMAX + 1];
+    __shared__ int s_kofs[CANDMAX + 1];
     __shared__ int s_qpos[CANDMAX];
-    __shared__ unsigned s_bits[SSMAX / 32];
-    __shared__ int s_wpre[SSMAX / 32 + 1];
     __shared__ F4 s_u[USTAGE];
     __shared__ F4 s_cb[CULLMAX];
+    __shared__ float s_b[24];
     __shared__ int s_w[16];
-    __shared__ int s_flag, s_rows, s_big;
+    __shared__ int s_rows, s_big;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int chunk = lb * (BLOCK / WAVE) + wv;
     const bool chunk_ok = chunk < S.nchunk;
     const int i = lb * BLOCK + tid;
     const bool valid = i < S.n;
     if (S.sc->err & ERR_CNBR) {          // no valid cell pairs: publish empty lists (block-uniform)
-        if (lane == 0 && chunk_ok) S.nlk[chunk] = 0;
-        if (tid == 0) { S.scount[lb] = 0; S.blkrows[lb] = 0; }
+        if (lane == 0 && chunk_ok) { S.nlk[chunk] = 0; S.ilk[chunk] = 0; }
+        if (tid == 0) { S.scount[lb] = 0; S.iscount[lb] = 0; S.blkrows[lb] = 0; }
         return;
     }
-    if (tid == 0) { s_flag = 0; s_rows = 0; s_big = 0; }
-    for (int w = tid; w < SSMAX / 32; w += BLOCK) s_bits[w] = 0u;
-    __syncthreads();
+    if (tid == 0) { s_rows = 0; s_big = 0; }
     // ---- candidate cells, their particle offsets, and the union position of every cell-pair entry
     const int first = lb * BLOCK;
     const int last = min(S.n - 1, first + BLOCK - 1);
@@ -1322,14 +1335,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
         if (tid == 0) s_ofs[nsc] = ss;
         __syncthreads();
     }
-    // ---- stage the union as FP32 offsets when it fits, with the candidate cells'
+    // ---- the stage: the union's particles near the block, as FP32 offsets, cell by
+    // cell (s_kofs: each candidate cell's first stage entry), with the candidate cells'
     // centroids and radii (widened by 2e-3 sigma for the offsets' rounding)
-    bool staged = have_union && ss <= USTAGE;
     const bool cull = nsc <= CULLMAX;
     const D4 ref = ldg(S.pos + first);
-    const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
-    if (staged) {
-        float big = 0.0f;
+    const D4 pi = valid ? S.pos[i] : ref;
+    float oi[3] = {(float)minimg1(pi.x - ref.x, S.per[0], S.box[0]), (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]),
+                   (float)minimg1(pi.z - ref.z, S.per[2], S.box[2])};
+    if (!valid) oi[0] = oi[1] = oi[2] = 0.0f;
+    int kept = 0;
+    // offsets beyond LIST_EXTENT (or not finite) leave the block without a stage
+    auto far = [](const float o[3]) {
+        return !(fabsf(o[0]) <= LIST_EXTENT && fabsf(o[1]) <= LIST_EXTENT && fabsf(o[2]) <= LIST_EXTENT);
+    };
+    if (have_union) {
         if (cull)
             for (int q = tid; q < nsc; q += BLOCK) {
                 const D4 c = ldg(S.seed + s_cand[q]);
@@ -1337,40 +1357,95 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                 const float oy = (float)minimg1(c.y - ref.y, S.per[1], S.box[1]);
                 const float oz = (float)minimg1(c.z - ref.z, S.per[2], S.box[2]);
                 s_cb[q] = F4{ox, oy, oz, (float)c.w + 2e-3f};
-                big = fmaxf(big, fmaxf(fabsf(ox), fmaxf(fabsf(oy), fabsf(oz))));
+                const float o[3] = {ox, oy, oz};
+                if (far(o)) s_big = 1;
             }
-        for (int u = tid; u < ss; u += BLOCK) {
-            const int c = union_cell(s_ofs, nsc + 1, u);
-            const int slot = ldg(S.cstart + s_cand[c]) + (u - s_ofs[c]);
-            const D4 pj = ldg(S.pos + slot);
-            const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
-            const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
-            const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
-            s_u[u] = F4{ox, oy, oz, __int_as_float((slot << 2) | ((int)pj.w & 3))};
-            big = fmaxf(big, fmaxf(fabsf(ox), fmaxf(fabsf(oy), fabsf(oz))));
+        // the boxes of the block's four chunks, widened by the largest list radius (plus
+        // 1e-3 for the rounding of the distance to them): a particle farther from every
+        // box has no partner in the block.  A periodic axis measures the distance to a
+        // box's centre by the minimum image, and keeps every particle where the widened
+        // box spans a quarter of the period or more.  A chunk without particles has no box.
+        {
+            const float lo_in[3] = {valid ? oi[0] : INFINITY, valid ? oi[1] : INFINITY, valid ? oi[2] : INFINITY};
+            const float hi_in[3] = {valid ? oi[0] : -INFINITY, valid ? oi[1] : -INFINITY, valid ? oi[2] : -INFINITY};
+            chunk_box(lo_in, hi_in, s_b);
         }
-        if (!(big <= LIST_EXTENT)) s_big = 1;       // also catches non-finite offsets
         __syncthreads();
-        staged = s_big == 0;
+        const float rb = fmaxf(P.rlmaxf[0], fmaxf(P.rlmaxf[1], P.rlmaxf[2])) + 1e-3f;
+        constexpr int NB = BLOCK / WAVE;
+        float bc[NB][3], bw[NB][3], L[3], iL[3];
+        for (int a = 0; a < 3; ++a) {
+            L[a] = S.per[a] ? (float)S.box[a] : 0.0f;
+            iL[a] = S.per[a] ? 1.0f / L[a] : 0.0f;
+        }
+        for (int w = 0; w < NB; ++w) {
+            const bool empty = !(s_b[w * 6] <= s_b[w * 6 + 3]);
+            for (int a = 0; a < 3; ++a) {
+                const float lo = s_b[w * 6 + a], hi = s_b[w * 6 + 3 + a];
+                bc[w][a] = empty ? 0.0f : 0.5f * (lo + hi);
+                bw[w][a] = empty ? -INFINITY : 0.5f * (hi - lo) + 1e-3f;   // half width; rounding of bc covered
+                if (!empty && S.per[a] && !(4.0f * (bw[w][a] + rb) < L[a])) bw[w][a] = INFINITY;
+            }
+        }
+        for (int u0 = 0; u0 < ss; u0 += BLOCK) {
+            const int u = u0 + tid;
+            bool keep = false;
+            F4 rec = F4{0.0f, 0.0f, 0.0f, 0.0f};
+            int c = -1;
+            if (u < ss) {
+                c = union_cell(s_ofs, nsc + 1, u);
+                const int slot = ldg(S.cstart + s_cand[c]) + (u - s_ofs[c]);
+                const D4 pj = ldg(S.pos + slot);
+                const float o[3] = {(float)minimg1(pj.x - ref.x, S.per[0], S.box[0]),
+                                    (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]),
+                                    (float)minimg1(pj.z - ref.z, S.per[2], S.box[2])};
+                if (far(o)) s_big = 1;
+                float e2min = INFINITY;
+                for (int w = 0; w < NB; ++w) {
+                    float e2 = 0.0f;
+                    for (int a = 0; a < 3; ++a) {
+                        float d = o[a] - bc[w][a];
+                        if (S.per[a]) d -= L[a] * rintf(d * iL[a]);
+                        const float e = bw[w][a] == INFINITY ? 0.0f : fmaxf(fabsf(d) - bw[w][a], 0.0f);
+                        e2 += e * e;
+                    }
+                    e2min = fminf(e2min, e2);
+                }
+                keep = e2min <= rb * rb;
+                rec = F4{o[0], o[1], o[2], __int_as_float((slot << 2) | ((int)pj.w & 3))};
+            }
+            int tot;
+            const int k = kept + block_excl_scan(keep ? 1 : 0, s_w, tot);
+            if (keep && k < USTAGE) s_u[k] = rec;
+            // each cell's first stage entry (cells without particles share the next one's)
+            if (u < ss && u == s_ofs[c])
+                for (int c2 = c; c2 >= 0 && s_ofs[c2] == u; --c2) s_kofs[c2] = k;
+            kept += tot;
+        }
+        for (int c = tid; c <= nsc; c += BLOCK)
+            if (s_ofs[c] == ss) s_kofs[c] = kept;
+        __syncthreads();
     }
-    // ---- pass 1
-    int cnt = 0;
-    int my_in = 0;                                       // entries in the inner part of the list
+    const bool staged = have_union && kept <= USTAGE && s_big == 0;
+    // ---- the lists, and the pruned lists (partners within rc + 2 inner skin) with the
+    // stage entries they use flagged in s_pflag (the candidate cells are done with)
+    unsigned char *s_pflag = reinterpret_cast<unsigned char *>(s_cand);
+    static_assert(sizeof(s_cand) >= USTAGE, "pruned-stage flags overlay the candidate cells");
+    for (int w = tid; w < USTAGE / 4; w += BLOCK) reinterpret_cast<unsigned *>(s_pflag)[w] = 0u;
+    __syncthreads();
+    int cnt = 0, pc = 0;
     int32_t *col = S.nl + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
     uint16_t *col16 = S.nl16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
+    uint16_t *icol = S.il16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
     if (valid && staged) {
-        // entries are union indices (< USTAGE) in the 16-bit lists until pass 2
-        const D4 pi = S.pos[i];
         const int ti = (int)pi.w;
         const int A = S.owner[i];
-        const float oix = (float)minimg1(pi.x - ref.x, S.per[0], S.box[0]);
-        const float oiy = (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]);
-        const float oiz = (float)minimg1(pi.z - ref.z, S.per[2], S.box[2]);
+        const float oix = oi[0], oiy = oi[1], oiz = oi[2];
         const float rlA = P.rl2f[ti][0], rlB = P.rl2f[ti][1], rlC = P.rl2f[ti][2];
-        const float rf = P.rf2f[ti];
+        const float riA = P.rin2f[ti][0], riB = P.rin2f[ti][1], riC = P.rin2f[ti][2];
         const float rlmax = P.rlmaxf[ti];
-        int nb = 0;                                      // entries beyond rc + skin, kept at the top
-        const int self = s_ofs[lds_lower_bound(s_cand, nsc, A)] + (i - S.cstart[A]);
+        const int selfw = (i << 2) | (ti & 3);            // this particle's own stage record
+        const bool periodic = (S.per[0] | S.per[1] | S.per[2]) != 0;
         const float Lx = S.per[0] ? (float)S.box[0] : 0.0f, Ly = S.per[1] ? (float)S.box[1] : 0.0f,
                     Lz = S.per[2] ? (float)S.box[2] : 0.0f;
         const float iLx = S.per[0] ? 1.0f / Lx : 0.0f, iLy = S.per[1] ? 1.0f / Ly : 0.0f,
@@ -1392,8 +1467,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     const float rr = cb.w + rlmax;
                     if (dx * dx + dy * dy + dz * dz > rr * rr) continue;
                 }
-                const int ue = s_ofs[pos + 1];
-                auto test = [&](const F4 &c, int u) {
+                const int ke = s_kofs[pos + 1];
+                auto test = [&](const F4 &c, int k) {
                     float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
                     if constexpr (PER) {
                         dx -= Lx * rintf(dx * iLx);
@@ -1401,43 +1476,52 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                         dz -= Lz * rintf(dz * iLz);
                     }
                     const float d2 = dx * dx + dy * dy + dz * dz;
-                    const int tj = __float_as_int(c.w) & 3;
-                    const float rl = sel3f(tj, rlA, rlB, rlC);
-                    if (d2 < rl && u != self) {
-                        // partners that can come within rc before the next update first,
-                        // the outer shell after them (the force loop's later rows then
-                        // rarely hold a pair in range)
-                        if (cnt < MAXNB) {
-                            const int row = d2 < rf ? cnt - nb : MAXNB - 1 - nb;
-                            stg(col16 + row * CHUNK, (uint16_t)u);
-                        }
-                        if (!(d2 < rf)) ++nb;
+                    const int w = __float_as_int(c.w);
+                    const float rl = sel3f(w & 3, rlA, rlB, rlC);
+                    if (d2 < rl && w != selfw) {
+                        if (cnt < MAXNB) stg(col16 + cnt * CHUNK, (uint16_t)k);
                         ++cnt;
-                        atomicOr(&s_bits[u >> 5], 1u << (u & 31));     // partner of the block
                     }
                 };
-                int u = s_ofs[pos];
-                for (; u + 1 < ue; u += 2) {                      // two candidates per trip
-                    const F4 c0 = s_u[u], c1 = s_u[u + 1];
-                    test(c0, u);
-                    test(c1, u + 1);
+                int k = s_kofs[pos];
+                for (; k + 1 < ke; k += 2) {                      // two candidates per trip
+                    const F4 a0 = s_u[k], a1 = s_u[k + 1];
+                    test(a0, k);
+                    test(a1, k + 1);
                 }
-                if (u < ue) test(s_u[u], u);
+                if (k < ke) test(s_u[k], k);
+            }
+            // the pruned list: the entries just written (read back by the lane that wrote
+            // them) within the pruned radius
+            const int mine = min(cnt, MAXNB);
+            for (int r0 = 0; r0 < mine; r0 += 8) {
+                int e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e[q] = r0 + q < mine ? (int)ldg(col16 + (r0 + q) * CHUNK) : 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (r0 + q >= mine) break;
+                    const F4 c = s_u[e[q]];
+                    float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
+                    if constexpr (PER) {
+                        dx -= Lx * rintf(dx * iLx);
+                        dy -= Ly * rintf(dy * iLy);
+                        dz -= Lz * rintf(dz * iLz);
+                    }
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 < sel3f(__float_as_int(c.w) & 3, riA, riB, riC)) {
+                        stg(icol + pc * CHUNK, (uint16_t)e[q]);
+                        ++pc;
+                        s_pflag[e[q]] = 1;
+                    }
+                }
             }
         };
         if (periodic) scan_cells(std::true_type{});
         else scan_cells(std::false_type{});
-        // close the gap: the outer entries follow the inner ones
-        const int nin = min(cnt, MAXNB) - min(nb, MAXNB);
-        const int nout = min(cnt, MAXNB) - nin;
-        if (nin + nout < MAXNB)
-            for (int q = 0; q < nout; ++q)
-                stg(col16 + (nin + q) * CHUNK, ldg(col16 + (MAXNB - nout + q) * CHUNK));
-        my_in = nin;
     } else if (valid) {
-        D4 pi = S.pos[i];
-        int ti = (int)pi.w;
-        int A = S.owner[i];
+        const int ti = (int)pi.w;
+        const int A = S.owner[i];
         for (int q = S.cnbr_start[A]; q < S.cnbr_start[A + 1]; ++q) {
             int B = ldg(S.cnbr + q);
             int b = ldg(S.cstart + B), e = b + ldg(S.ccount + B);
@@ -1458,102 +1542,67 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
         if (lane == 0) atomicOr(&S.sc->err, ERR_NLIST);
         rows = MAXNB;
     }
-    const int mycnt = min(cnt, MAXNB);
-    if (!staged) my_in = mycnt;                          // unordered lists: every row is inner
-    const int rows_in = min(wave_max_int(my_in), rows);
-    if (chunk_ok && lane == 0) {
-        S.nlk[chunk] = rows;
-        S.nlin[chunk] = rows_in;
-    }
+    if (chunk_ok && lane == 0) S.nlk[chunk] = rows;
     if (lane == 0) atomicMax(&s_rows, rows);
-    // ---- pass 2: mark partners in the union, number them, write the stage list
-    const int nwords = staged ? (USTAGE / 32) : (SSMAX / 32);
-    bool stage_ok = have_union && (staged || ss <= SSMAX);
-    if (stage_ok && valid && !staged) {            // staged blocks marked their partners in pass 1
-        for (int r = 0; r < mycnt; ++r) {
-            int u;
-            {
-                const int j = ldg(col + r * CHUNK);
-                const int B = S.owner[j];
-                const int pos = lds_lower_bound(s_cand, nsc, B);
-                if (pos >= nsc || s_cand[pos] != B) { s_flag = 1; continue; }
-                u = s_ofs[pos] + (j - S.cstart[B]);
-            }
-            atomicOr(&s_bits[u >> 5], 1u << (u & 31));
-        }
+    // pad every lane to the chunk's row count, and write the stage's slots
+    if (chunk_ok) {
+        const int mycnt = valid ? min(cnt, MAXNB) : 0;
+        if (staged)
+            for (int r = mycnt; r < rows; ++r) stg(col16 + r * CHUNK, (uint16_t)0xffff);
+        else
+            for (int r = mycnt; r < rows; ++r) stg(col + r * CHUNK, (int32_t)-1);
     }
+    if (staged)
+        for (int k = tid; k < kept; k += BLOCK) stg(S.stage + (size_t)lb * SSTRIDE + k, __float_as_int(s_u[k].w) >> 2);
+    // the pruned stage: the flagged stage entries, in stage order; the pruned lists are
+    // rewritten as indices into it (each lane reads back what it wrote) and padded to
+    // the chunk's row count rounded up to even (the step kernel takes rows in pairs).
+    // A block without a stage walks its 32-bit lists unpruned.
+    int irows = wave_max_int(min(pc, MAXNB));
+    if (!staged) irows = rows;
+    if (chunk_ok && lane == 0) S.ilk[chunk] = irows;
     __syncthreads();
-    int nstaged = 0;
-    if (stage_ok) {
-        for (int w = tid; w < nwords; w += BLOCK) s_wpre[w] = __popc(s_bits[w]);
-        __syncthreads();
-        nstaged = block_scan_lds(s_wpre, nwords, s_w);
-        stage_ok = nstaged <= SMAX && s_flag == 0;
-    }
-    if (stage_ok) {
+    unsigned *s_bits = reinterpret_cast<unsigned *>(s_ofs);          // the union offsets are done with
+    int *s_pre = s_ofs + USTAGE / 32;
+    static_assert(sizeof(s_ofs) >= 2 * (USTAGE / 32) * sizeof(int), "pruned-stage words overlay the union offsets");
+    int nkept = -1;
+    if (staged) {
+        const int nwords = (kept + 31) / 32;
         for (int w = tid; w < nwords; w += BLOCK) {
-            unsigned bits = s_bits[w];
-            int r = s_wpre[w];
-            while (bits) {
-                const int b = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                const int u = w * 32 + b;
-                int slot;
-                if (staged) {
-                    slot = __float_as_int(s_u[u].w) >> 2;
-                } else {
-                    const int c = union_cell(s_ofs, nsc + 1, u);
-                    slot = ldg(S.cstart + s_cand[c]) + (u - s_ofs[c]);
-                }
-                stg(S.stage + (size_t)lb * SMAX + r, (int32_t)slot);
-                ++r;
-            }
+            s_bits[w] = pack_flags(s_pflag + 32 * w);
+            s_pre[w] = __popc(s_bits[w]);
         }
-        if (chunk_ok && staged) {
-            // union index -> stage index, eight rows per batch of loads
-            for (int r0 = 0; r0 < rows; r0 += 8) {
-                int u8[8];
+        __syncthreads();
+        nkept = block_scan_lds(s_pre, nwords, s_w);
+        for (int k = tid; k < kept; k += BLOCK) {
+            const int w = k >> 5;
+            const unsigned m = 1u << (k & 31);
+            if (s_bits[w] & m)
+                stg(S.istage + (size_t)lb * SSTRIDE + s_pre[w] + __popc(s_bits[w] & (m - 1u)), __float_as_int(s_u[k].w) >> 2);
+        }
+        const int prows = (irows + 1) & ~1;
+        const int mine = valid ? min(pc, MAXNB) : 0;
+        if (chunk_ok)
+            for (int r0 = 0; r0 < prows; r0 += 8) {
+                int e[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    u8[q] = (valid && r0 + q < mycnt) ? (int)ldg(col16 + (r0 + q) * CHUNK) : -1;
+                for (int q = 0; q < 8; ++q) e[q] = r0 + q < mine ? (int)ldg(icol + (r0 + q) * CHUNK) : -1;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    if (r0 + q >= rows) break;
+                    if (r0 + q >= prows) break;
                     int local = 0xffff;
-                    if (u8[q] >= 0) {
-                        const int w = u8[q] >> 5;
-                        local = s_wpre[w] + __popc(s_bits[w] & ((1u << (u8[q] & 31)) - 1u));
+                    if (e[q] >= 0) {
+                        const int w = e[q] >> 5;
+                        local = s_pre[w] + __popc(s_bits[w] & ((1u << (e[q] & 31)) - 1u));
                     }
-                    stg(col16 + (r0 + q) * CHUNK, (uint16_t)local);
+                    stg(icol + (r0 + q) * CHUNK, (uint16_t)local);
                 }
             }
-        } else if (chunk_ok) {
-            for (int r = 0; r < rows; ++r) {
-                int local = 0xffff;
-                if (valid && r < mycnt) {
-                    int u;
-                    {
-                        const int j = ldg(col + r * CHUNK);
-                        const int B = S.owner[j];
-                        u = s_ofs[lds_lower_bound(s_cand, nsc, B)] + (j - S.cstart[B]);
-                    }
-                    const int w = u >> 5;
-                    local = s_wpre[w] + __popc(s_bits[w] & ((1u << (u & 31)) - 1u));
-                }
-                stg(col16 + r * CHUNK, (uint16_t)local);
-            }
-        }
-    } else if (chunk_ok) {
-        // unstaged block: the 32-bit lists hold global slots, padded with -1
-        for (int r = 0; r < rows; ++r) {
-            int j = -1;
-            if (valid && r < mycnt) j = staged ? (__float_as_int(s_u[ldg(col16 + r * CHUNK)].w) >> 2) : ldg(col + r * CHUNK);
-            stg(col + r * CHUNK, (int32_t)j);
-        }
     }
     __syncthreads();
     if (tid == 0) {
-        S.scount[lb] = stage_ok ? nstaged : -1;
+        S.scount[lb] = staged ? kept : -1;
+        S.iscount[lb] = nkept;
         S.blkrows[lb] = s_rows;
     }
 }
@@ -1565,9 +1614,10 @@ void launch_nlist(const LaunchCtx &L) {
 // ------------------------------------------------------------------ pruned lists
 
 // One block per 256 consecutive cell-sorted particles.  The block's lists hold every
-// partner within rc + 2 skin at the last build; between builds, the partners within
-// rc + 2 inner skin at the current positions are kept in a pruned list, which the
-// force kernel walks instead.  A pair left out was farther apart than rc + 2 inner
+// partner within rc + 2 skin at the last build; the partners within rc + 2 inner skin
+// are kept in a pruned list, which the force kernel walks instead.  The build writes
+// the pruned lists for its own positions; this kernel prunes again between builds, at
+// the current positions.  A pair left out was farther apart than rc + 2 inner
 // skin when the lists were pruned, so it cannot come within rc before some particle
 // has moved more than the inner skin since then; the runtime prunes again before
 // that.  As in the list build, the test runs on FP32 offsets from the block's first
@@ -1604,17 +1654,17 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     if (tid == 0) s_big = 0;
     for (int w = tid; w < SMAX / 4; w += BLOCK) reinterpret_cast<unsigned *>(s_flag)[w] = 0u;
     const D4 ref = ldg(S.pos + (size_t)lb * BLOCK);
-    float big = 0.0f;
+    bool far = false;
     for (int q = tid; q < scnt; q += BLOCK) {
-        const int slot = ldg(S.stage + (size_t)lb * SMAX + q);
+        const int slot = ldg(S.stage + (size_t)lb * SSTRIDE + q);
         const D4 pj = ldg(S.pos + slot);
         const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
         const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
         const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
         s_o[q] = F4{ox, oy, oz, __int_as_float((int)pj.w & 3)};
-        big = fmaxf(big, fmaxf(fabsf(ox), fmaxf(fabsf(oy), fabsf(oz))));
+        far = far || !(fabsf(ox) <= LIST_EXTENT && fabsf(oy) <= LIST_EXTENT && fabsf(oz) <= LIST_EXTENT);
     }
-    if (!(big <= LIST_EXTENT)) s_big = 1;            // also catches non-finite offsets
+    if (far) s_big = 1;                              // offsets out of range or not finite
     __syncthreads();
     const bool keep_all = s_big != 0;
     int cnt = 0;
@@ -1674,7 +1724,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
         while (bits) {
             const int b = __ffs(bits) - 1;
             bits &= bits - 1u;
-            stg(S.istage + (size_t)lb * SMAX + r, ldg(S.stage + (size_t)lb * SMAX + w * 32 + b));
+            stg(S.istage + (size_t)lb * SSTRIDE + r, ldg(S.stage + (size_t)lb * SSTRIDE + w * 32 + b));
             ++r;
         }
     }
@@ -1735,6 +1785,7 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
     if (i < S.n) {
         const D4 p = S.pos[i];
         S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
+        S.xp[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
         const D4 o = S.ori[i];
         S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, 0.0f};
     }

@@ -547,7 +547,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int scnt = __builtin_amdgcn_readfirstlane(S.iscount[lb]);
     const int nlds = min(scnt, SL);                 // stage entries held in LDS
     for (int q = tid; q < nlds; q += BLOCK) {
-        const int slot = ldg(S.istage + (size_t)lb * SMAX + q);
+        const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + q);
         const D4 p = ldg(S.pos + slot);
         s_x[q] = p.x;
         s_y[q] = p.y;
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             Rec c;
             if constexpr (PARTIAL) {
                 if (e >= nlds && e < scnt) {            // stage entry beyond the LDS part
-                    const int slot = ldg(S.istage + (size_t)lb * SMAX + e);
+                    const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + e);
                     const D4 p = ldg(S.pos + slot);
                     const F4 o = ldg(S.ori32 + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
@@ -737,7 +737,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             Rec c;
             if constexpr (PARTIAL) {
                 if (e >= nlds && e < scnt) {
-                    const int slot = ldg(S.istage + (size_t)lb * SMAX + e);
+                    const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + e);
                     const D4 p = ldg(S.pos + slot);
                     const D4 o = ldg(S.ori + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
@@ -1241,7 +1241,7 @@ __device__ __forceinline__ int entry_slot(const SysDev &S, int blk, int scnt, in
     const size_t at = (size_t)chunk * MAXNB * CHUNK + (size_t)r * CHUNK + lane;
     if (scnt >= 0) {
         const int e = S.il16[at];
-        return e < scnt ? S.istage[(size_t)blk * SMAX + e] : -1;
+        return e < scnt ? S.istage[(size_t)blk * SSTRIDE + e] : -1;
     }
     return S.nl[at];
 }

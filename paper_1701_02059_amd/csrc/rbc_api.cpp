@@ -191,8 +191,6 @@ void make_dev_params(rbc_ctx *h) {
         double m = 0.0;
         for (int b = 0; b < 3; ++b) m = std::max(m, p.rc[a][b] + 2.0 * p.skin + 1e-3);
         d.rlmaxf[a] = std::nextafter((float)m, INFINITY);
-        const double f = m - 1e-3 - p.skin;
-        d.rf2f[a] = (float)(f * f);
     }
     const double din = inner_skin(p);
     for (int a = 0; a < 3; ++a)
@@ -273,7 +271,6 @@ size_t layout(HostSys &s, char *base) {
     d.gpos = c.take<D4>(k);
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
     d.nl16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK);
-    d.nlin = c.take<int32_t>(s.nchunk);
     d.ori32 = c.take<F4>(n);
     d.ori32b = c.take<F4>(n);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);
@@ -281,11 +278,11 @@ size_t layout(HostSys &s, char *base) {
     d.vpart = c.take<double>((size_t)s.nchunk * 8);
     d.vred = c.take<double>(32 * 8);
     const int64_t nblkp = (n + BLOCK - 1) / BLOCK;
-    d.stage = c.take<int32_t>((size_t)nblkp * SMAX);
+    d.stage = c.take<int32_t>((size_t)nblkp * SSTRIDE);
     d.scount = c.take<int32_t>(nblkp);
     d.il16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK + 16 * CHUNK);   // + rows the step kernel may prefetch
     d.ilk = c.take<int32_t>(s.nchunk);
-    d.istage = c.take<int32_t>((size_t)nblkp * SMAX);
+    d.istage = c.take<int32_t>((size_t)nblkp * SSTRIDE);
     d.iscount = c.take<int32_t>(nblkp);
     d.blkrows = c.take<int32_t>(nblkp);
     d.bred = c.take<double>((size_t)nblkp * BRED);
@@ -502,7 +499,6 @@ void lists_body(const LaunchCtx &L) {
     launch_cell_pairs(L);
     launch_nlist(L);
     launch_finish_update(L);
-    launch_prune(L);
 }
 
 // The status and message of one slot's error bits.
@@ -704,14 +700,26 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         // this event completes
         hipEventRecord(h->step_ev[slot], h->st);
         // Systems of at least EXACT_MIN_N particles decide from the statistics of the drift
-        // to this step's positions: the host waits for them (the GPU idles for the host's
-        // reaction time, small beside such a system's step).  Smaller systems decide from
-        // the previous step's statistics plus a bound on one more drift, while this step's
-        // force runs.  A system's rule depends on its own size only, so its trajectory does
-        // not depend on its batch.
+        // to this step's positions.  The host waits for them (the GPU idles for the host's
+        // reaction time) only when the previous step's statistics plus a bound on one more
+        // drift cannot rule out a prune; otherwise no list work is due and nothing waits.
+        // Smaller systems always decide from the previous step's statistics plus that bound,
+        // while this step's force runs.  A system's rule depends on its own size and
+        // statistics only, so its trajectory does not depend on its batch.
+        bool waited = false;
         if (exact_any) {
-            hipEventSynchronize(h->step_ev[slot]);
-            read_stats();
+            bool need = false;
+            for (const auto &hs : h->sys) {
+                if (!runs(hs) || hs.n < EXACT_MIN_N || hs.steps_since + 1 >= K) continue;
+                if (!hs.have_stats) { need = true; break; }
+                const double pred_p = (hs.refreshed_last ? 0.0 : std::sqrt(hs.disp2p)) + 2.0 * dt * std::sqrt(hs.v2);
+                if (pred_p > din - EXACT_MARGIN) { need = true; break; }
+            }
+            if (need) {
+                hipEventSynchronize(h->step_ev[slot]);
+                read_stats();
+                waited = true;
+            }
         }
         // decide which systems update their cells (every K steps), which rebuild their
         // lists (the skin is running out) and which prune them (the pruned lists' buffer
@@ -729,8 +737,9 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             }
             bool prune = false, rebuild = false;
             if (hs.n >= EXACT_MIN_N) {
-                // exact displacements at this step's positions (FP32 references: margin)
-                if (std::sqrt(hs.cur_d2p) > din - EXACT_MARGIN) {
+                // exact displacements at this step's positions (FP32 references: margin);
+                // without them the bound above has ruled out any list work
+                if (waited && std::sqrt(hs.cur_d2p) > din - EXACT_MARGIN) {
                     prune = true;
                     rebuild = std::sqrt(hs.cur_d2) > skin - din - EXACT_MARGIN;
                 }
@@ -762,9 +771,8 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         }
         if (!last) swap_drift_buffers(h);
         if (timed) hipEventRecord(h->ev_step[st], h->st);
-        // while the force runs, read this step's drift statistics (already read above when
-        // some system decides from them)
-        if (!exact_any) {
+        // while the force runs, read this step's drift statistics (unless read above)
+        if (!waited) {
             hipEventSynchronize(h->step_ev[slot]);
             read_stats();
         }

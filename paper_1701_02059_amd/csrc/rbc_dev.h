@@ -14,10 +14,11 @@ constexpr int SORT_IPT = 16;          // items per thread in the radix sort
 constexpr int SORT_TILE = BLOCK * SORT_IPT;
 constexpr int MAX_SLOTS = 256;
 constexpr int CNBR_ROW_MAX = 2048;      // cell pairs per cell before the build reports overflow
-constexpr int SMAX = 1024;             // neighbours staged in LDS per 256-particle block
+constexpr int SMAX = 2048;             // stage entries (slots) per 256-particle block
+constexpr int SSTRIDE = SMAX + 32;     // stride of the blocks' stage lists (not a multiple of a large power of two)
 constexpr int CANDMAX = 1024;          // candidate cells (cell-pair entries) per block while staging
-constexpr int SSMAX = 4096;            // particles in a block's candidate cells while staging
 constexpr int USTAGE = 2048;           // candidate particles staged in LDS while building a block's lists
+static_assert(USTAGE <= SMAX && USTAGE < 0xffff, "a staged candidate union is the block's stage, indexed in 16 bits");
 constexpr float LIST_EXTENT = 4096.0f; // largest FP32 offset (sigma) allowed in that staging
 constexpr int CULLMAX = 256;           // candidate cells whose bounding spheres are staged for culling
 constexpr int SCAN_TILE = 2048;        // elements per block in the segmented scans
@@ -104,7 +105,6 @@ struct SysDev {
     int32_t *gstart, *gcount, *gseed, *sgcell;      // seed grid (gcap+1, gcap, k, k)
     D4 *gpos;                                       // centroids in grid order, w = seed index (k)
     int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
-    int32_t *nlin;                                  // per chunk: rows holding partners built within rc + skin
     uint16_t *nl16;                                 // the same lists as stage indices (staged blocks)
     F4 *ori32;                                      // FP32 copy of the orientations (mixed-mode staging)
     F4 *ori32b;                                     // its second buffer (fused drift target; pos2 / ori2 likewise)
@@ -132,7 +132,6 @@ struct DevParams {
     double rl2[3][3];      // (rc + 2 skin)^2 with a small relative margin: list radius
     float rl2f[3][3];      // (rc + 2 skin + 1e-3)^2 rounded up: list radius for FP32 offsets
     float rlmaxf[3];       // largest list radius (+ 1e-3) of a particle type, rounded up
-    float rf2f[3];         // (largest rc of the type + skin)^2: list entries inside come first
     float rin2f[3][3];     // (rc + 2 inner skin + 1e-3)^2 rounded up: pruned-list radius for FP32 offsets
     float rc2lo[3][3];     // FP32 squared distances below this are inside fl(rc^2) in the exact test
     float rc2hi[3][3];     // ... and at or above this outside it; between, the FP64 test decides

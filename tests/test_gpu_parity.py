@@ -549,12 +549,18 @@ def test_nonfinite_state_is_reported(R, mp, patch):
     c.close()
 
 
-def _dense_cloud(n_side=14, spacing=1.36, seed=11):
-    """Jittered cubic lattice of lipids (3D, density ~0.4): neighbour unions of a
-    256-particle block exceed the LDS stage, so the global-gather path is used."""
+def _dense_cloud(n_side=14, spacing=1.36, seed=11, far=6000.0):
+    """Jittered cubic lattice of lipids (3D, density ~0.4), plus a 4x4x4 cluster of the
+    same lattice `far` sigma away along x.  The pruned partners of a 256-particle block
+    in the cloud can outgrow the step kernel's LDS stage, and the block that holds both
+    cloud and cluster particles spans more than the FP32 offset range of the list
+    build, so it keeps 32-bit lists of global slots."""
     rng = np.random.default_rng(seed)
     g = np.arange(n_side) * spacing
     x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    h = np.arange(4) * spacing
+    c = np.stack(np.meshgrid(h, h, h, indexing="ij"), axis=-1).reshape(-1, 3) + np.array([far, 0.0, 0.0])
+    x = np.concatenate([x, c])
     x = x + rng.normal(0, 0.05, size=x.shape)
     nrm = rng.normal(size=x.shape)
     nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
@@ -567,8 +573,8 @@ def _dense_cloud(n_side=14, spacing=1.36, seed=11):
 def test_dense_3d_cloud_unstaged_blocks(R, mp, prec):
     """All three stage layouts of the step kernel at once: blocks whose pruned partners
     fit its LDS stage (640 entries in mixed mode, 800 in FP64), blocks with more (the
-    entries past the LDS part read from global memory) and blocks whose full lists
-    outgrew a stage (global slots in 32-bit lists)."""
+    entries past the LDS part read from global memory) and a block without a stage
+    (global slots in 32-bit lists)."""
     s = _dense_cloud()
     p = O.params_for(s, mp)
     F0, T0, U0, W0 = O.forces(p, s)
