@@ -494,7 +494,8 @@ __device__ __forceinline__ float lipid_pair_bf(const DevParams &P, float dx, flo
 // FP32 orientations with the type in w (mixed) or FP64 orientations and a type byte.
 // The stage is the block's pruned partner set; entries beyond the LDS part (rare)
 // are read from global memory.  Mixed mode keeps one more entry, a sentinel far
-// from every particle, which list padding points to.
+// from every particle with a padding type, which list padding points to (on periodic
+// axes the wrap may bring it back into range, so periodic systems also test its type).
 template <int MIXED>
 struct Stage {
     static constexpr int lds = MIXED ? 640 : 800;
@@ -503,6 +504,7 @@ struct Stage {
 };
 static_assert(Stage<1>::lds < SMAX && (Stage<1>::ext * 24) % 16 == 0, "mixed stage layout");
 constexpr double SENTINEL = 1.0e8;    // sigma: the padding entry's coordinates (finite FP32 squares)
+constexpr int PAD_TYPE = 3;           // the padding entry's type (a periodic wrap may bring it into range)
 
 // One workgroup per 256 consecutive cell-sorted particles.  The block's pruned
 // partners (its stage) are read once from HBM into LDS; lane i then walks column i of
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         s_x[SL] = SENTINEL;
         s_y[SL] = SENTINEL;
         s_z[SL] = SENTINEL;
-        s_n4[SL] = F4{0.0f, 0.0f, 1.0f, __int_as_float(0)};
+        s_n4[SL] = F4{0.0f, 0.0f, 1.0f, __int_as_float(PAD_TYPE)};
     }
     __syncthreads();
     if (chunk >= S.nchunk) return;
@@ -668,6 +670,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 const float hi = FAST ? (tj == 0 ? hiA : hiB) : sel_cutf(tj, hiA, hiB, hiC);
                 in[q] = r2[q] < lo;
                 band[q] = !in[q] && r2[q] < hi;
+                if constexpr (PER) {            // the wrapped sentinel may land anywhere
+                    in[q] = in[q] && tj != PAD_TYPE;
+                    band[q] = band[q] && tj != PAD_TYPE;
+                }
                 anyband = anyband || band[q];
                 lip[q] = (ti | tj) == 0;
             }

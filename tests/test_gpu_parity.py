@@ -593,6 +593,33 @@ def test_dense_3d_cloud_unstaged_blocks(R, mp, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fully_periodic_cloud(R, mp, prec):
+    """A jittered lattice periodic on all three axes.  List padding points at a far
+    sentinel entry, which a periodic wrap would bring back into range; the pair set and
+    forces must still be the oracle's."""
+    rng = np.random.default_rng(5)
+    n, spacing = 10, 1.5
+    g = np.arange(n) * spacing
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    x = x + rng.normal(0, 0.05, size=x.shape)
+    nrm = rng.normal(size=x.shape)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    N = x.shape[0]
+    box = np.full(3, n * spacing)
+    s = I.System("cloud3p", np.mod(x, box), nrm, np.zeros(N, np.int32), np.zeros((N, 3)), np.zeros((N, 3)),
+                 np.zeros((0, 2), np.int32), np.zeros(0), box, np.ones(3, np.int32))
+    p = O.params_for(s, mp)
+    F0, T0, U0, W0 = O.forces(p, s)
+    c = _ctx(R, mp, s, R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED)
+    assert np.array_equal(c.get_pairs(), O.pairs(p, s.x, s.type))
+    F, T = (to_np(t) for t in c.forces())
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    check_forces(F, F0, tol, PP_FP64_TOL if tol == FP64_TOL else PP_MIXED_TOL, "F")
+    check_forces(T, T0, tol, PP_FP64_TOL if tol == FP64_TOL else PP_MIXED_TOL, "tau")
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_forces_nondefault_constants(R, prec, ves):
     """Generic pair-law path: spontaneous-curvature angle, zeta = 3, mu = 2.5."""
     from paper_1701_02059_amd.inputs import ModelParams
