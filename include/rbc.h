@@ -211,6 +211,13 @@ rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_
  * timing (an event per step) on or off for later calls. */
 rbc_status rbc_step_times(rbc_handle h, int32_t enable, int64_t cap, double *ms, int64_t *count, double *gap_ms);
 
+/* Host time per step of the last rbc_step / rbc_ensemble_step call: [host] *host_us
+ * the microseconds per step the calling thread spent outside waits for the device
+ * (step decisions and kernel launches, cell-update launches included), *wait_us the
+ * microseconds per step it waited for the drift statistics of earlier steps.  Either
+ * pointer may be NULL; both read -1 before the first call.  No device work. */
+rbc_status rbc_host_times(rbc_handle h, double *host_us, double *wait_us);
+
 /* Replay the step's fixed launch sequence (the force kernel with its fused drift
  * and the drift statistics) as a HIP graph captured once per system table and time
  * step (enable = 1), or launch every kernel directly (0).  Cell updates always

@@ -1068,9 +1068,10 @@ __device__ int cell_query_wave(const SysDev &S, const SysScal *sc, int A, double
 
 // Cell-pair kernels.  Systems of at least CQ_SERIAL_MIN cells take one thread per
 // cell (there are enough threads to hide the serial walk's latency); smaller ones
-// give each cell a wavefront, with four blocks per 256-cell block of the cell map and
-// CQ_WAVE consecutive cells per wavefront in turn.  Both write the same rows.
-constexpr int CQ_WAVE = 16;
+// give each cell a wavefront, CQ_WAVE consecutive cells per wavefront in turn and
+// CQ_BLOCKS blocks per 256-cell block of the cell map.  Both write the same rows.
+constexpr int CQ_WAVE = 1;
+constexpr int CQ_BLOCKS = BLOCK / ((BLOCK / WAVE) * CQ_WAVE);
 constexpr int CQ_SERIAL_MIN = 20000;
 
 __global__ __launch_bounds__(BLOCK) void k_cnbr_count_serial(const SysDev *Sd, Maps L_maps, double search) {
@@ -1106,14 +1107,14 @@ __global__ __launch_bounds__(BLOCK) void k_cnbr_fill_serial(const SysDev *Sd, Ma
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cnbr_count(const SysDev *Sd, Maps L_maps, double search) {
-    const int cbk = blockIdx.x >> 2;
+    const int cbk = blockIdx.x / CQ_BLOCKS;
     if (cbk >= L_maps.c[L_maps.nsys]) return;
     const int s = find_sys(L_maps.c, L_maps.nsys, cbk);
     const SysDev &S = Sd[s];
     if (!S.sc->rebuild || S.k >= CQ_SERIAL_MIN) return;
     const int lb = cbk - L_maps.c[s];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int c0 = lb * BLOCK + (blockIdx.x & 3) * WAVE + wv * CQ_WAVE;
+    const int c0 = lb * BLOCK + ((blockIdx.x % CQ_BLOCKS) * (BLOCK / WAVE) + wv) * CQ_WAVE;
     int m = 0;
     for (int k = 0; k < CQ_WAVE; ++k) {
         const int c = c0 + k;
@@ -1136,21 +1137,21 @@ __global__ __launch_bounds__(BLOCK) void k_cnbr_count(const SysDev *Sd, Maps L_m
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cnbr_fill(const SysDev *Sd, Maps L_maps, double search) {
-    const int cbk = blockIdx.x >> 2;
+    const int cbk = blockIdx.x / CQ_BLOCKS;
     if (cbk >= L_maps.c[L_maps.nsys]) return;
     const int s = find_sys(L_maps.c, L_maps.nsys, cbk);
     const SysDev &S = Sd[s];
     if (!S.sc->rebuild || S.k >= CQ_SERIAL_MIN) return;
     const int lb = cbk - L_maps.c[s];
     const int wv = threadIdx.x / WAVE;
-    const bool first = lb == 0 && (blockIdx.x & 3) == 0 && threadIdx.x == 0;
+    const bool first = lb == 0 && blockIdx.x % CQ_BLOCKS == 0 && threadIdx.x == 0;
     const int total = S.cnbr_start[S.k];
     if (first) S.sc->cnbr_total = total;
     if (total > S.cnbr_cap || (S.sc->err & ERR_CNBR)) {
         if (first) atomicOr(&S.sc->err, ERR_CNBR);
         return;
     }
-    const int c0 = lb * BLOCK + (blockIdx.x & 3) * WAVE + wv * CQ_WAVE;
+    const int c0 = lb * BLOCK + ((blockIdx.x % CQ_BLOCKS) * (BLOCK / WAVE) + wv) * CQ_WAVE;
     for (int k = 0; k < CQ_WAVE; ++k) {
         const int c = c0 + k;
         if (c >= S.k) break;
@@ -1167,10 +1168,10 @@ void launch_cell_bounds(const LaunchCtx &L) {
 void launch_cell_pairs(const LaunchCtx &L) {
     if (L.nblk_c == 0) return;
     hipLaunchKernelGGL(k_cnbr_count_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
-    hipLaunchKernelGGL(k_cnbr_count, dim3(4 * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    hipLaunchKernelGGL(k_cnbr_count, dim3(CQ_BLOCKS * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
     launch_scan(L, 3);
     hipLaunchKernelGGL(k_cnbr_fill_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
-    hipLaunchKernelGGL(k_cnbr_fill, dim3(4 * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    hipLaunchKernelGGL(k_cnbr_fill, dim3(CQ_BLOCKS * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
 }
 
 // ------------------------------------------------------------------ neighbour lists

@@ -370,7 +370,7 @@ __device__ __forceinline__ void volume_term(const SysScal *sc, const D4 &x, cons
 // |x - x_prune|^2 of the wave's particles (chunk w of the particle block) go to the
 // block's partial slots 3w, 3w+1 and 3w+2; a non-finite state raises the system's
 // error bit.
-__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, int w, double disp2, double v2, double disp2p,
+__device__ __forceinline__ void drift_stats(const SysDev &S, int blk, int w, double &disp2, double &v2, double &disp2p,
                                             bool bad) {
     disp2 = wave_max_lane63(disp2);
     v2 = wave_max_lane63(v2);
@@ -399,6 +399,29 @@ __device__ __forceinline__ void publish_drift(SysScal *sc, StepStat *hstat) {
     __threadfence_system();
     e->tag = st + 1;
     sc->step = st + 1;
+}
+
+__device__ __forceinline__ void swap_drift(SysDev &W);
+
+// A small (split) system publishes its drift statistics from the step kernel itself:
+// lane 63 of each workgroup's wave 0 (which holds the wave's maxima after drift_stats)
+// folds them into the system's running maxima; the last of the system's nwg
+// workgroups (one per chunk) to finish publishes them and swaps the drift buffers, as the statistics
+// kernel does for larger systems.  Atomic maxima of non-negative doubles' bit patterns
+// do not depend on their order.
+__device__ __forceinline__ void publish_split(SysDev &W, int nwg, double disp2, double v2, double disp2p) {
+    if (lane_id_f() != WAVE - 1) return;
+    SysScal *sc = W.sc;
+    atomicMax(&sc->maxdisp2, dbits(disp2));
+    atomicMax(&sc->maxv2, dbits(v2));
+    atomicMax(&sc->maxdisp2p, dbits(disp2p));
+    __threadfence();
+    if (atomicAdd(&sc->parts_done, 1u) == (unsigned)nwg - 1u) {
+        __threadfence();
+        publish_drift(sc, W.hstat);
+        sc->parts_done = 0;
+        swap_drift(W);
+    }
 }
 
 __device__ __forceinline__ void swap_drift(SysDev &W) {
@@ -940,6 +963,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     if (KICK == 2) {
         drift_stats(S, lb, csub, disp2, vmax2, disp2p, bad);
         if (P.vol_on) volume_chunk_store(S, chunk, vsum);
+        if (split) publish_split(const_cast<SysDev &>(S), S.nchunk, disp2, vmax2, disp2p);   // a workgroup per chunk
     }
     if (ENERGY) {
         // per-chunk partials of U, W, KE, sum F and sum (r x F + tau), reduced across
@@ -1050,6 +1074,7 @@ constexpr int STATS_BLOCKS = 16;
 
 __global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int swap) {
     SysDev &S = Sd[blockIdx.x / STATS_BLOCKS];
+    if (swap && S.split) return;          // the step kernel published this small system's drift
     const int part = blockIdx.x % STATS_BLOCKS;
     const int per = (S.nchunk + STATS_BLOCKS - 1) / STATS_BLOCKS;
     const int c0 = part * per, c1 = min(S.nchunk, c0 + per);

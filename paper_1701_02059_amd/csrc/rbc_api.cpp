@@ -15,6 +15,7 @@
 #include "rbc_dev.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -117,6 +118,8 @@ struct rbc_ctx {
     bool have_prev_end = false;
     std::vector<double> step_ms;      // the last call's step intervals
     double gap_ms = -1.0;             // from the previous call's last step to the last call's start
+    // host time of the last step call, per step: outside waits for the device, and waiting
+    double host_us_step = -1.0, wait_us_step = -1.0;
     // force-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tb, te;
@@ -601,6 +604,16 @@ void drop_graphs(rbc_ctx *h) {
     h->graph_version = -1;
 }
 
+// Whether some running system needs the statistics kernel after a fused drift (small,
+// split systems publish their statistics from the step kernel).
+bool stats_kernel_needed(const rbc_ctx *h) {
+    for (int s = 0; s < h->nsys; ++s) {
+        const HostSys &hs = h->sys[s];
+        if (runs(hs) && hs.n > 0 && !hs.dev.split) return true;
+    }
+    return false;
+}
+
 template <class F>
 hipGraphExec_t capture(rbc_ctx *h, F body) {
     hipGraph_t g = nullptr;
@@ -619,9 +632,10 @@ bool ensure_graphs(rbc_ctx *h, double dt) {
     if (h->graph_version == h->table_version && h->graph_dt == dt && h->g_step && h->g_last) return true;
     drop_graphs(h);
     const int mixed = h->prm.precision == RBC_MIXED;
+    const bool stats = stats_kernel_needed(h);
     h->g_step = capture(h, [&] {
         launch_force(h->L, mixed, 0, 2, dt);
-        launch_drift_stats_swap(h->L);
+        if (stats) launch_drift_stats_swap(h->L);
     });
     h->g_last = capture(h, [&] { launch_force(h->L, mixed, 0, 1, dt); });
     if (!(h->g_step && h->g_last)) {
@@ -671,6 +685,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
         }
         hipEventRecord(h->ev_call0, h->st);
     }
+    const bool stats_kernel = stats_kernel_needed(h);
     bool exact_any = false;
     for (const auto &hs : h->sys)
         if (runs(hs) && hs.n >= EXACT_MIN_N) exact_any = true;
@@ -689,6 +704,31 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             hs.cur_d2p = e.d2p;
             hs.drifts++;
         }
+    };
+    using clk = std::chrono::steady_clock;
+    const auto t_loop0 = clk::now();
+    double wait_s = 0.0;
+    // Waiting for a step's drift statistics: poll the ring tags in pinned memory (the
+    // device writes them last, after a system-scope fence), checking the event that
+    // follows their publication every 64 polls; the event completing (or failing) ends
+    // the wait too, and read_stats then checks the tags.  Polling answers within about
+    // a microsecond of the publication, where a blocking event wait takes several.
+    auto stats_ready = [&]() {
+        for (int s = 0; s < h->nsys; ++s) {
+            const HostSys &hs = h->sys[s];
+            if (!runs(hs) || hs.n == 0) continue;
+            const volatile StepStat &e = h->h_stat[(size_t)s * STAT_RING + hs.drifts % STAT_RING];
+            if (e.tag != hs.drifts + 1) return false;
+        }
+        return true;
+    };
+    auto wait_event = [&](hipEvent_t ev) {
+        const auto a = clk::now();
+        for (int k = 1;; ++k) {
+            if (stats_ready()) break;
+            if (k % 64 == 0 && hipEventQuery(ev) != hipErrorNotReady) break;
+        }
+        wait_s += std::chrono::duration<double>(clk::now() - a).count();
     };
     launch_kick_drift(h->L, dt);
     h->vol_fresh = true;              // every drift also writes the volume's lipid sums
@@ -716,7 +756,7 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
                 if (pred_p > din - EXACT_MARGIN) { need = true; break; }
             }
             if (need) {
-                hipEventSynchronize(h->step_ev[slot]);
+                wait_event(h->step_ev[slot]);
                 read_stats();
                 waited = true;
             }
@@ -767,13 +807,13 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             hipGraphLaunch(last ? h->g_last : h->g_step, h->st);
         } else {
             force_launch(h, 0, last ? 1 : 2, dt);
-            if (!last) launch_drift_stats_swap(h->L);
+            if (!last && stats_kernel) launch_drift_stats_swap(h->L);
         }
         if (!last) swap_drift_buffers(h);
         if (timed) hipEventRecord(h->ev_step[st], h->st);
         // while the force runs, read this step's drift statistics (unless read above)
         if (!waited) {
-            hipEventSynchronize(h->step_ev[slot]);
+            wait_event(h->step_ev[slot]);
             read_stats();
         }
         for (int s = 0; s < h->nsys; ++s) {
@@ -797,9 +837,16 @@ rbc_status step_all(rbc_ctx *h, int64_t nsteps, double dt) {
             hs.steps_total++;
         }
         if (h->timing && h->tcount >= (int)h->tb.size()) {   // the timing events are all in use
+            const auto a = clk::now();
             HIPCHK(hipStreamSynchronize(h->st));
+            wait_s += std::chrono::duration<double>(clk::now() - a).count();
             harvest_timing(h);
         }
+    }
+    {
+        const double loop_s = std::chrono::duration<double>(clk::now() - t_loop0).count();
+        h->host_us_step = (loop_s - wait_s) / (double)nsteps * 1e6;
+        h->wait_us_step = wait_s / (double)nsteps * 1e6;
     }
     h->ens_steps += nsteps;
     if (timed) hipEventRecord(h->ev_prev_end, h->st);
@@ -1519,6 +1566,13 @@ rbc_status rbc_step_times(rbc_handle h, int32_t enable, int64_t cap, double *ms,
     const bool on = enable != 0;
     if (on && !h->step_timing) h->have_prev_end = false;   // gaps count from the first timed call
     h->step_timing = on;
+    return RBC_OK;
+}
+
+rbc_status rbc_host_times(rbc_handle h, double *host_us, double *wait_us) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    if (host_us) *host_us = h->host_us_step;
+    if (wait_us) *wait_us = h->wait_us_step;
     return RBC_OK;
 }
 

@@ -26,7 +26,7 @@ FUNCTIONS = [
     "rbc_status_string", "rbc_last_error", "rbc_ensemble_create", "rbc_ensemble_footprint", "rbc_ensemble_admit",
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
     "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs", "rbc_ensemble_stage", "rbc_ensemble_commit",
-    "rbc_get_pairs_noalloc", "rbc_ensemble_failed", "rbc_step_times",
+    "rbc_get_pairs_noalloc", "rbc_ensemble_failed", "rbc_step_times", "rbc_host_times",
 ]
 
 
@@ -76,6 +76,7 @@ def lib():
             "rbc_get_pairs_noalloc": [h, C.c_int64, ip, i64p],
             "rbc_ensemble_failed": [h, C.c_int64, ip, ip, i64p],
             "rbc_step_times": [h, C.c_int32, C.c_int64, dp, i64p, dp],
+            "rbc_host_times": [h, dp, dp],
             "rbc_energy": [h, dp],
             "rbc_stats": [h, i64p],
             "rbc_get_cells": [h, ip, dp],
@@ -178,6 +179,12 @@ def _step_times(h, enable):
     return ms[:n.value], gap.value
 
 
+def _host_times(h):
+    host, wait = C.c_double(-1.0), C.c_double(-1.0)
+    _check(h, lib().rbc_host_times(h, C.byref(host), C.byref(wait)))
+    return host.value, wait.value
+
+
 class Context:
     """One system on the current GPU (rbc_create / rbc_set_system / rbc_step ...)."""
 
@@ -278,6 +285,10 @@ class Context:
     def step_times(self, enable: bool = True):
         """As Ensemble.step_times."""
         return _step_times(self._h, enable)
+
+    def host_times(self):
+        """As Ensemble.host_times."""
+        return _host_times(self._h)
 
     def force_timing(self, enable: bool = True):
         avg = C.c_double(0.0)
@@ -393,6 +404,11 @@ class Ensemble:
         """Per-step GPU intervals (ms) of the last step call and the gap (ms) since the
         previous timed call (-1: none); turns step timing on or off for later calls."""
         return _step_times(self._h, enable)
+
+    def host_times(self):
+        """Microseconds per step of the last step call that the host spent deciding and
+        launching, and waiting for earlier steps' drift statistics (-1 before any)."""
+        return _host_times(self._h)
 
     def info(self) -> dict:
         out = np.zeros(4, dtype=np.int64)
