@@ -50,6 +50,7 @@ PEAK_HBM = 8000.0           # GB/s
 FORCE_TRAFFIC = {"sources_sha256": "76155b89d5fd69fd", "skin": 0.5, "inner_skin": None,
                  "bytes": 2521082635, "fetch_kib": 955267, "write_kib": 551460,
                  "valu_insts": 278759823}   # SQ_INSTS_VALU per launch (wavefront instructions)
+BYTES_BUILD_READ = 25       # list build: position (3 x 8 B) and type (1 B) of every particle, read once
 CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
                   "paper_1701_02059_amd/csrc/rbc_dev.h")
@@ -91,6 +92,8 @@ def timed_run(R, mp, system, precision, steps, warmup, label):
     ctx.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    host_us, wait_us = ctx.host_times()
+    build_ms, builds = ctx.build_timing()
     avg_ms, launches = ctx.force_timing(False)
     st1 = ctx.stats()
     e = ctx.energy()
@@ -105,11 +108,43 @@ def timed_run(R, mp, system, precision, steps, warmup, label):
            "list_rebuilds": st1["rebuilds"] - st0["rebuilds"],
            "early_rebuilds": st1["early_rebuilds"] - st0["early_rebuilds"],
            "prunes": st1["prunes"] - st0["prunes"],
-           "max_list_rows": st1["max_list_rows"], "energy": e.tolist()}
+           "max_list_rows": st1["max_list_rows"],
+           # the list-build kernel (lists and pruned lists of a build), HIP events
+           "build_kernel_ms": build_ms, "build_launches": builds,
+           # host time per step in the step loop: deciding and launching, and waiting for
+           # the drift statistics of the step before
+           "host_us_per_step": host_us, "host_wait_us_per_step": wait_us,
+           "energy": e.tolist()}
     log(f"[{label}] {steps} steps in {t1 - t0:.3f} s -> {out['particle_steps_per_s']:.4g} particle-steps/s, "
         f"force kernel {avg_ms * 1e3:.1f} us avg over {launches} launches, {out['cell_updates']} cell updates, "
         f"{out['list_rebuilds']} list builds, {out['prunes']} prunes")
     return ctx, out
+
+
+def list_output_bytes(ctx):
+    """What a list build of the current state writes, in bytes: the 16-bit lists and
+    pruned lists as stored (ELL rows of each 64-particle chunk, padding included) and
+    the 32-bit stage and pruned-stage slots of each 256-particle block."""
+    nlk = ctx.debug_array(8).view(np.int32).astype(np.int64)
+    scount = ctx.debug_array(9).view(np.int32).astype(np.int64)
+    iscount = ctx.debug_array(12).view(np.int32).astype(np.int64)
+    ilk = ctx.debug_array(13).view(np.int32).astype(np.int64)
+    return int(2 * 64 * (nlk.sum() + ilk.sum()) + 4 * (np.maximum(scount, 0).sum() + np.maximum(iscount, 0).sum()))
+
+
+def build_roofline(mixed, list_bytes, n):
+    """The list-build kernel against the HBM roofline: its algorithmic bytes are every
+    particle's position and type read once (BYTES_BUILD_READ per particle) plus what it
+    writes (list_output_bytes)."""
+    if not mixed["build_launches"]:
+        return None
+    b = BYTES_BUILD_READ * n + list_bytes
+    t = mixed["build_kernel_ms"] * 1e-3
+    return {"kernel": "k_nlist (candidate union, stage, lists and pruned lists of a build)", "bound": "hbm",
+            "avg_launch_ms": round(mixed["build_kernel_ms"], 4), "launches_timed": mixed["build_launches"],
+            "algorithmic_bytes_per_launch": b, "achieved": round(b / t / 1e9, 3), "peak": PEAK_HBM,
+            "unit": "GB/s", "frac": round(b / t / 1e9 / PEAK_HBM, 4),
+            "roofline_time_us": round(b / (PEAK_HBM * 1e9) * 1e6, 2)}
 
 
 def _oracle_steps(system, mp, threads):
@@ -318,6 +353,7 @@ def main():
     # the amortised cell updates, list builds and prunes
     steps = max(args.steps, 2 * mp.update_every)
     ctx, mixed = timed_run(R, mp, system, R.RBC_MIXED, steps, args.warmup, "mixed")
+    list_bytes = list_output_bytes(ctx)
     n_ll, n_wca = pair_counts(ctx, system)
     n_bond = int(system.bonds.shape[0])
     ctx.close()
@@ -352,6 +388,8 @@ def main():
             "valu_busy_frac": round(valu_busy, 4) if valu_busy else None,
             "lipid_pairs": n_ll, "wca_pairs": n_wca, "bonds": n_bond}
     log(f"[roofline] {roof}")
+    build = build_roofline(mixed, list_bytes, system.N)
+    log(f"[list build] {build}")
 
     fp64 = None
     if not args.no_fp64:
@@ -421,6 +459,7 @@ def main():
                                f"{mp.update_every} steps, skin {mp.skin}, pruned-list buffer {mp.inner_skin}",
                    "particles": system.N, "precision": "mixed", "parallelism": "single GPU"},
         "roofline": roof,
+        "list_build": build,
         "cpu_baseline": cpu,
         "fp64": fp64,
         "mixed": mixed,

@@ -202,6 +202,13 @@ rbc_status rbc_get_cells(rbc_handle h, int32_t *owner, double *seeds);
  * when timing is enabled), and the number of launches timed. */
 rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_t *launches);
 
+/* Average duration in milliseconds of the list-build kernel launches (one per list
+ * build or cell update, building every rebuilding system's lists and pruned lists)
+ * timed while force timing was enabled, since the last call, and their number
+ * (sync).  Timing keeps at most 64 launches between harvests, which every 256 timed
+ * steps and every call of this function or rbc_force_timing make. */
+rbc_status rbc_build_timing(rbc_handle h, double *avg_ms, int64_t *launches);
+
 /* Per-step timing of the last rbc_step / rbc_ensemble_step call made while step
  * timing was on: [host] ms[q] (at most cap) the GPU interval of step q, from the end
  * of the previous step's launches (for q = 0, the start of the call) to the end of

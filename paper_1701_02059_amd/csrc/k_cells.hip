@@ -1656,14 +1656,25 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     for (int w = tid; w < SMAX / 4; w += BLOCK) reinterpret_cast<unsigned *>(s_flag)[w] = 0u;
     const D4 ref = ldg(S.pos + (size_t)lb * BLOCK);
     bool far = false;
-    for (int q = tid; q < scnt; q += BLOCK) {
-        const int slot = ldg(S.stage + (size_t)lb * SSTRIDE + q);
-        const D4 pj = ldg(S.pos + slot);
-        const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
-        const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
-        const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
-        s_o[q] = F4{ox, oy, oz, __int_as_float((int)pj.w & 3)};
-        far = far || !(fabsf(ox) <= LIST_EXTENT && fabsf(oy) <= LIST_EXTENT && fabsf(oz) <= LIST_EXTENT);
+    // four entries per thread in flight: their slots, then their positions
+    for (int q0 = tid; q0 < scnt; q0 += 4 * BLOCK) {
+        int slot[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = q0 + k * BLOCK;
+            slot[k] = q < scnt ? ldg(S.stage + (size_t)lb * SSTRIDE + q) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = q0 + k * BLOCK;
+            if (slot[k] < 0) break;
+            const D4 pj = ldg(S.pos + slot[k]);
+            const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
+            const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
+            const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
+            s_o[q] = F4{ox, oy, oz, __int_as_float((int)pj.w & 3)};
+            far = far || !(fabsf(ox) <= LIST_EXTENT && fabsf(oy) <= LIST_EXTENT && fabsf(oz) <= LIST_EXTENT);
+        }
     }
     if (far) s_big = 1;                              // offsets out of range or not finite
     __syncthreads();
@@ -1719,15 +1730,13 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     }
     __syncthreads();
     const int nkept = block_scan_lds(s_pre, nwords, s_w);
-    for (int w = tid; w < nwords; w += BLOCK) {
-        unsigned bits = s_bits[w];
-        int r = s_pre[w];
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1u;
-            stg(S.istage + (size_t)lb * SSTRIDE + r, ldg(S.stage + (size_t)lb * SSTRIDE + w * 32 + b));
-            ++r;
-        }
+    // the pruned stage: every kept entry's slot at its rank among the kept entries
+    for (int q = tid; q < scnt; q += BLOCK) {
+        const int w = q >> 5;
+        const unsigned m = 1u << (q & 31);
+        if (s_bits[w] & m)
+            stg(S.istage + (size_t)lb * SSTRIDE + s_pre[w] + __popc(s_bits[w] & (m - 1u)),
+                ldg(S.stage + (size_t)lb * SSTRIDE + q));
     }
     // rewrite the kept entries as pruned-stage indices (the lane reads back what it
     // wrote), padding every lane to the chunk's row count rounded up to even (the step

@@ -126,6 +126,11 @@ struct rbc_ctx {
     int tcount = 0;
     double tsum_ms = 0.0;
     int64_t tlaunches = 0;
+    // list-build kernel timing (with force timing)
+    std::vector<hipEvent_t> nb, ne;
+    int ncount = 0;
+    double nsum_ms = 0.0;
+    int64_t nlaunches = 0;
 };
 
 namespace {
@@ -390,7 +395,7 @@ bool any_live(const rbc_ctx *h) {
 }
 
 void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd);
-void lists_body(const LaunchCtx &L);
+void lists_body(rbc_ctx *h, const LaunchCtx &L);
 
 // Launch context whose block maps cover only the systems in `which`, with their
 // rebuild flags set: the device builds the restricted prefix maps from the flags,
@@ -445,7 +450,7 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
 // distances, so the cell pairs and the lists stay complete.
 void run_lists(rbc_ctx *h, const std::vector<int> &which) {
     if (which.empty()) return;
-    lists_body(restricted(h, which));
+    lists_body(h, restricted(h, which));
     for (int s : which) h->sys[s].rebuilds++;
 }
 
@@ -493,14 +498,17 @@ void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd) {
     launch_morton_sort_seeds(L);
     launch_block_permute(L);
     launch_grid_build(L);
-    lists_body(L);
+    lists_body(h, L);
 }
 
 // Cell radii, cell pairs and neighbour lists on the current cells.
-void lists_body(const LaunchCtx &L) {
+void lists_body(rbc_ctx *h, const LaunchCtx &L) {
     launch_cell_bounds(L);
     launch_cell_pairs(L);
+    const bool t = h->timing && h->ncount < (int)h->nb.size();
+    if (t) hipEventRecord(h->nb[h->ncount], L.st);
     launch_nlist(L);
+    if (t) hipEventRecord(h->ne[h->ncount++], L.st);
     launch_finish_update(L);
 }
 
@@ -585,6 +593,14 @@ void harvest_timing(rbc_ctx *h) {
         }
     }
     h->tcount = 0;
+    for (int q = 0; q < h->ncount; ++q) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->nb[q], h->ne[q]) == hipSuccess) {
+            h->nsum_ms += ms;
+            h->nlaunches++;
+        }
+    }
+    h->ncount = 0;
 }
 
 rbc_status ensure_forces(rbc_ctx *h) {
@@ -1160,6 +1176,8 @@ rbc_status rbc_destroy(rbc_handle h) {
     }
     for (auto e : h->tb) hipEventDestroy(e);
     for (auto e : h->te) hipEventDestroy(e);
+    for (auto e : h->nb) hipEventDestroy(e);
+    for (auto e : h->ne) hipEventDestroy(e);
     for (int q = 0; q < RING; ++q) if (h->step_ev[q]) hipEventDestroy(h->step_ev[q]);
     for (auto e : h->ev_step) hipEventDestroy(e);
     for (hipEvent_t e : {h->ev_call0, h->ev_prev_end, h->ev_prev_end_last})
@@ -1442,7 +1460,24 @@ rbc_status rbc_force_timing(rbc_handle h, int32_t enable, double *avg_ms, int64_
             hipEventCreate(&h->tb[q]);
             hipEventCreate(&h->te[q]);
         }
+        h->nb.resize(64);
+        h->ne.resize(64);
+        for (int q = 0; q < 64; ++q) {
+            hipEventCreate(&h->nb[q]);
+            hipEventCreate(&h->ne[q]);
+        }
     }
+    return RBC_OK;
+}
+
+rbc_status rbc_build_timing(rbc_handle h, double *avg_ms, int64_t *launches) {
+    if (!h) return RBC_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(h->st));
+    harvest_timing(h);
+    if (avg_ms) *avg_ms = h->nlaunches ? h->nsum_ms / (double)h->nlaunches : 0.0;
+    if (launches) *launches = h->nlaunches;
+    h->nsum_ms = 0.0;
+    h->nlaunches = 0;
     return RBC_OK;
 }
 

@@ -27,6 +27,7 @@ FUNCTIONS = [
     "rbc_ensemble_step", "rbc_ensemble_get_state", "rbc_ensemble_energy", "rbc_ensemble_retire",
     "rbc_ensemble_info", "rbc_debug_array", "rbc_set_graphs", "rbc_ensemble_stage", "rbc_ensemble_commit",
     "rbc_get_pairs_noalloc", "rbc_ensemble_failed", "rbc_step_times", "rbc_host_times",
+    "rbc_build_timing",
 ]
 
 
@@ -77,6 +78,7 @@ def lib():
             "rbc_ensemble_failed": [h, C.c_int64, ip, ip, i64p],
             "rbc_step_times": [h, C.c_int32, C.c_int64, dp, i64p, dp],
             "rbc_host_times": [h, dp, dp],
+            "rbc_build_timing": [h, dp, i64p],
             "rbc_energy": [h, dp],
             "rbc_stats": [h, i64p],
             "rbc_get_cells": [h, ip, dp],
@@ -294,6 +296,14 @@ class Context:
         avg = C.c_double(0.0)
         cnt = C.c_int64(0)
         _check(self._h, lib().rbc_force_timing(self._h, int(enable), C.byref(avg), C.byref(cnt)))
+        return avg.value, cnt.value
+
+    def build_timing(self):
+        """Average list-build kernel duration (ms) and launch count since the last call,
+        timed while force timing is on."""
+        avg = C.c_double(0.0)
+        cnt = C.c_int64(0)
+        _check(self._h, lib().rbc_build_timing(self._h, C.byref(avg), C.byref(cnt)))
         return avg.value, cnt.value
 
     def sync(self):

@@ -52,6 +52,7 @@ class ServeStats:
     particle_steps: int
     max_resident: int
     calls: int
+    host_us: Optional[np.ndarray] = None   # host time per step (decisions, launches) of each call
 
     def summary(self) -> dict:
         lat = self.step_latency
@@ -74,6 +75,8 @@ class ServeStats:
             "busy_s": self.busy,
             "max_resident": self.max_resident,
             "calls": self.calls,
+            "host_us_per_step_mean": float(np.mean(self.host_us)) if self.host_us is not None and
+            self.host_us.size else None,
         }
 
 
@@ -100,6 +103,8 @@ def serve(requests: List[dict], systems: Dict[int, object], executor, dt: float 
     first_arrival = pending[0]["arrival"] if pending else 0.0
     two_phase = hasattr(executor, "stage") and hasattr(executor, "commit")
     timed = hasattr(executor, "step_times")
+    host_timed = hasattr(executor, "host_times")
+    host_us: List[float] = []
     if timed:
         executor.step_times(True)
     prev_resident: set = set()
@@ -163,6 +168,10 @@ def serve(requests: List[dict], systems: Dict[int, object], executor, dt: float 
         te = clock()
         calls += 1
         busy += te - ts
+        if host_timed:
+            hu = executor.host_times()[0]
+            if hu >= 0:
+                host_us.append(hu)
         for slot, status in frozen.items():     # slots frozen by an error in this call
             if slot in live:
                 rec = live.pop(slot)
@@ -201,4 +210,5 @@ def serve(requests: List[dict], systems: Dict[int, object], executor, dt: float 
     wall = (max(r.done for r in results) - first_arrival) if results else 0.0
     lat = np.concatenate(lat_chunks) if lat_chunks else np.zeros(0)
     cl = np.concatenate(call_chunks) if call_chunks else np.zeros(0)
-    return ServeStats(sorted(results, key=lambda r: r.req_id), lat, cl, wall, busy, psteps, max_res, calls)
+    return ServeStats(sorted(results, key=lambda r: r.req_id), lat, cl, wall, busy, psteps, max_res, calls,
+                      np.asarray(host_us) if host_timed else None)
