@@ -1070,7 +1070,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
 // patterns); the last one publishes the result.  swap: after the drift fused into
 // the force kernel, which wrote the second position / orientation buffers; the last
 // block swaps them in.
-constexpr int STATS_BLOCKS = 16;
+constexpr int STATS_BLOCKS = 64;
 
 __global__ __launch_bounds__(256) void k_stats_reduce(SysDev *Sd, int nsys, int swap) {
     SysDev &S = Sd[blockIdx.x / STATS_BLOCKS];
