@@ -47,9 +47,9 @@ PEAK_HBM = 8000.0           # GB/s
 # HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
 # skin 0.5: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
-FORCE_TRAFFIC = {"sources_sha256": "76155b89d5fd69fd", "skin": 0.5, "inner_skin": None,
-                 "bytes": 2521082635, "fetch_kib": 955267, "write_kib": 551460,
-                 "valu_insts": 278759823}   # SQ_INSTS_VALU per launch (wavefront instructions)
+FORCE_TRAFFIC = {"sources_sha256": "e734966e6845956f", "skin": 0.6, "inner_skin": 0.15,
+                 "bytes": 2260542453, "fetch_kib": 796893, "write_kib": 613775,
+                 "valu_insts": 199351233}   # SQ_INSTS_VALU per launch (wavefront instructions)
 BYTES_BUILD_READ = 25       # list build: position (3 x 8 B) and type (1 B) of every particle, read once
 CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
