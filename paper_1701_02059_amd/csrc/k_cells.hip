@@ -117,16 +117,16 @@ __device__ void pack_one(const SysDev &S, const double *x, const double *n, cons
     S.pos[i] = p;
     S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
     S.xp[i] = S.xb[i];
-    S.vel[i] = D4{v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0};
+    S.vel[i] = V3{v[3 * i], v[3 * i + 1], v[3 * i + 2]};
     if (t == 0) {
-        S.ori[i] = D4{n[3 * i], n[3 * i + 1], n[3 * i + 2], 0.0};
-        S.angv[i] = D4{w[3 * i], w[3 * i + 1], w[3 * i + 2], 0.0};
+        S.ori[i] = V3{n[3 * i], n[3 * i + 1], n[3 * i + 2]};
+        S.angv[i] = V3{w[3 * i], w[3 * i + 1], w[3 * i + 2]};
     } else {
-        S.ori[i] = D4{0.0, 0.0, 0.0, 0.0};
-        S.angv[i] = D4{0.0, 0.0, 0.0, 0.0};
+        S.ori[i] = V3{0.0, 0.0, 0.0};
+        S.angv[i] = V3{0.0, 0.0, 0.0};
     }
-    S.frc[i] = D4{0.0, 0.0, 0.0, 0.0};
-    S.trq[i] = D4{0.0, 0.0, 0.0, 0.0};
+    S.frc[i] = V3{0.0, 0.0, 0.0};
+    S.trq[i] = V3{0.0, 0.0, 0.0};
     S.gid[i] = i;
     S.slot[i] = i;
     S.owner[i] = -1;
@@ -711,11 +711,11 @@ __global__ void k_swap_state(SysDev *Sd, int nsys) {
     if (s >= nsys) return;
     SysDev &S = Sd[s];
     if (S.n <= 0 || !S.sc->rebuild) return;
-    D4 *t;
-    t = S.pos; S.pos = S.pos2; S.pos2 = t;
-    t = S.vel; S.vel = S.vel2; S.vel2 = t;
-    t = S.ori; S.ori = S.ori2; S.ori2 = t;
-    t = S.angv; S.angv = S.angv2; S.angv2 = t;
+    D4 *t = S.pos; S.pos = S.pos2; S.pos2 = t;
+    V3 *u;
+    u = S.vel; S.vel = S.vel2; S.vel2 = u;
+    u = S.ori; S.ori = S.ori2; S.ori2 = u;
+    u = S.angv; S.angv = S.angv2; S.angv2 = u;
     int32_t *g = S.gid; S.gid = S.gid2; S.gid2 = g;
 }
 
@@ -1796,7 +1796,7 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
         const D4 p = S.pos[i];
         S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
         S.xp[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
-        const D4 o = S.ori[i];
+        const V3 o = S.ori[i];
         S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, 0.0f};
     }
 }

@@ -426,7 +426,7 @@ __device__ __forceinline__ void publish_split(SysDev &W, int nwg, double disp2, 
 
 __device__ __forceinline__ void swap_drift(SysDev &W) {
     D4 *t = W.pos; W.pos = W.pos2; W.pos2 = t;
-    t = W.ori; W.ori = W.ori2; W.ori2 = t;
+    V3 *u = W.ori; W.ori = W.ori2; W.ori2 = u;
     F4 *f = W.ori32; W.ori32 = W.ori32b; W.ori32b = f;
 }
 
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             const F4 o = ldg(S.ori32 + slot);
             s_n4[q] = F4{o.x, o.y, o.z, __int_as_float((int)p.w)};
         } else {
-            const D4 o = S.ori[slot];
+            const V3 o = S.ori[slot];
             s_nx[q] = o.x;
             s_ny[q] = o.y;
             s_nz[q] = o.z;
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     __syncthreads();
     if (chunk >= S.nchunk) return;
     const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
-    const D4 ni = valid ? ldg(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
+    const D4 ni = valid ? ld3(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
     const int ti = (int)pi.w;
     const T nix = (T)ni.x, niy = (T)ni.y, niz = (T)ni.z;
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
@@ -768,7 +768,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 if (e >= nlds && e < scnt) {
                     const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + e);
                     const D4 p = ldg(S.pos + slot);
-                    const D4 o = ldg(S.ori + slot);
+                    const V3 o = ldg(S.ori + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
                     c.nx = o.x; c.ny = o.y; c.nz = o.z;
                     c.t = (int)p.w;
@@ -852,7 +852,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             T ax = 0, ay = 0, az = 0;
             T u;
             if ((ti | tj) == 0) {
-                const D4 nj = S.ori[j];
+                const V3 nj = S.ori[j];
                 u = lipid_pair<T, FAST>(P, (T)dx, (T)dy, (T)dz, nix, niy, niz, (T)nj.x, (T)nj.y, (T)nj.z, ax, ay, az,
                                         tx, ty, tz);
             } else {
@@ -921,11 +921,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         }
         if (P.vol_on && ti == 0) volume_term(S.sc, pi, ni, Fx, Fy, Fz, Tq);
         if (KICK != 2) {
-            S.frc[i] = D4{Fx, Fy, Fz, 0.0};
-            S.trq[i] = Tq;
+            S.frc[i] = V3{Fx, Fy, Fz};
+            st3(S.trq + i, Tq);
         }
-        v = S.vel[i];
-        w = S.angv[i];
+        v = ld3(S.vel + i);
+        w = ld3(S.angv + i);
         if (KICK) {
             const double h = 0.5 * dt * P.inv_mass[ti];
             const double hw = 0.5 * dt * P.inv_inertia;
@@ -937,23 +937,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 if (ti == 0) project_along(w, Tq.x, Tq.y, Tq.z);
             }
             if (KICK == 1) {
-                S.vel[i] = v;
-                if (ti == 0) S.angv[i] = w;
+                st3(S.vel + i, v);
+                if (ti == 0) st3(S.angv + i, w);
             } else {
                 D4 vn = v, wn = w, xn = pi;
                 half_kick(vn, h, Fx, Fy, Fz);
                 if (P.quench_on) cap_move(vn, dt, P.quench_max);
                 drift_pos(xn, vn, dt);
-                S.vel[i] = vn;
+                st3(S.vel + i, vn);
                 S.pos2[i] = xn;
                 D4 on = ni;
                 if (ti == 0) {
                     half_kick(wn, hw, Tq.x, Tq.y, Tq.z);
                     if (P.quench_on) cap_move(wn, dt, P.quench_max);
-                    S.angv[i] = wn;
+                    st3(S.angv + i, wn);
                     on = rotor_drift(ni, wn, dt);
                 }
-                S.ori2[i] = on;
+                st3(S.ori2 + i, on);
                 S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
                 drift_measures(xn, vn, S.xb[i], S.xp[i], disp2, disp2p, vmax2, bad);
                 if (P.vol_on && ti == 0) volume_terms(xn, on, vsum);
@@ -1036,24 +1036,24 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
     bool bad = false;
     double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
-        D4 p = S.pos[i], v = S.vel[i];
-        const D4 f = S.frc[i];
+        D4 p = S.pos[i], v = ld3(S.vel + i);
+        const D4 f = ld3(S.frc + i);
         const int t = (int)p.w;
         const double h = 0.5 * dt * P.inv_mass[t];
         half_kick(v, h, f.x, f.y, f.z);
         if (P.quench_on) cap_move(v, dt, P.quench_max);
         drift_pos(p, v, dt);
-        S.vel[i] = v;
+        st3(S.vel + i, v);
         S.pos[i] = p;
         if (t == 0) {
-            D4 w = S.angv[i];
-            const D4 tq = S.trq[i];
+            D4 w = ld3(S.angv + i);
+            const D4 tq = ld3(S.trq + i);
             const double hw = 0.5 * dt * P.inv_inertia;
             half_kick(w, hw, tq.x, tq.y, tq.z);
             if (P.quench_on) cap_move(w, dt, P.quench_max);
-            const D4 n = rotor_drift(S.ori[i], w, dt);
-            S.angv[i] = w;
-            S.ori[i] = n;
+            const D4 n = rotor_drift(ld3(S.ori + i), w, dt);
+            st3(S.angv + i, w);
+            st3(S.ori + i, n);
             S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
             if (P.vol_on) volume_terms(p, n, vsum);
         }
@@ -1160,7 +1160,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume_partials(const SysDev *Sd, Map
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
         const D4 p = S.pos[i];
-        if (p.w == 0.0) volume_terms(p, S.ori[i], v);
+        if (p.w == 0.0) volume_terms(p, ld3(S.ori + i), v);
     }
     volume_chunk_store(S, i / CHUNK, v);
 }
@@ -1238,9 +1238,9 @@ __global__ void k_scatter_state(const SysDev *Sd, int s, double *x, double *n, d
     if (i >= S.n) return;
     const int g = S.gid[i];
     if (x) { D4 p = S.pos[i]; x[3 * g] = p.x; x[3 * g + 1] = p.y; x[3 * g + 2] = p.z; }
-    if (n) { D4 p = S.ori[i]; n[3 * g] = p.x; n[3 * g + 1] = p.y; n[3 * g + 2] = p.z; }
-    if (v) { D4 p = S.vel[i]; v[3 * g] = p.x; v[3 * g + 1] = p.y; v[3 * g + 2] = p.z; }
-    if (w) { D4 p = S.angv[i]; w[3 * g] = p.x; w[3 * g + 1] = p.y; w[3 * g + 2] = p.z; }
+    if (n) { V3 p = S.ori[i]; n[3 * g] = p.x; n[3 * g + 1] = p.y; n[3 * g + 2] = p.z; }
+    if (v) { V3 p = S.vel[i]; v[3 * g] = p.x; v[3 * g + 1] = p.y; v[3 * g + 2] = p.z; }
+    if (w) { V3 p = S.angv[i]; w[3 * g] = p.x; w[3 * g + 1] = p.y; w[3 * g + 2] = p.z; }
 }
 
 void launch_scatter_state(const LaunchCtx &L, int sys, double *x, double *n, double *v, double *w, int count) {
@@ -1253,8 +1253,8 @@ __global__ void k_scatter_forces(const SysDev *Sd, int s, double *F, double *T) 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.n) return;
     const int g = S.gid[i];
-    if (F) { D4 p = S.frc[i]; F[3 * g] = p.x; F[3 * g + 1] = p.y; F[3 * g + 2] = p.z; }
-    if (T) { D4 p = S.trq[i]; T[3 * g] = p.x; T[3 * g + 1] = p.y; T[3 * g + 2] = p.z; }
+    if (F) { V3 p = S.frc[i]; F[3 * g] = p.x; F[3 * g + 1] = p.y; F[3 * g + 2] = p.z; }
+    if (T) { V3 p = S.trq[i]; T[3 * g] = p.x; T[3 * g + 1] = p.y; T[3 * g + 2] = p.z; }
 }
 
 void launch_scatter_forces(const LaunchCtx &L, int sys, double *F, double *T, int count) {

@@ -34,6 +34,14 @@ struct alignas(16) D4 {
     double x, y, z, w;
 };
 
+// A 3-vector of doubles as stored in the particle arrays that need no fourth
+// component (velocity, orientation, angular velocity, force, torque): 24 B, no
+// padding.  Kernels compute on D4 (ld3 / st3).
+struct V3 {
+    double x, y, z;
+};
+static_assert(sizeof(V3) == 24, "packed 3-vector");
+
 struct alignas(16) F4 {
     float x, y, z, w;
 };
@@ -91,10 +99,12 @@ struct SysDev {
     int32_t nsrcp;                                  // protein seed sources after the lipid ids in `lip`
     int32_t split;                                  // the step kernel spreads each chunk's rows over four waves
     double box[3];
-    D4 *pos, *vel, *ori, *angv, *frc, *trq;         // pos.w = particle type
+    D4 *pos;                                        // pos.w = particle type
+    V3 *vel, *ori, *angv, *frc, *trq;
     F4 *xb;                                         // positions at the last list build (FP32)
     F4 *xp;                                         // positions at the last prune (FP32)
-    D4 *pos2, *vel2, *ori2, *angv2;
+    D4 *pos2;
+    V3 *vel2, *ori2, *angv2;
     int32_t *gid, *gid2, *slot, *owner;
     uint64_t *key, *key2;
     uint32_t *val, *val2;
@@ -258,6 +268,22 @@ __device__ __forceinline__ D4 ldg(const D4 *p) {
     typedef double v4d __attribute__((ext_vector_type(4)));
     const v4d v = *(const __attribute__((address_space(1))) v4d *)p;
     return D4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ V3 ldg(const V3 *p) {
+    typedef const __attribute__((address_space(1))) double *gp;
+    const gp q = (gp)p;
+    return V3{q[0], q[1], q[2]};
+}
+__device__ __forceinline__ D4 ld3(const V3 *p) {
+    const V3 v = ldg(p);
+    return D4{v.x, v.y, v.z, 0.0};
+}
+__device__ __forceinline__ void st3(V3 *p, const D4 &v) {
+    typedef __attribute__((address_space(1))) double *gp;
+    const gp q = (gp)p;
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
 }
 __device__ __forceinline__ F4 ldg(const F4 *p) {
     typedef float v4f __attribute__((ext_vector_type(4)));
