@@ -901,6 +901,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     D4 Tq = {(double)tx, (double)ty, (double)tz, 0.0};
     double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (valid) {
+        // the own-state loads first, so that they are in flight during the bond lookups
+        if (KICK || ENERGY) {
+            v = ld3(S.vel + i);
+            w = ld3(S.angv + i);
+        }
+        const F4 xb = KICK == 2 ? ldg(S.xb + i) : F4{0.f, 0.f, 0.f, 0.f};
+        const F4 xp = KICK == 2 ? ldg(S.xp + i) : F4{0.f, 0.f, 0.f, 0.f};
         // bonds of this particle (CSR by caller id), FP64 in both modes
         const int g = S.gid[i];
         for (int q = S.bstart[g]; q < S.bstart[g + 1]; ++q) {
@@ -924,8 +931,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             S.frc[i] = V3{Fx, Fy, Fz};
             st3(S.trq + i, Tq);
         }
-        v = ld3(S.vel + i);
-        w = ld3(S.angv + i);
         if (KICK) {
             const double h = 0.5 * dt * P.inv_mass[ti];
             const double hw = 0.5 * dt * P.inv_inertia;
@@ -955,7 +960,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 }
                 st3(S.ori2 + i, on);
                 S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
-                drift_measures(xn, vn, S.xb[i], S.xp[i], disp2, disp2p, vmax2, bad);
+                drift_measures(xn, vn, xb, xp, disp2, disp2p, vmax2, bad);
                 if (P.vol_on && ti == 0) volume_terms(xn, on, vsum);
             }
         }
