@@ -324,7 +324,7 @@ def main():
     ap.add_argument("--detached-steps", type=int, default=500)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
-    ap.add_argument("--skin", type=float, default=0.6,
+    ap.add_argument("--skin", type=float, default=0.65,
                     help="Verlet skin of the full lists (sigma); measured optimum for the whole cell")
     ap.add_argument("--inner-skin", type=float, default=0.15,
                     help="buffer of the pruned lists the step kernel walks (sigma)")

@@ -515,7 +515,7 @@ void lists_body(rbc_ctx *h, const LaunchCtx &L) {
 // The status and message of one slot's error bits.
 rbc_status slot_error(rbc_ctx *h, int s, int e) {
     if (e & ERR_NONFINITE) return fail(h, RBC_ERR_NONFINITE, "non-finite positions or velocities in slot " + std::to_string(s));
-    if (e & ERR_NLIST) return fail(h, RBC_ERR_CAPACITY, "a particle has more than 64 neighbours within rc + 2 skin (slot " + std::to_string(s) + ")");
+    if (e & ERR_NLIST) return fail(h, RBC_ERR_CAPACITY, "a particle has more than " + std::to_string(MAXNB) + " neighbours within rc + 2 skin (slot " + std::to_string(s) + ")");
     if (e & ERR_CNBR) return fail(h, RBC_ERR_CAPACITY, "cell-pair list capacity exceeded (slot " + std::to_string(s) + ")");
     if (e & ERR_ASSIGN) return fail(h, RBC_ERR_CAPACITY, "nearest-seed search failed (slot " + std::to_string(s) + ")");
     return RBC_OK;

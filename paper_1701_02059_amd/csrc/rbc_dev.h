@@ -9,7 +9,7 @@ namespace rbc {
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;            // threads per block for particle / cell kernels
 constexpr int CHUNK = 64;             // particles per neighbour-list chunk (one wavefront)
-constexpr int MAXNB = 64;             // neighbour-list rows per chunk
+constexpr int MAXNB = 96;             // neighbour-list rows per chunk
 constexpr int SORT_IPT = 16;          // items per thread in the radix sort
 constexpr int SORT_TILE = BLOCK * SORT_IPT;
 constexpr int MAX_SLOTS = 256;

@@ -28,7 +28,7 @@ pytestmark = pytest.mark.gpu
 DT = 0.01
 FP64_TOL = 1e-10
 MIXED_TOL = 1e-5
-SKIN, INNER = 0.6, 0.15   # the benchmark's skins for the whole-cell workload
+SKIN, INNER = 0.65, 0.15  # the benchmark's skins for the whole-cell workload
 
 
 @pytest.fixture(scope="module")

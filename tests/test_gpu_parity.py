@@ -362,7 +362,7 @@ def test_ensemble_failed_admission_leaves_others(R, mp):
     disturbing the resident ones: the slot is released and the other trajectory is
     bitwise the one it has alone."""
     import dataclasses
-    mp5 = dataclasses.replace(mp, skin=0.5)        # the dense cloud then has up to 80 list partners
+    mp5 = dataclasses.replace(mp, skin=0.9)        # the dense cloud then has up to 140 list partners
     good = I.build_request({"kind": "patch", "nL": 2500, "seed": 21})
     alone = R.Ensemble(mp5, R.RBC_MIXED, max_slots=4)
     sa = alone.admit(good)
@@ -444,7 +444,7 @@ def test_ensemble_staged_admission_equals_admit(R, mp):
     one by one; a staged system whose build fails (list overflow) is released and
     listed while the others go on; stepping waits for the commit."""
     import dataclasses
-    mp5 = dataclasses.replace(mp, skin=0.5)
+    mp5 = dataclasses.replace(mp, skin=0.9)        # the dense cloud's lists then overflow
     systems = [I.build_request({"kind": "patch", "nL": 2500, "seed": 71}),
                I.build_request({"kind": "vesicle", "nL": 4000, "seed": 72}),
                I.build_request({"kind": "vesicle", "nL": 9000, "seed": 73})]
