@@ -571,21 +571,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const bool valid = i < S.n;
     const int scnt = __builtin_amdgcn_readfirstlane(S.iscount[lb]);
     const int nlds = min(scnt, SL);                 // stage entries held in LDS
-    for (int q = tid; q < nlds; q += BLOCK) {
-        const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + q);
-        const D4 p = ldg(S.pos + slot);
-        s_x[q] = p.x;
-        s_y[q] = p.y;
-        s_z[q] = p.z;
-        if constexpr (MIXED) {
-            const F4 o = ldg(S.ori32 + slot);
-            s_n4[q] = F4{o.x, o.y, o.z, __int_as_float((int)p.w)};
-        } else {
-            const V3 o = S.ori[slot];
-            s_nx[q] = o.x;
-            s_ny[q] = o.y;
-            s_nz[q] = o.z;
-            s_t[q] = (unsigned char)p.w;
+    // this lane's own particle, loaded while the stage is read
+    const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
+    const D4 ni = valid ? ld3(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
+    // the stage: every thread's (at most three) slots first, then their records
+    constexpr int SPT = (SL + BLOCK - 1) / BLOCK;
+    for (int q0 = tid; q0 < nlds; q0 += SPT * BLOCK) {
+        int slot[SPT];
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int q = q0 + k * BLOCK;
+            slot[k] = q < nlds ? ldg(S.istage + (size_t)lb * SSTRIDE + q) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int q = q0 + k * BLOCK;
+            if (slot[k] < 0) break;
+            const D4 p = ldg(S.pos + slot[k]);
+            s_x[q] = p.x;
+            s_y[q] = p.y;
+            s_z[q] = p.z;
+            if constexpr (MIXED) {
+                const F4 o = ldg(S.ori32 + slot[k]);
+                s_n4[q] = F4{o.x, o.y, o.z, __int_as_float((int)p.w)};
+            } else {
+                const V3 o = S.ori[slot[k]];
+                s_nx[q] = o.x;
+                s_ny[q] = o.y;
+                s_nz[q] = o.z;
+                s_t[q] = (unsigned char)p.w;
+            }
         }
     }
     if (MIXED && tid == 0) {
@@ -596,8 +611,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
     __syncthreads();
     if (chunk >= S.nchunk) return;
-    const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
-    const D4 ni = valid ? ld3(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
     const int ti = (int)pi.w;
     const T nix = (T)ni.x, niy = (T)ni.y, niz = (T)ni.z;
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
