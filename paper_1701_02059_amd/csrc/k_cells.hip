@@ -1631,7 +1631,9 @@ void launch_nlist(const LaunchCtx &L) {
 // since the prune.
 __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, DevParams P) {
     SYS_FROM(p);
-    __shared__ F4 s_o[SMAX];
+    // stage offsets, 12 B each: the type rides in the two low mantissa bits of x (a
+    // change of at most three ulp, far inside the 1e-3 sigma widening of the radius)
+    __shared__ F3 s_o[SMAX];
     __shared__ __align__(16) unsigned char s_flag[SMAX];   // stage entry kept by some lane (plain stores of 1)
     __shared__ unsigned s_bits[SMAX / 32];
     __shared__ int s_pre[SMAX / 32];
@@ -1672,7 +1674,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
             const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
             const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
             const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
-            s_o[q] = F4{ox, oy, oz, __int_as_float((int)pj.w & 3)};
+            s_o[q] = F3{__int_as_float((__float_as_int(ox) & ~3) | ((int)pj.w & 3)), oy, oz};
             far = far || !(fabsf(ox) <= LIST_EXTENT && fabsf(oy) <= LIST_EXTENT && fabsf(oz) <= LIST_EXTENT);
         }
     }
@@ -1703,7 +1705,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
 #pragma unroll
             for (int q = 0; q < BATCH; ++q) {
                 const int eq = (r0 + q < rows) ? e[q] : 0xffff;
-                const F4 c = s_o[eq < scnt ? eq : 0];
+                const F3 c = s_o[eq < scnt ? eq : 0];
                 float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
                 if (periodic) {
                     dx -= Lx * rintf(dx * iLx);
@@ -1711,7 +1713,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
                     dz -= Lz * rintf(dz * iLz);
                 }
                 const float d2 = dx * dx + dy * dy + dz * dz;
-                const float rr = sel3f(__float_as_int(c.w), rA, rB, rC);
+                const float rr = sel3f(__float_as_int(c.x) & 3, rA, rB, rC);
                 if (eq < scnt && (keep_all || d2 < rr)) {
                     stg(icol + cnt * CHUNK, (uint16_t)eq);
                     ++cnt;

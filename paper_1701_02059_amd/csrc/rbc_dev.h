@@ -46,6 +46,10 @@ struct alignas(16) F4 {
     float x, y, z, w;
 };
 
+struct F3 {
+    float x, y, z;
+};
+
 // Per-system scalars living in device memory.
 struct alignas(256) SysScal {
     unsigned long long maxdisp2;      // bits of the largest |x - x_build|^2 since the last build
