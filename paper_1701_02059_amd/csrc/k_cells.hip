@@ -114,7 +114,8 @@ __device__ void pack_one(const SysDev &S, const double *x, const double *n, cons
     if (i >= S.n) return;
     const int t = type[i];
     D4 p = {x[3 * i], x[3 * i + 1], x[3 * i + 2], (double)t};
-    S.pos[i] = p;
+    S.pos[i] = V3{p.x, p.y, p.z};
+    S.typ[i] = (uint8_t)t;
     S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
     S.xp[i] = S.xb[i];
     S.vel[i] = V3{v[3 * i], v[3 * i + 1], v[3 * i + 2]};
@@ -152,7 +153,7 @@ __global__ void k_init_seeds(const SysDev *Sd, Maps L_maps, const int32_t *const
         if (c < S.kl) j = (long long)c * S.nlip / S.kl;
         else j = S.nlip + (long long)(c - S.kl) * S.nsrcp / (S.k - S.kl);
         int g = lipids[s][j];
-        D4 p = S.pos[S.slot[g]];
+        D4 p = ld3(S.pos + S.slot[g]);
         p.x = wrap_coord(p.x, S.per[0], S.box[0]);
         p.y = wrap_coord(p.y, S.per[1], S.box[1]);
         p.z = wrap_coord(p.z, S.per[2], S.box[2]);
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(BLOCK) void k_bbox_partial(const SysDev *Sd, Maps L
     const int i = lb * BLOCK + threadIdx.x;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     if (i < S.n) {
-        D4 p = S.pos[i];
+        D4 p = ld3(S.pos + i);
         double v[3] = {wrap_coord(p.x, S.per[0], S.box[0]), wrap_coord(p.y, S.per[1], S.box[1]),
                        wrap_coord(p.z, S.per[2], S.box[2])};
         for (int a = 0; a < 3; ++a) { mn[a] = v[a]; mx[a] = v[a]; }
@@ -543,7 +544,7 @@ __global__ void k_assign(const SysDev *Sd, Maps L_maps, int warm) {
     if (!S.sc->rebuild) return;
     int i = lb * BLOCK + threadIdx.x;
     if (i >= S.n) return;
-    D4 p = S.pos[i];
+    D4 p = ldpos(S, i);
     double d2;
     // lipids search cells [0, kl), protein beads [kl, k) (all cells when kl == k)
     const bool lipid_set = (p.w == 0.0) || S.kl == S.k;
@@ -681,6 +682,7 @@ __global__ void k_gather(const SysDev *Sd, Maps L_maps) {
     if (j >= S.n) return;
     int src = (int)S.val[j];
     S.pos2[j] = S.pos[src];
+    S.typ2[j] = S.typ[src];
     S.vel2[j] = S.vel[src];
     S.ori2[j] = S.ori[src];
     S.angv2[j] = S.angv[src];
@@ -694,6 +696,7 @@ __global__ void k_commit(const SysDev *Sd, Maps L_maps, int mode) {
     int j = lb * BLOCK + threadIdx.x;
     if (j >= S.n) return;
     S.pos[j] = S.pos2[j];
+    S.typ[j] = S.typ2[j];
     S.vel[j] = S.vel2[j];
     S.ori[j] = S.ori2[j];
     S.angv[j] = S.angv2[j];
@@ -711,8 +714,9 @@ __global__ void k_swap_state(SysDev *Sd, int nsys) {
     if (s >= nsys) return;
     SysDev &S = Sd[s];
     if (S.n <= 0 || !S.sc->rebuild) return;
-    D4 *t = S.pos; S.pos = S.pos2; S.pos2 = t;
     V3 *u;
+    u = S.pos; S.pos = S.pos2; S.pos2 = u;
+    uint8_t *y = S.typ; S.typ = S.typ2; S.typ2 = y;
     u = S.vel; S.vel = S.vel2; S.vel2 = u;
     u = S.ori; S.ori = S.ori2; S.ori2 = u;
     u = S.angv; S.angv = S.angv2; S.angv2 = u;
@@ -784,7 +788,7 @@ __global__ void k_mstep(const SysDev *Sd, Maps L_maps) {
     const bool lipid_cell = c < S.kl;
     int b = S.cstart[c], e = b + S.ccount[c];
     for (int i = b; i < e; ++i) {
-        D4 p = S.pos[i];
+        D4 p = ldpos(S, i);
         if ((p.w == 0.0) != lipid_cell) continue;
         double dx, dy, dz;
         (void)dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz);
@@ -893,6 +897,7 @@ __global__ void k_block_permute(const SysDev *Sd, Maps L_maps) {
     int cn = S.cmap[c];
     int dst = S.cstart2[cn] + (j - S.cstart[c]);
     S.pos2[dst] = S.pos[j];
+    S.typ2[dst] = S.typ[j];
     S.vel2[dst] = S.vel[j];
     S.ori2[dst] = S.ori[j];
     S.angv2[dst] = S.angv[j];
@@ -929,7 +934,7 @@ __global__ void k_cell_bounds(const SysDev *Sd, Maps L_maps) {
         double r2 = 0.0;
         int b = S.cstart[c], e = b + S.ccount[c];
         for (int i = b; i < e; ++i) {
-            D4 p = S.pos[i];
+            D4 p = ld3(S.pos + i);
             double dx, dy, dz;
             r2 = fmax(r2, dist2_exact(S, p.x, p.y, p.z, sd.x, sd.y, sd.z, dx, dy, dz));
         }
@@ -1340,8 +1345,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
     // cell (s_kofs: each candidate cell's first stage entry), with the candidate cells'
     // centroids and radii (widened by 2e-3 sigma for the offsets' rounding)
     const bool cull = nsc <= CULLMAX;
-    const D4 ref = ldg(S.pos + first);
-    const D4 pi = valid ? S.pos[i] : ref;
+    const D4 ref = ld3(S.pos + first);
+    const D4 pi = valid ? ldpos(S, i) : ref;
     float oi[3] = {(float)minimg1(pi.x - ref.x, S.per[0], S.box[0]), (float)minimg1(pi.y - ref.y, S.per[1], S.box[1]),
                    (float)minimg1(pi.z - ref.z, S.per[2], S.box[2])};
     if (!valid) oi[0] = oi[1] = oi[2] = 0.0f;
@@ -1396,7 +1401,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
             if (u < ss) {
                 c = union_cell(s_ofs, nsc + 1, u);
                 const int slot = ldg(S.cstart + s_cand[c]) + (u - s_ofs[c]);
-                const D4 pj = ldg(S.pos + slot);
+                const D4 pj = ldpos(S, slot);
                 const float o[3] = {(float)minimg1(pj.x - ref.x, S.per[0], S.box[0]),
                                     (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]),
                                     (float)minimg1(pj.z - ref.z, S.per[2], S.box[2])};
@@ -1528,7 +1533,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
             int b = ldg(S.cstart + B), e = b + ldg(S.ccount + B);
             for (int j = b; j < e; ++j) {
                 if (j == i) continue;
-                D4 pj = ldg(S.pos + j);
+                D4 pj = ldpos(S, j);
                 double dx, dy, dz;
                 double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
                 if (d2 < P.rl2[ti][(int)pj.w]) {
@@ -1645,7 +1650,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     const int i = lb * BLOCK + tid;
     const bool valid = i < S.n;
     if (lb == 0 && tid == 0) S.sc->maxdisp2p = 0ull;
-    const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
+    const D4 pi = valid ? ldpos(S, i) : D4{0.0, 0.0, 0.0, 0.0};
     if (valid) S.xp[i] = F4{(float)pi.x, (float)pi.y, (float)pi.z, 0.0f};
     const int scnt = S.scount[lb];
     const int rows = chunk_ok ? min(S.nlk[chunk], MAXNB) : 0;
@@ -1656,7 +1661,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     }
     if (tid == 0) s_big = 0;
     for (int w = tid; w < SMAX / 4; w += BLOCK) reinterpret_cast<unsigned *>(s_flag)[w] = 0u;
-    const D4 ref = ldg(S.pos + (size_t)lb * BLOCK);
+    const D4 ref = ld3(S.pos + (size_t)lb * BLOCK);
     bool far = false;
     // four entries per thread in flight: their slots, then their positions
     for (int q0 = tid; q0 < scnt; q0 += 4 * BLOCK) {
@@ -1670,7 +1675,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
         for (int k = 0; k < 4; ++k) {
             const int q = q0 + k * BLOCK;
             if (slot[k] < 0) break;
-            const D4 pj = ldg(S.pos + slot[k]);
+            const D4 pj = ldpos(S, slot[k]);
             const float ox = (float)minimg1(pj.x - ref.x, S.per[0], S.box[0]);
             const float oy = (float)minimg1(pj.y - ref.y, S.per[1], S.box[1]);
             const float oz = (float)minimg1(pj.z - ref.z, S.per[2], S.box[2]);
@@ -1795,11 +1800,11 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
     if (!S.sc->rebuild) return;
     int i = lb * BLOCK + threadIdx.x;
     if (i < S.n) {
-        const D4 p = S.pos[i];
+        const V3 p = S.pos[i];
         S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
         S.xp[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
         const V3 o = S.ori[i];
-        S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, 0.0f};
+        S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, __int_as_float((int)S.typ[i])};
     }
 }
 

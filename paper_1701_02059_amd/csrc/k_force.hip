@@ -425,8 +425,8 @@ __device__ __forceinline__ void publish_split(SysDev &W, int nwg, double disp2, 
 }
 
 __device__ __forceinline__ void swap_drift(SysDev &W) {
-    D4 *t = W.pos; W.pos = W.pos2; W.pos2 = t;
-    V3 *u = W.ori; W.ori = W.ori2; W.ori2 = u;
+    V3 *u = W.pos; W.pos = W.pos2; W.pos2 = u;
+    u = W.ori; W.ori = W.ori2; W.ori2 = u;
     F4 *f = W.ori32; W.ori32 = W.ori32b; W.ori32b = f;
 }
 
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int scnt = __builtin_amdgcn_readfirstlane(S.iscount[lb]);
     const int nlds = min(scnt, SL);                 // stage entries held in LDS
     // this lane's own particle, loaded while the stage is read
-    const D4 pi = valid ? ldg(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
+    const D4 pi = valid ? ldpos(S, i) : D4{0.0, 0.0, 0.0, 0.0};
     const D4 ni = valid ? ld3(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
     // the stage: every thread's (at most three) slots first, then their records
     constexpr int SPT = (SL + BLOCK - 1) / BLOCK;
@@ -587,19 +587,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         for (int k = 0; k < SPT; ++k) {
             const int q = q0 + k * BLOCK;
             if (slot[k] < 0) break;
-            const D4 p = ldg(S.pos + slot[k]);
+            const V3 p = ldg(S.pos + slot[k]);
             s_x[q] = p.x;
             s_y[q] = p.y;
             s_z[q] = p.z;
             if constexpr (MIXED) {
-                const F4 o = ldg(S.ori32 + slot[k]);
-                s_n4[q] = F4{o.x, o.y, o.z, __int_as_float((int)p.w)};
+                s_n4[q] = ldg(S.ori32 + slot[k]);       // w: the type's bits
             } else {
                 const V3 o = S.ori[slot[k]];
                 s_nx[q] = o.x;
                 s_ny[q] = o.y;
                 s_nz[q] = o.z;
-                s_t[q] = (unsigned char)p.w;
+                s_t[q] = ldg(S.typ + slot[k]);
             }
         }
     }
@@ -655,11 +654,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             if constexpr (PARTIAL) {
                 if (e >= nlds && e < scnt) {            // stage entry beyond the LDS part
                     const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + e);
-                    const D4 p = ldg(S.pos + slot);
+                    const V3 p = ldg(S.pos + slot);
                     const F4 o = ldg(S.ori32 + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
                     c.nx = o.x; c.ny = o.y; c.nz = o.z;
-                    c.t = (int)p.w;
+                    c.t = __float_as_int(o.w);
                     return c;
                 }
             }
@@ -780,11 +779,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             if constexpr (PARTIAL) {
                 if (e >= nlds && e < scnt) {
                     const int slot = ldg(S.istage + (size_t)lb * SSTRIDE + e);
-                    const D4 p = ldg(S.pos + slot);
+                    const V3 p = ldg(S.pos + slot);
                     const V3 o = ldg(S.ori + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
                     c.nx = o.x; c.ny = o.y; c.nz = o.z;
-                    c.t = (int)p.w;
+                    c.t = ldg(S.typ + slot);
                     return c;
                 }
             }
@@ -857,7 +856,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         for (int r = r0; r < rows; r += rstep) {
             const int j = valid ? col[r * CHUNK] : -1;
             if (j < 0 || j >= S.n) continue;
-            const D4 pj = S.pos[j];
+            const D4 pj = ldpos(S, j);
             const int tj = (int)pj.w;
             double dx, dy, dz;
             const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
@@ -925,7 +924,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         const int g = S.gid[i];
         for (int q = S.bstart[g]; q < S.bstart[g + 1]; ++q) {
             const int j = S.slot[S.bpart[q]];
-            const D4 pj = S.pos[j];
+            const D4 pj = ld3(S.pos + j);
             double dx, dy, dz;
             const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
             const double r = sqrt(d2);
@@ -963,7 +962,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 if (P.quench_on) cap_move(vn, dt, P.quench_max);
                 drift_pos(xn, vn, dt);
                 st3(S.vel + i, vn);
-                S.pos2[i] = xn;
+                st3(S.pos2 + i, xn);
                 D4 on = ni;
                 if (ti == 0) {
                     half_kick(wn, hw, Tq.x, Tq.y, Tq.z);
@@ -972,7 +971,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                     on = rotor_drift(ni, wn, dt);
                 }
                 st3(S.ori2 + i, on);
-                S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, 0.0f};
+                S.ori32b[i] = F4{(float)on.x, (float)on.y, (float)on.z, __int_as_float(ti)};
                 drift_measures(xn, vn, xb, xp, disp2, disp2p, vmax2, bad);
                 if (P.vol_on && ti == 0) volume_terms(xn, on, vsum);
             }
@@ -1054,7 +1053,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
     bool bad = false;
     double vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
-        D4 p = S.pos[i], v = ld3(S.vel + i);
+        D4 p = ldpos(S, i), v = ld3(S.vel + i);
         const D4 f = ld3(S.frc + i);
         const int t = (int)p.w;
         const double h = 0.5 * dt * P.inv_mass[t];
@@ -1062,7 +1061,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
         if (P.quench_on) cap_move(v, dt, P.quench_max);
         drift_pos(p, v, dt);
         st3(S.vel + i, v);
-        S.pos[i] = p;
+        st3(S.pos + i, p);
         if (t == 0) {
             D4 w = ld3(S.angv + i);
             const D4 tq = ld3(S.trq + i);
@@ -1072,7 +1071,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(const SysDev *Sd, Maps L_m
             const D4 n = rotor_drift(ld3(S.ori + i), w, dt);
             st3(S.angv + i, w);
             st3(S.ori + i, n);
-            S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, 0.0f};
+            S.ori32[i] = F4{(float)n.x, (float)n.y, (float)n.z, __int_as_float(t)};
             if (P.vol_on) volume_terms(p, n, vsum);
         }
         drift_measures(p, v, S.xb[i], S.xp[i], disp2, disp2p, v2, bad);
@@ -1177,7 +1176,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume_partials(const SysDev *Sd, Map
     if (i / CHUNK >= S.nchunk) return;           // whole wavefronts past the last chunk
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.n) {
-        const D4 p = S.pos[i];
+        const D4 p = ldpos(S, i);
         if (p.w == 0.0) volume_terms(p, ld3(S.ori + i), v);
     }
     volume_chunk_store(S, i / CHUNK, v);
@@ -1255,7 +1254,7 @@ __global__ void k_scatter_state(const SysDev *Sd, int s, double *x, double *n, d
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.n) return;
     const int g = S.gid[i];
-    if (x) { D4 p = S.pos[i]; x[3 * g] = p.x; x[3 * g + 1] = p.y; x[3 * g + 2] = p.z; }
+    if (x) { V3 p = S.pos[i]; x[3 * g] = p.x; x[3 * g + 1] = p.y; x[3 * g + 2] = p.z; }
     if (n) { V3 p = S.ori[i]; n[3 * g] = p.x; n[3 * g + 1] = p.y; n[3 * g + 2] = p.z; }
     if (v) { V3 p = S.vel[i]; v[3 * g] = p.x; v[3 * g + 1] = p.y; v[3 * g + 2] = p.z; }
     if (w) { V3 p = S.angv[i]; w[3 * g] = p.x; w[3 * g + 1] = p.y; w[3 * g + 2] = p.z; }
@@ -1303,7 +1302,7 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P, int32_t *ou
     D4 pi = {0, 0, 0, 0};
     int ti = 0, gi = 0, rows = 0, scnt = -1;
     if (valid) {
-        pi = S.pos[i];
+        pi = ldpos(S, i);
         ti = (int)pi.w;
         gi = S.gid[i];
         rows = min(S.ilk[chunk], MAXNB);
@@ -1330,7 +1329,7 @@ __global__ void k_export_pairs(const SysDev *Sd, int s, DevParams P, int32_t *ou
             if (j < 0 || j >= S.n) continue;
             const int gj = S.gid[j];
             if (gj <= gi) continue;
-            const D4 pj = S.pos[j];
+            const D4 pj = ldpos(S, j);
             double dx, dy, dz;
             const double d2 = dist2_exact(S, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
             if (d2 < P.rc2[ti][(int)pj.w]) {

@@ -262,9 +262,9 @@ size_t layout(HostSys &s, char *base) {
     const int64_t n = s.n;
     const int32_t k = s.k;
     SysDev &d = s.dev;
-    d.pos = c.take<D4>(n); d.vel = c.take<V3>(n); d.ori = c.take<V3>(n); d.angv = c.take<V3>(n);
+    d.pos = c.take<V3>(n); d.vel = c.take<V3>(n); d.ori = c.take<V3>(n); d.angv = c.take<V3>(n);
     d.frc = c.take<V3>(n); d.trq = c.take<V3>(n); d.xb = c.take<F4>(n); d.xp = c.take<F4>(n);
-    d.pos2 = c.take<D4>(n); d.vel2 = c.take<V3>(n); d.ori2 = c.take<V3>(n); d.angv2 = c.take<V3>(n);
+    d.pos2 = c.take<V3>(n); d.vel2 = c.take<V3>(n); d.ori2 = c.take<V3>(n); d.angv2 = c.take<V3>(n);
     d.gid = c.take<int32_t>(n); d.gid2 = c.take<int32_t>(n); d.slot = c.take<int32_t>(n);
     d.owner = c.take<int32_t>(n);
     d.key = c.take<uint64_t>(n); d.key2 = c.take<uint64_t>(n);
@@ -279,6 +279,7 @@ size_t layout(HostSys &s, char *base) {
     d.gpos = c.take<D4>(k);
     d.nl = c.take<int32_t>((size_t)s.nchunk * MAXNB * CHUNK); d.nlk = c.take<int32_t>(s.nchunk);
     d.nl16 = c.take<uint16_t>((size_t)s.nchunk * MAXNB * CHUNK);
+    d.typ = c.take<uint8_t>(n); d.typ2 = c.take<uint8_t>(n);
     d.ori32 = c.take<F4>(n);
     d.ori32b = c.take<F4>(n);
     d.bstart = c.take<int32_t>(n + 1); d.bpart = c.take<int32_t>(2 * s.nbond); d.br0 = c.take<double>(2 * s.nbond);

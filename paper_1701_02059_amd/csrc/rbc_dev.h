@@ -103,11 +103,13 @@ struct SysDev {
     int32_t nsrcp;                                  // protein seed sources after the lipid ids in `lip`
     int32_t split;                                  // the step kernel spreads each chunk's rows over four waves
     double box[3];
-    D4 *pos;                                        // pos.w = particle type
+    V3 *pos;
+    uint8_t *typ;                                   // particle type (0 lipid, 1 junction, 2 spectrin)
     V3 *vel, *ori, *angv, *frc, *trq;
     F4 *xb;                                         // positions at the last list build (FP32)
     F4 *xp;                                         // positions at the last prune (FP32)
-    D4 *pos2;
+    V3 *pos2;
+    uint8_t *typ2;
     V3 *vel2, *ori2, *angv2;
     int32_t *gid, *gid2, *slot, *owner;
     uint64_t *key, *key2;
@@ -120,7 +122,7 @@ struct SysDev {
     D4 *gpos;                                       // centroids in grid order, w = seed index (k)
     int32_t *nl, *nlk;                              // neighbour lists (nchunk x MAXNB x 64), rows
     uint16_t *nl16;                                 // the same lists as stage indices (staged blocks)
-    F4 *ori32;                                      // FP32 copy of the orientations (mixed-mode staging)
+    F4 *ori32;                                      // FP32 copy of the orientations, w = type bits (staging)
     F4 *ori32b;                                     // its second buffer (fused drift target; pos2 / ori2 likewise)
     int32_t *bstart, *bpart;                        // bonds by caller id (n+1, 2 nbond)
     double *br0;
@@ -281,6 +283,11 @@ __device__ __forceinline__ V3 ldg(const V3 *p) {
 __device__ __forceinline__ D4 ld3(const V3 *p) {
     const V3 v = ldg(p);
     return D4{v.x, v.y, v.z, 0.0};
+}
+// a particle's position with its type in w
+__device__ __forceinline__ D4 ldpos(const SysDev &S, int i) {
+    const V3 p = ldg(S.pos + i);
+    return D4{p.x, p.y, p.z, (double)ldg(S.typ + i)};
 }
 __device__ __forceinline__ void st3(V3 *p, const D4 &v) {
     typedef __attribute__((address_space(1))) double *gp;
