@@ -115,8 +115,8 @@ __device__ void pack_one(const SysDev &S, const double *x, const double *n, cons
     const int t = type[i];
     D4 p = {x[3 * i], x[3 * i + 1], x[3 * i + 2], (double)t};
     S.pos[i] = V3{p.x, p.y, p.z};
-    S.typ[i] = (uint8_t)t;
-    S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
+    S.typ[i] = (uint8_t)(t | (S.bstart[i + 1] > S.bstart[i] ? TYP_BONDED : 0));   // bonds by caller id = i
+    S.xb[i] = F3{(float)p.x, (float)p.y, (float)p.z};
     S.xp[i] = S.xb[i];
     S.vel[i] = V3{v[3 * i], v[3 * i + 1], v[3 * i + 2]};
     if (t == 0) {
@@ -1651,7 +1651,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     const bool valid = i < S.n;
     if (lb == 0 && tid == 0) S.sc->maxdisp2p = 0ull;
     const D4 pi = valid ? ldpos(S, i) : D4{0.0, 0.0, 0.0, 0.0};
-    if (valid) S.xp[i] = F4{(float)pi.x, (float)pi.y, (float)pi.z, 0.0f};
+    if (valid) S.xp[i] = F3{(float)pi.x, (float)pi.y, (float)pi.z};
     const int scnt = S.scount[lb];
     const int rows = chunk_ok ? min(S.nlk[chunk], MAXNB) : 0;
     if (scnt < 0) {
@@ -1801,10 +1801,10 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
     int i = lb * BLOCK + threadIdx.x;
     if (i < S.n) {
         const V3 p = S.pos[i];
-        S.xb[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
-        S.xp[i] = F4{(float)p.x, (float)p.y, (float)p.z, 0.0f};
+        S.xb[i] = F3{(float)p.x, (float)p.y, (float)p.z};
+        S.xp[i] = F3{(float)p.x, (float)p.y, (float)p.z};
         const V3 o = S.ori[i];
-        S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, __int_as_float((int)S.typ[i])};
+        S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, __int_as_float((int)S.typ[i] & TYP_MASK)};
     }
 }
 

@@ -210,7 +210,7 @@ __device__ __forceinline__ void drift_pos(D4 &x, const D4 &v, double dt) {
 // Displacements since the last list build and since the last prune, measured
 // against FP32 copies of the reference positions (their rounding, below 6e-5 sigma for
 // coordinates under 1000 sigma, is covered by the runtime's margins).
-__device__ __forceinline__ void drift_measures(const D4 &x, const D4 &v, const F4 &b, const F4 &p, double &disp2,
+__device__ __forceinline__ void drift_measures(const D4 &x, const D4 &v, const F3 &b, const F3 &p, double &disp2,
                                                double &disp2p, double &v2, bool &bad) {
 #pragma clang fp contract(off)
     const double ddx = x.x - (double)b.x, ddy = x.y - (double)b.y, ddz = x.z - (double)b.z;
@@ -572,7 +572,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int scnt = __builtin_amdgcn_readfirstlane(S.iscount[lb]);
     const int nlds = min(scnt, SL);                 // stage entries held in LDS
     // this lane's own particle, loaded while the stage is read
-    const D4 pi = valid ? ldpos(S, i) : D4{0.0, 0.0, 0.0, 0.0};
+    const int traw = valid ? ldg(S.typ + i) : 0;
+    const D4 pi = valid ? ld3(S.pos + i) : D4{0.0, 0.0, 0.0, 0.0};
     const D4 ni = valid ? ld3(S.ori + i) : D4{0.0, 0.0, 0.0, 0.0};
     // the stage: every thread's (at most three) slots first, then their records
     constexpr int SPT = (SL + BLOCK - 1) / BLOCK;
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 s_nx[q] = o.x;
                 s_ny[q] = o.y;
                 s_nz[q] = o.z;
-                s_t[q] = ldg(S.typ + slot[k]);
+                s_t[q] = ldg(S.typ + slot[k]) & TYP_MASK;
             }
         }
     }
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
     __syncthreads();
     if (chunk >= S.nchunk) return;
-    const int ti = (int)pi.w;
+    const int ti = traw & TYP_MASK;
     const T nix = (T)ni.x, niy = (T)ni.y, niz = (T)ni.z;
     T fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
     double U = 0.0, W = 0.0;
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                     const V3 o = ldg(S.ori + slot);
                     c.x = p.x; c.y = p.y; c.z = p.z;
                     c.nx = o.x; c.ny = o.y; c.nz = o.z;
-                    c.t = ldg(S.typ + slot);
+                    c.t = ldg(S.typ + slot) & TYP_MASK;
                     return c;
                 }
             }
@@ -916,13 +917,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         // the own-state loads first, so that they are in flight during the bond lookups
         if (KICK || ENERGY) {
             v = ld3(S.vel + i);
-            w = ld3(S.angv + i);
+            if (ti == 0) w = ld3(S.angv + i);        // zero for protein beads
         }
-        const F4 xb = KICK == 2 ? ldg(S.xb + i) : F4{0.f, 0.f, 0.f, 0.f};
-        const F4 xp = KICK == 2 ? ldg(S.xp + i) : F4{0.f, 0.f, 0.f, 0.f};
-        // bonds of this particle (CSR by caller id), FP64 in both modes
-        const int g = S.gid[i];
-        for (int q = S.bstart[g]; q < S.bstart[g + 1]; ++q) {
+        const F3 xb = KICK == 2 ? ldg(S.xb + i) : F3{0.f, 0.f, 0.f};
+        const F3 xp = KICK == 2 ? ldg(S.xp + i) : F3{0.f, 0.f, 0.f};
+        // bonds of this particle (CSR by caller id), FP64 in both modes; the table is
+        // looked up only for particles flagged as bonded
+        const bool bonded = (traw & TYP_BONDED) != 0;
+        const int g = (bonded || P.thermo_on) ? S.gid[i] : 0;
+        const int qb = bonded ? S.bstart[g] : 0, qe = bonded ? S.bstart[g + 1] : 0;
+        for (int q = qb; q < qe; ++q) {
             const int j = S.slot[S.bpart[q]];
             const D4 pj = ld3(S.pos + j);
             double dx, dy, dz;

@@ -263,7 +263,7 @@ size_t layout(HostSys &s, char *base) {
     const int32_t k = s.k;
     SysDev &d = s.dev;
     d.pos = c.take<V3>(n); d.vel = c.take<V3>(n); d.ori = c.take<V3>(n); d.angv = c.take<V3>(n);
-    d.frc = c.take<V3>(n); d.trq = c.take<V3>(n); d.xb = c.take<F4>(n); d.xp = c.take<F4>(n);
+    d.frc = c.take<V3>(n); d.trq = c.take<V3>(n); d.xb = c.take<F3>(n); d.xp = c.take<F3>(n);
     d.pos2 = c.take<V3>(n); d.vel2 = c.take<V3>(n); d.ori2 = c.take<V3>(n); d.angv2 = c.take<V3>(n);
     d.gid = c.take<int32_t>(n); d.gid2 = c.take<int32_t>(n); d.slot = c.take<int32_t>(n);
     d.owner = c.take<int32_t>(n);

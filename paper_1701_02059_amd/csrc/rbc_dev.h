@@ -10,6 +10,10 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;            // threads per block for particle / cell kernels
 constexpr int CHUNK = 64;             // particles per neighbour-list chunk (one wavefront)
 constexpr int MAXNB = 96;             // neighbour-list rows per chunk
+// per-particle type byte: the type in the low bits, and a flag for particles with bonds
+// (the step kernel looks up the bond table only for those)
+constexpr int TYP_MASK = 3;
+constexpr int TYP_BONDED = 0x80;
 constexpr int SORT_IPT = 16;          // items per thread in the radix sort
 constexpr int SORT_TILE = BLOCK * SORT_IPT;
 constexpr int MAX_SLOTS = 256;
@@ -104,10 +108,10 @@ struct SysDev {
     int32_t split;                                  // the step kernel spreads each chunk's rows over four waves
     double box[3];
     V3 *pos;
-    uint8_t *typ;                                   // particle type (0 lipid, 1 junction, 2 spectrin)
+    uint8_t *typ;                                   // type (0 lipid, 1 junction, 2 spectrin) | TYP_BONDED
     V3 *vel, *ori, *angv, *frc, *trq;
-    F4 *xb;                                         // positions at the last list build (FP32)
-    F4 *xp;                                         // positions at the last prune (FP32)
+    F3 *xb;                                         // positions at the last list build (FP32)
+    F3 *xp;                                         // positions at the last prune (FP32)
     V3 *pos2;
     uint8_t *typ2;
     V3 *vel2, *ori2, *angv2;
@@ -280,6 +284,11 @@ __device__ __forceinline__ V3 ldg(const V3 *p) {
     const gp q = (gp)p;
     return V3{q[0], q[1], q[2]};
 }
+__device__ __forceinline__ F3 ldg(const F3 *p) {
+    typedef const __attribute__((address_space(1))) float *gp;
+    const gp q = (gp)p;
+    return F3{q[0], q[1], q[2]};
+}
 __device__ __forceinline__ D4 ld3(const V3 *p) {
     const V3 v = ldg(p);
     return D4{v.x, v.y, v.z, 0.0};
@@ -287,7 +296,7 @@ __device__ __forceinline__ D4 ld3(const V3 *p) {
 // a particle's position with its type in w
 __device__ __forceinline__ D4 ldpos(const SysDev &S, int i) {
     const V3 p = ldg(S.pos + i);
-    return D4{p.x, p.y, p.z, (double)ldg(S.typ + i)};
+    return D4{p.x, p.y, p.z, (double)(ldg(S.typ + i) & TYP_MASK)};
 }
 __device__ __forceinline__ void st3(V3 *p, const D4 &v) {
     typedef __attribute__((address_space(1))) double *gp;
