@@ -447,20 +447,26 @@ __device__ __forceinline__ double minimg_fast(double d, double L, double iL) {
 // Branch-free FP32 lipid-lipid law for the mixed-precision step kernel, on the
 // separation (dx, dy, dz) = x_i - x_j with r2 = |d|^2 > 0.  Both radial branches are
 // evaluated and selected (the repulsive core below r_min, the cos^(2 zeta) well above
-// it); `on` masks the pair out (no force, torque or energy) without a branch.  Returns
-// U; the force on i is minus (mx, my, mz) as returned, the torque on i (tx, ty, tz).
-// The same law as lipid_pair, rearranged for fewer operations: with g = -t n_i -
-// s n_j + sin(th0) (n_j - n_i) and k = dU/da / r, the force on i is
-// -[(dU/dr - k g.e) e + k g], and g.e = -2 s t + sin(th0) (t - s).
+// it); `on` masks the pair out (every coefficient and U zero) without a branch.
+// With g = -t n_i - s n_j + sin(th0) (n_j - n_i) and k = dU/da / r, the force on i is
+// -[(dU/dr - k g.e) e + k g], where g.e = -2 s t + sin(th0) (t - s), and the torque on i
+// is n_i x g_i with g_i = -dU/da (n_j - (t + sin th0) e).  Both are returned as
+// coefficients, so that the caller sums the terms along n_i, and the torque's cross
+// product with n_i, once per particle instead of once per pair:
+//   force on i  = -(A e + bi n_i + bj n_j),    g_i = cn n_j + ce e.
+// Returns U; (ex, ey, ez) is the unit separation.
 template <bool FAST>
-__device__ __forceinline__ float lipid_pair_bf(const DevParams &P, float dx, float dy, float dz, float r2, float nix,
-                                               float niy, float niz, float njx, float njy, float njz, bool on,
-                                               float &mx, float &my, float &mz, float &tx, float &ty, float &tz) {
+__device__ __forceinline__ float lipid_coef(const DevParams &P, float dx, float dy, float dz, float r2, float nix,
+                                            float niy, float niz, float njx, float njy, float njz, bool on,
+                                            float &ex, float &ey, float &ez, float &A, float &bi, float &bj,
+                                            float &cn, float &ce) {
     const float eps = (float)P.eps, mu = (float)P.mu, rmin = (float)P.r_min;
     const float st0 = FAST ? 0.0f : (float)P.st0;
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
-    const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+    ex = dx * rinv;
+    ey = dy * rinv;
+    ez = dz * rinv;
     const float s = nix * ex + niy * ey + niz * ez;
     const float t = njx * ex + njy * ey + njz * ez;
     const float c = nix * njx + niy * njy + niz * njz;
@@ -495,21 +501,15 @@ __device__ __forceinline__ float lipid_pair_bf(const DevParams &P, float dx, flo
     const float kt = k * t, ks = k * s;
     float ge2 = 2.0f * kt * s;                           // -k g.e
     if (!FAST) ge2 -= k * st0 * (t - s);
-    const float A = dUdr + ge2;
-    float bi = -kt, bj = -ks;                            // k g = bi n_i + bj n_j
+    A = dUdr + ge2;
+    bi = -kt;                                            // k g = bi n_i + bj n_j
+    bj = -ks;
     if (!FAST) {
         bi -= k * st0;
         bj += k * st0;
     }
-    mx = A * ex + bi * nix + bj * njx;
-    my = A * ey + bi * niy + bj * njy;
-    mz = A * ez + bi * niz + bj * njz;
-    // torque on i: n_i x g_i with g_i = -dU/da (n_j - (t + sin th0) e)
-    const float bb = t + st0;
-    const float wx = -dUda * (njx - bb * ex), wy = -dUda * (njy - bb * ey), wz = -dUda * (njz - bb * ez);
-    tx = niy * wz - niz * wy;
-    ty = niz * wx - nix * wz;
-    tz = nix * wy - niy * wx;
+    cn = -dUda;
+    ce = dUda * (FAST ? t : t + st0);
     return U;
 }
 
@@ -676,6 +676,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         // Software pipeline: the list entries of the next trip are loaded from global
         // memory while this trip's rows are evaluated (the lists carry padding rows past
         // the last chunk, so the load after the last trip stays in bounds).
+        float sbi = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;   // sum of bi; sum of g_i
         int en[UNR];
         for (int q = 0; q < UNR; ++q) en[q] = ntrip > 0 ? (int)ldg(col + q * CHUNK) : 0xffff;
         for (int it = 0; it < ntrip; ++it) {
@@ -721,37 +722,61 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                     if (band[q]) in[q] = d2 < sel_cut(c[q].t, rcA, rcB, rcC);
                 }
             }
-            // the pair law of every row, in one block of straight-line code; (ax, ay, az)
-            // receives minus the pair's force on i
-            float ax[UNR], ay[UNR], az[UNR], u[UNR], qx[UNR], qy[UNR], qz[UNR];
+            // the pair law of every row, in one block of straight-line code, as coefficients
+            float ex[UNR], ey[UNR], ez[UNR], A[UNR], bi[UNR], bj[UNR], cn[UNR], ce[UNR], u[UNR];
             bool anywca = false;
             for (int q = 0; q < UNR; ++q) {
                 in[q] = in[q] && valid;
-                u[q] = lipid_pair_bf<FAST>(P, fdx[q], fdy[q], fdz[q], r2[q], nix, niy, niz, c[q].nx, c[q].ny,
-                                           c[q].nz, in[q] && lip[q], ax[q], ay[q], az[q], qx[q], qy[q], qz[q]);
+                u[q] = lipid_coef<FAST>(P, fdx[q], fdy[q], fdz[q], r2[q], nix, niy, niz, c[q].nx, c[q].ny, c[q].nz,
+                                        in[q] && lip[q], ex[q], ey[q], ez[q], A[q], bi[q], bj[q], cn[q], ce[q]);
                 anywca = anywca || (in[q] && !lip[q]);
+            }
+            for (int q = 0; q < UNR; ++q) {
+                fx = fmaf(-A[q], ex[q], fx);
+                fy = fmaf(-A[q], ey[q], fy);
+                fz = fmaf(-A[q], ez[q], fz);
+                fx = fmaf(-bj[q], c[q].nx, fx);
+                fy = fmaf(-bj[q], c[q].ny, fy);
+                fz = fmaf(-bj[q], c[q].nz, fz);
+                sbi += bi[q];
+                gx = fmaf(cn[q], c[q].nx, gx);
+                gy = fmaf(cn[q], c[q].ny, gy);
+                gz = fmaf(cn[q], c[q].nz, gz);
+                gx = fmaf(ce[q], ex[q], gx);
+                gy = fmaf(ce[q], ey[q], gy);
+                gz = fmaf(ce[q], ez[q], gz);
+                if (ENERGY) {
+                    const float ax = A[q] * ex[q] + bi[q] * nix + bj[q] * c[q].nx;
+                    const float ay = A[q] * ey[q] + bi[q] * niy + bj[q] * c[q].ny;
+                    const float az = A[q] * ez[q] + bi[q] * niz + bj[q] * c[q].nz;
+                    U += 0.5 * (double)u[q];
+                    W -= 0.5 * (dx[q] * (double)ax + dy[q] * (double)ay + dz[q] * (double)az);
+                }
             }
             if (__builtin_expect(__ballot(anywca) != 0ull, 0)) {
                 for (int q = 0; q < UNR; ++q) {
                     const bool wca = in[q] && !lip[q];
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
                     const float uw = wca_pair<float>(P, wca ? fdx[q] : 2.0f, fdy[q], fdz[q], bx, by, bz);
-                    if (wca) { ax[q] = -bx; ay[q] = -by; az[q] = -bz; u[q] = uw; }
-                }
-            }
-            for (int q = 0; q < UNR; ++q) {
-                fx -= ax[q];
-                fy -= ay[q];
-                fz -= az[q];
-                tx += qx[q];
-                ty += qy[q];
-                tz += qz[q];
-                if (ENERGY) {
-                    U += 0.5 * (double)u[q];
-                    W -= 0.5 * (dx[q] * (double)ax[q] + dy[q] * (double)ay[q] + dz[q] * (double)az[q]);
+                    if (wca) {
+                        fx += bx;
+                        fy += by;
+                        fz += bz;
+                        if (ENERGY) {
+                            U += 0.5 * (double)uw;
+                            W += 0.5 * (dx[q] * (double)bx + dy[q] * (double)by + dz[q] * (double)bz);
+                        }
+                    }
                 }
             }
         }
+        // the terms along n_i, and the torque n_i x sum g_i
+        fx -= sbi * nix;
+        fy -= sbi * niy;
+        fz -= sbi * niz;
+        tx += niy * gz - niz * gy;
+        ty += niz * gx - nix * gz;
+        tz += nix * gy - niy * gx;
     };
 
     // ---- FP64 mode: exact test on every entry, FP64 pair law
