@@ -27,6 +27,14 @@ namespace rbc {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// A running maximum that many waves raise: the atomic is issued only when the value
+// read (never above the true running maximum) is smaller, so that most waves skip the
+// serialised same-address atomic.
+template <class T>
+__device__ __forceinline__ void max_if_larger(T *p, T v) {
+    if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
     return v;
@@ -942,16 +950,21 @@ __global__ void k_cell_bounds(const SysDev *Sd, Maps L_maps) {
         S.seed[c].w = R;
     }
     for (int o = 32; o > 0; o >>= 1) R = fmax(R, __shfl_xor(R, o));
-    if ((threadIdx.x & 63) == 0 && c - (int)(threadIdx.x & 63) < S.k) atomicMax(&S.sc->rmax, dbits(R));
+    if ((threadIdx.x & 63) == 0 && c - (int)(threadIdx.x & 63) < S.k) max_if_larger(&S.sc->rmax, dbits(R));
 }
 
-// Cells B paired with A (as below), one thread per cell: the serial walk of the
-// window.  mode 0 counts, mode 1 writes (grid-scan order).
-__device__ int cell_query_serial(const SysDev &S, const SysScal *sc, int A, double search, int mode, int *out, int cap) {
-    D4 ca = S.seed[A];
-    double Ra = ca.w;
-    double rho = Ra + bitsd(sc->rmax) + search + 1e-9;
-    double xa[3] = {ca.x, ca.y, ca.z};
+// The query window of cell A on the seed grid: per axis the grid rows within
+// R_A + R_max + search of its centroid (a periodic axis wraps; a window that covers
+// the period, or a non-finite bound, takes the whole axis).  Along z, whose grid cells
+// are consecutive in the grid's linear order, the window is one or two runs of grid
+// cells (two where it wraps), so that the seeds of a run are one range of `gseed`.
+struct QWin {
+    int lo[2], n[2];          // x and y: first row (before wrapping) and row count
+    int za[2], zb[2], nz;     // z runs [za, zb] (wrapped), in walk order
+};
+__device__ __forceinline__ QWin query_window(const SysDev &S, const SysScal *sc, const D4 &ca, double search) {
+    const double rho = ca.w + bitsd(sc->rmax) + search + 1e-9;
+    const double xa[3] = {ca.x, ca.y, ca.z};
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
         double u = wrap_coord(xa[a], S.per[a], S.box[a]) - sc->glo[a];
@@ -969,87 +982,94 @@ __device__ int cell_query_serial(const SysDev &S, const SysScal *sc, int A, doub
         lo[a] = l;
         hi[a] = h;
     }
-    int cnt = 0;
+    QWin w;
+    for (int a = 0; a < 2; ++a) {
+        w.lo[a] = lo[a];
+        w.n[a] = max(0, hi[a] - lo[a] + 1);
+    }
+    const int dz = sc->gdim[2];
+    w.nz = 0;
+    if (hi[2] >= lo[2]) {
+        if (lo[2] < 0) {                  // periodic: the rows below 0 are the top ones, walked first
+            w.za[0] = lo[2] + dz; w.zb[0] = dz - 1;
+            w.za[1] = 0; w.zb[1] = hi[2];
+            w.nz = 2;
+        } else if (hi[2] >= dz) {
+            w.za[0] = lo[2]; w.zb[0] = dz - 1;
+            w.za[1] = 0; w.zb[1] = hi[2] - dz;
+            w.nz = 2;
+        } else {
+            w.za[0] = lo[2]; w.zb[0] = hi[2];
+            w.nz = 1;
+        }
+    }
+    return w;
+}
+
+// The linear index of grid column (x row, y row) of the window, wrapped on periodic axes.
+__device__ __forceinline__ int window_column(const SysDev &S, const SysScal *sc, const QWin &w, int ix, int iy) {
+    int gx = w.lo[0] + ix, gy = w.lo[1] + iy;
+    if (S.per[0]) gx = ((gx % sc->gdim[0]) + sc->gdim[0]) % sc->gdim[0];
+    if (S.per[1]) gy = ((gy % sc->gdim[1]) + sc->gdim[1]) % sc->gdim[1];
+    return (gx * sc->gdim[1] + gy) * sc->gdim[2];
+}
+
+// Whether seed B pairs with cell A (centroid ca, radius ca.w).
+__device__ __forceinline__ bool cell_pair_test(const SysDev &S, const D4 &ca, const D4 &cb, double search) {
     double dx, dy, dz;
-    for (int gx0 = lo[0]; gx0 <= hi[0]; ++gx0) {
-        int gx = S.per[0] ? ((gx0 % sc->gdim[0]) + sc->gdim[0]) % sc->gdim[0] : gx0;
-        for (int gy0 = lo[1]; gy0 <= hi[1]; ++gy0) {
-            int gy = S.per[1] ? ((gy0 % sc->gdim[1]) + sc->gdim[1]) % sc->gdim[1] : gy0;
-            for (int gz0 = lo[2]; gz0 <= hi[2]; ++gz0) {
-                int gz = S.per[2] ? ((gz0 % sc->gdim[2]) + sc->gdim[2]) % sc->gdim[2] : gz0;
-                int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
-                const int qe = ldg(S.gstart + g + 1);
-                for (int q = ldg(S.gstart + g); q < qe; ++q) {
+    const double d = sqrt(dist2_exact(S, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, dx, dy, dz));
+    return d <= ca.w + cb.w + search + 1e-9;
+}
+
+// Cells B paired with A (as below), one thread per cell: the serial walk of the
+// window, a column's z runs at a time.  mode 0 counts, mode 1 writes (grid-scan order).
+__device__ int cell_query_serial(const SysDev &S, const SysScal *sc, int A, double search, int mode, int *out, int cap) {
+    const D4 ca = S.seed[A];
+    const QWin w = query_window(S, sc, ca, search);
+    int cnt = 0;
+    for (int ix = 0; ix < w.n[0]; ++ix)
+        for (int iy = 0; iy < w.n[1]; ++iy) {
+            const int base = window_column(S, sc, w, ix, iy);
+            for (int r = 0; r < w.nz; ++r) {
+                const int qe = ldg(S.gstart + base + w.zb[r] + 1);
+                for (int q = ldg(S.gstart + base + w.za[r]); q < qe; ++q) {
                     const int B = ldg(S.gseed + q);
-                    const D4 cb = ldg(S.seed + B);
-                    double d = sqrt(dist2_exact(S, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, dx, dy, dz));
-                    if (d <= Ra + cb.w + search + 1e-9) {
+                    if (cell_pair_test(S, ca, ldg(S.seed + B), search)) {
                         if (mode && cnt < cap) out[cnt] = B;
                         ++cnt;
                     }
                 }
             }
         }
-    }
     return cnt;
 }
 
 // Cells B paired with A: |minimg(c_A - c_B)| <= R_A + R_B + search + 1e-9 with
-// search = largest (rc + 2 skin).  One wavefront per cell A: the grid cells within
-// reach (x slowest, z fastest) are taken 64 at a time, lane l scanning the seeds of
-// the l-th one.  With `out`, the hits are written in that scan order (an exclusive
-// scan of the lanes' counts places each lane's hits), so the row is the same as a
-// serial walk of the window would give.  Returns the row's length on every lane.
+// search = largest (rc + 2 skin).  One wavefront per cell A: the window's grid columns
+// (x slowest) are taken 64 at a time, lane l scanning the seeds of the l-th one's z
+// runs.  With `out`, the hits are written in that scan order (an exclusive scan of the
+// lanes' counts places each lane's hits), so the row is the same as a serial walk of
+// the window would give.  Returns the row's length on every lane.
 __device__ int cell_query_wave(const SysDev &S, const SysScal *sc, int A, double search, int32_t *out, int cap) {
     const int lane = threadIdx.x & (WAVE - 1);
     const D4 ca = S.seed[A];
-    const double Ra = ca.w;
-    const double rho = Ra + bitsd(sc->rmax) + search + 1e-9;
-    const double xa[3] = {ca.x, ca.y, ca.z};
-    int lo[3], nw[3];
-    for (int a = 0; a < 3; ++a) {
-        double u = wrap_coord(xa[a], S.per[a], S.box[a]) - sc->glo[a];
-        int dim = sc->gdim[a];
-        double fl = floor((u - rho) / sc->gh[a]), fh = floor((u + rho) / sc->gh[a]);
-        if (!(fl > -1e9 && fh < 1e9)) { fl = 0.0; fh = (double)(dim - 1); }   // non-finite: scan the axis
-        int l = (int)fl;
-        int h = (int)fh;
-        if (S.per[a]) {
-            if (h - l + 1 >= dim) { l = 0; h = dim - 1; }
-        } else {
-            l = max(l, 0);
-            h = min(h, dim - 1);
-        }
-        lo[a] = l;
-        nw[a] = max(0, h - l + 1);
-    }
-    const int W = nw[0] * nw[1] * nw[2];
+    const QWin w = query_window(S, sc, ca, search);
+    const int W = w.n[0] * w.n[1];
     int total = 0;
-    double dx, dy, dz;
     for (int w0 = 0; w0 < W; w0 += WAVE) {
         const int wi = w0 + lane;
-        int qb = 0, qe = 0;
+        int qb[2] = {0, 0}, qe[2] = {0, 0};
         if (wi < W) {
-            const int iz = wi % nw[2], iy = (wi / nw[2]) % nw[1], ix = wi / (nw[2] * nw[1]);
-            int gx = lo[0] + ix, gy = lo[1] + iy, gz = lo[2] + iz;
-            if (S.per[0]) gx = ((gx % sc->gdim[0]) + sc->gdim[0]) % sc->gdim[0];
-            if (S.per[1]) gy = ((gy % sc->gdim[1]) + sc->gdim[1]) % sc->gdim[1];
-            if (S.per[2]) gz = ((gz % sc->gdim[2]) + sc->gdim[2]) % sc->gdim[2];
-            const int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
-            qb = ldg(S.gstart + g);
-            qe = ldg(S.gstart + g + 1);
+            const int base = window_column(S, sc, w, wi / w.n[1], wi % w.n[1]);
+            for (int r = 0; r < w.nz; ++r) {
+                qb[r] = ldg(S.gstart + base + w.za[r]);
+                qe[r] = ldg(S.gstart + base + w.zb[r] + 1);
+            }
         }
-        auto hit = [&](int q, int &B) {
-            B = ldg(S.gseed + q);
-            const D4 cb = ldg(S.seed + B);
-            const double d = sqrt(dist2_exact(S, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, dx, dy, dz));
-            return d <= Ra + cb.w + search + 1e-9;
-        };
         int cnt = 0;
-        for (int q = qb; q < qe; ++q) {
-            int B;
-            if (hit(q, B)) ++cnt;
-        }
+        for (int r = 0; r < 2; ++r)
+            for (int q = qb[r]; q < qe[r]; ++q)
+                if (cell_pair_test(S, ca, ldg(S.seed + ldg(S.gseed + q)), search)) ++cnt;
         // inclusive scan of the lanes' counts
         int inc = cnt;
         for (int o = 1; o < WAVE; o <<= 1) {
@@ -1058,13 +1078,14 @@ __device__ int cell_query_wave(const SysDev &S, const SysScal *sc, int A, double
         }
         if (out && cnt > 0) {
             int k = total + inc - cnt;
-            for (int q = qb; q < qe; ++q) {
-                int B;
-                if (hit(q, B)) {
-                    if (k < cap) out[k] = B;
-                    ++k;
+            for (int r = 0; r < 2; ++r)
+                for (int q = qb[r]; q < qe[r]; ++q) {
+                    const int B = ldg(S.gseed + q);
+                    if (cell_pair_test(S, ca, ldg(S.seed + B), search)) {
+                        if (k < cap) out[k] = B;
+                        ++k;
+                    }
                 }
-            }
         }
         total += __shfl(inc, WAVE - 1);
     }
@@ -1093,7 +1114,7 @@ __global__ __launch_bounds__(BLOCK) void k_cnbr_count_serial(const SysDev *Sd, M
         S.cnbr_start[c] = n;
     }
     const int m = wave_max_int(n);
-    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(&S.sc->cnbr_maxrow, m);
+    if ((threadIdx.x & 63) == 0 && m > 0) max_if_larger(&S.sc->cnbr_maxrow, m);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cnbr_fill_serial(const SysDev *Sd, Maps L_maps, double search) {
@@ -1137,7 +1158,7 @@ __global__ __launch_bounds__(BLOCK) void k_cnbr_count(const SysDev *Sd, Maps L_m
     __syncthreads();
     if (threadIdx.x == 0) {
         const int mm = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
-        if (mm > 0) atomicMax(&S.sc->cnbr_maxrow, mm);
+        if (mm > 0) max_if_larger(&S.sc->cnbr_maxrow, mm);
     }
 }
 
