@@ -1193,11 +1193,19 @@ void launch_cell_bounds(const LaunchCtx &L) {
 
 void launch_cell_pairs(const LaunchCtx &L) {
     if (L.nblk_c == 0) return;
-    hipLaunchKernelGGL(k_cnbr_count_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
-    hipLaunchKernelGGL(k_cnbr_count, dim3(CQ_BLOCKS * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    // each size class's kernels only where the launch holds a system of that class
+    const bool large = L.kmax >= CQ_SERIAL_MIN, small = L.kmin < CQ_SERIAL_MIN;
+    if (large)
+        hipLaunchKernelGGL(k_cnbr_count_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    if (small)
+        hipLaunchKernelGGL(k_cnbr_count, dim3(CQ_BLOCKS * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps,
+                           L.prm.cell_search);
     launch_scan(L, 3);
-    hipLaunchKernelGGL(k_cnbr_fill_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
-    hipLaunchKernelGGL(k_cnbr_fill, dim3(CQ_BLOCKS * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    if (large)
+        hipLaunchKernelGGL(k_cnbr_fill_serial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps, L.prm.cell_search);
+    if (small)
+        hipLaunchKernelGGL(k_cnbr_fill, dim3(CQ_BLOCKS * L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps,
+                           L.prm.cell_search);
 }
 
 // ------------------------------------------------------------------ neighbour lists

@@ -334,6 +334,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
     std::vector<SysDev> tab(ns);
     std::vector<const int32_t *> lips(ns, nullptr);
     std::vector<int32_t> maps(8 * (ns + 1), 0);
+    int32_t kmin = INT32_MAX, kmax = 0;
     int32_t *mp = maps.data(), *mc = mp + (ns + 1), *mg = mc + (ns + 1), *mtp = mg + (ns + 1), *mts = mtp + (ns + 1);
     int32_t *msc = mts + (ns + 1), *msg = msc + (ns + 1), *mf = msg + (ns + 1);
     for (int s = 0; s < ns; ++s) {
@@ -349,6 +350,7 @@ rbc_status refresh_tables(rbc_ctx *h) {
         const bool on = runs(hs);
         const int64_t n = on ? hs.n : 0;
         const int32_t k = on ? hs.k : 0;
+        if (on) { kmin = std::min(kmin, k); kmax = std::max(kmax, k); }
         mp[s + 1] = mp[s] + (int32_t)((n + BLOCK - 1) / BLOCK);
         mc[s + 1] = mc[s] + (k + BLOCK - 1) / BLOCK;
         mg[s + 1] = mg[s] + (on ? (hs.gcap + BLOCK - 1) / BLOCK : 0);
@@ -375,6 +377,8 @@ rbc_status refresh_tables(rbc_ctx *h) {
     L.maps.sg = h->d_maps + 6 * (ns + 1);
     L.maps.f = h->d_maps + 7 * (ns + 1);
     L.maps.nsys = ns;
+    L.kmin = kmin;
+    L.kmax = kmax;
     L.nblk_p = mp[ns];
     L.nblk_c = mc[ns];
     L.nblk_g = mg[ns];
@@ -417,8 +421,12 @@ LaunchCtx restricted(rbc_ctx *h, const std::vector<int> &which) {
     U.maps.sc = h->d_umaps + 5 * (ns + 1);
     U.maps.sg = h->d_umaps + 6 * (ns + 1);
     U.nblk_p = U.nblk_c = U.nblk_g = U.nblk_tp = U.nblk_ts = U.nblk_sc = U.nblk_sg = 0;
+    U.kmin = INT32_MAX;
+    U.kmax = 0;
     for (int s : which) {
         const HostSys &hs = h->sys[s];
+        U.kmin = std::min(U.kmin, hs.k);
+        U.kmax = std::max(U.kmax, hs.k);
         U.nblk_p += (int32_t)((hs.n + BLOCK - 1) / BLOCK);
         U.nblk_c += (hs.k + BLOCK - 1) / BLOCK;
         U.nblk_g += (hs.gcap + BLOCK - 1) / BLOCK;

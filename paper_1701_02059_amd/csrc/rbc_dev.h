@@ -329,6 +329,7 @@ struct LaunchCtx {
     Maps maps;
     int32_t nblk_p, nblk_c, nblk_g, nblk_tp, nblk_ts, nblk_sc, nblk_sg, nblk_f;   // totals over systems
     int32_t nsys;
+    int32_t kmin, kmax;      // fewest and most cells of a system in the launch
     DevParams prm;
     hipStream_t st;
 };
