@@ -45,15 +45,23 @@ PEAK_FP32 = 157.3           # TFLOP/s, MI355X FP32 vector (published; counts pac
 PEAK_FP64 = 78.6            # TFLOP/s, MI355X FP64 vector
 PEAK_HBM = 8000.0           # GB/s
 # HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
-# skin 0.5: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
+# skins 0.65 and 0.15: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
-FORCE_TRAFFIC = {"sources_sha256": "e734966e6845956f", "skin": 0.6, "inner_skin": 0.15,
-                 "bytes": 2260542453, "fetch_kib": 796893, "write_kib": 613775,
-                 "valu_insts": 199351233}   # SQ_INSTS_VALU per launch (wavefront instructions)
+FORCE_TRAFFIC = {"sources_sha256": "3b92c8c287101acd", "skin": 0.65, "inner_skin": 0.15,
+                 "bytes": 1512720435, "fetch_kib": 504532, "write_kib": 468201,
+                 "valu_insts": 176634971}   # SQ_INSTS_VALU per launch (wavefront instructions)
 BYTES_BUILD_READ = 25       # list build: position (3 x 8 B) and type (1 B) of every particle, read once
 CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
                   "paper_1701_02059_amd/csrc/rbc_dev.h")
+
+
+def workload_shape(name: str) -> str:
+    """What the named synthetic workload is, for the JSON line's config."""
+    base = name[: -len("_detached")] if name.endswith("_detached") else name
+    shape = {"patch": "flat periodic membrane patch", "vesicle": "spherical vesicle",
+             "tiny": "small spherical vesicle"}.get(base, "whole-RBC biconcave cell")
+    return shape + (", detached cytoskeleton" if base != name else "")
 
 
 def kernel_sources_digest() -> str:
@@ -453,7 +461,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 pair arithmetic / f64 state",
         "data": "synthetic (seeded generator; no dataset)",
-        "config": {"workload": f"whole-RBC biconcave cell ({args.workload}), {system.N:,} particles: "
+        "config": {"workload": f"{workload_shape(args.workload)} ({args.workload}), {system.N:,} particles: "
                                f"{system.counts()['L']:,} lipids, {system.counts()['J']:,} junctions, "
                                f"{system.counts()['S']:,} spectrin beads; dt={DT}, NVE, cells updated every "
                                f"{mp.update_every} steps, skin {mp.skin}, pruned-list buffer {mp.inner_skin}",
