@@ -451,8 +451,8 @@ __device__ __forceinline__ double minimg_fast(double d, double L, double iL) {
 // With g = -t n_i - s n_j + sin(th0) (n_j - n_i) and k = dU/da / r, the force on i is
 // -[(dU/dr - k g.e) e + k g], where g.e = -2 s t + sin(th0) (t - s), and the torque on i
 // is n_i x g_i with g_i = -dU/da (n_j - (t + sin th0) e).  Both are returned as
-// coefficients, so that the caller sums the terms along n_i once per particle instead
-// of once per pair:
+// coefficients, so that the caller sums the terms along n_i, and forms the torque's
+// cross product with n_i, once per particle instead of once per pair:
 //   force on i  = -(A e + bi n_i + bj n_j),    g_i = cn n_j + ce e.
 // Returns U; (ex, ey, ez) is the unit separation.
 template <bool FAST>
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         // Software pipeline: the list entries of the next trip are loaded from global
         // memory while this trip's rows are evaluated (the lists carry padding rows past
         // the last chunk, so the load after the last trip stays in bounds).
-        float sbi = 0.0f;                                  // sum of bi
+        float sbi = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;   // sum of bi; of g_i - cn n_i
         int en[UNR];
         for (int q = 0; q < UNR; ++q) en[q] = ntrip > 0 ? (int)ldg(col + q * CHUNK) : 0xffff;
         for (int it = 0; it < ntrip; ++it) {
@@ -739,14 +739,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 fy = fmaf(-bj[q], c[q].ny, fy);
                 fz = fmaf(-bj[q], c[q].nz, fz);
                 sbi += bi[q];
-                // the torque n_i x g_i pair by pair: g_i's large part along n_i cancels in
-                // the cross product, which a sum of the g_i before it would round away
-                const float wx = fmaf(ce[q], ex[q], cn[q] * c[q].nx);
-                const float wy = fmaf(ce[q], ey[q], cn[q] * c[q].ny);
-                const float wz = fmaf(ce[q], ez[q], cn[q] * c[q].nz);
-                tx += niy * wz - niz * wy;
-                ty += niz * wx - nix * wz;
-                tz += nix * wy - niy * wx;
+                // the torque n_i x g_i with g_i = cn n_j + ce e: n_i x n_i = 0, so the sum
+                // takes cn (n_j - n_i) + ce e instead, without g_i's large part along n_i
+                // (which the FP32 sum would round before the cross product cancels it)
+                gx = fmaf(cn[q], c[q].nx - nix, gx);
+                gy = fmaf(cn[q], c[q].ny - niy, gy);
+                gz = fmaf(cn[q], c[q].nz - niz, gz);
+                gx = fmaf(ce[q], ex[q], gx);
+                gy = fmaf(ce[q], ey[q], gy);
+                gz = fmaf(ce[q], ez[q], gz);
                 if (ENERGY) {
                     const float ax = A[q] * ex[q] + bi[q] * nix + bj[q] * c[q].nx;
                     const float ay = A[q] * ey[q] + bi[q] * niy + bj[q] * c[q].ny;
@@ -772,10 +773,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 }
             }
         }
-        // the terms along n_i
+        // the terms along n_i, and the torque n_i x (sum of the g_i - cn n_i)
         fx -= sbi * nix;
         fy -= sbi * niy;
         fz -= sbi * niz;
+        tx += niy * gz - niz * gy;
+        ty += niz * gx - nix * gz;
+        tz += nix * gy - niy * gx;
     };
 
     // ---- FP64 mode: exact test on every entry, FP64 pair law
