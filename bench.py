@@ -47,9 +47,9 @@ PEAK_HBM = 8000.0           # GB/s
 # HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
 # skins 0.65 and 0.15: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
-FORCE_TRAFFIC = {"sources_sha256": "b2abdc1af4d22a4a", "skin": 0.65, "inner_skin": 0.15,
-                 "bytes": 1512656816, "fetch_kib": 504496, "write_kib": 468212,
-                 "valu_insts": 190919146}   # SQ_INSTS_VALU per launch (wavefront instructions)
+FORCE_TRAFFIC = {"sources_sha256": "b89934748bc95f59", "skin": 0.65, "inner_skin": 0.15,
+                 "bytes": 1512712016, "fetch_kib": 504527, "write_kib": 468204,
+                 "valu_insts": 181583857}   # SQ_INSTS_VALU per launch (wavefront instructions)
 BYTES_BUILD_READ = 25       # list build: position (3 x 8 B) and type (1 B) of every particle, read once
 CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
 KERNEL_SOURCES = ("paper_1701_02059_amd/csrc/k_force.hip", "paper_1701_02059_amd/csrc/k_cells.hip",
