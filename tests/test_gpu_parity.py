@@ -88,6 +88,51 @@ def test_forces_mixed(R, mp, name, patch, ves):
     c.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bonds_between_lipids(R, mp, patch, prec):
+    """Bonds may join any particles: extra harmonic bonds between lipids (partners up to
+    6 sigma apart, some across the periodic boundary, stretched and compressed by up to
+    10%) reach the forces of both ends, against the oracle, and in FP64 a short
+    trajectory stays on the oracle's."""
+    rng = np.random.default_rng(5)
+    lip = np.flatnonzero(patch.type == 0)
+    L = np.where(patch.periodic, patch.box, 0.0)
+
+    def sep(i, j):
+        d = patch.x[i] - patch.x[j]
+        return d - L * np.round(d / np.where(L > 0, L, 1.0))
+
+    pairs = []
+    for i in rng.choice(lip, 400, replace=False):
+        r = np.linalg.norm(sep(i, lip), axis=1)
+        cand = lip[(r > 1.5) & (r < 6.0)]
+        if cand.size:
+            pairs.append((i, rng.choice(cand)))
+        if len(pairs) == 60:
+            break
+    extra = np.array(pairs, dtype=np.int32)
+    d = np.linalg.norm(sep(extra[:, 0], extra[:, 1]), axis=1)
+    s = dataclasses.replace(patch, bonds=np.concatenate([patch.bonds, extra]).astype(np.int32),
+                            r0=np.concatenate([patch.r0, d * rng.uniform(0.9, 1.1, d.size)]))
+    p = O.params_for(s, mp)
+    F0, T0, _, _ = O.forces(p, s)
+    precision = R.RBC_FP64 if prec == "fp64" else R.RBC_MIXED
+    tol, pp = (FP64_TOL, PP_FP64_TOL) if prec == "fp64" else (MIXED_TOL, PP_MIXED_TOL)
+    c = _ctx(R, mp, s, precision)
+    F, T = (to_np(t) for t in c.forces())
+    check_forces(F, F0, tol, pp, f"lipid bonds {prec} F")
+    check_forces(T, T0, tol, pp, f"lipid bonds {prec} tau")
+    if prec == "fp64":
+        xr, vr, nr, wr, _ = O.vv_run(p, s, 0.01, 5)
+        c.step(5, 0.01)
+        x, n, v, w = (to_np(t) for t in c.get_state())
+        assert np.abs(x - xr).max() < 1e-9
+        assert np.abs(v - vr).max() < 1e-8
+        assert np.abs(n - nr).max() < 1e-9
+        assert np.abs(w - wr).max() < 1e-8
+    c.close()
+
+
 def test_energy_record(R, mp, ves):
     p = O.params_for(ves, mp)
     F0, T0, U0, W0 = O.forces(p, ves)
