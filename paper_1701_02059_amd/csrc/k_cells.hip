@@ -509,19 +509,41 @@ __device__ int nearest_seed(const SysDev &S, const SysScal *sc, double xi, doubl
                 bool ny = nx || (oy < plo[1] || oy > phi[1]);
                 int gy = cc[1] + oy;
                 if (S.per[1]) gy = (gy % sc->gdim[1] + sc->gdim[1]) % sc->gdim[1];
-                for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-                    bool nz = ny || (oz < plo[2] || oz > phi[2]);
-                    if (!nz) continue;   // visited at a smaller radius
-                    int gz = cc[2] + oz;
-                    if (S.per[2]) gz = (gz % sc->gdim[2] + sc->gdim[2]) % sc->gdim[2];
-                    int g = (gx * sc->gdim[1] + gy) * sc->gdim[2] + gz;
-                    const int qe = ldg(S.gstart + g + 1);
-                    for (int q = ldg(S.gstart + g); q < qe; ++q) {
-                        const D4 c = ldg(S.gpos + q);
-                        const int sd = (int)c.w;
-                        if ((unsigned)(sd - slo) >= span) continue;   // the other particle set's cells
-                        double d2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
-                        if (d2 < bestd2 || (d2 == bestd2 && sd < best)) { bestd2 = d2; best = sd; }
+                // the column's cells not visited at a smaller radius: the whole z window
+                // where the column is new, else the rows below and above the previous
+                // window; each a run of consecutive grid cells (split where a periodic z
+                // axis wraps), whose seeds are one range of gpos
+                int ra[2], rb[2], nr = 0;
+                if (ny) {
+                    ra[0] = lo[2]; rb[0] = hi[2]; nr = 1;
+                } else {
+                    if (lo[2] < plo[2]) { ra[nr] = lo[2]; rb[nr] = min(hi[2], plo[2] - 1); ++nr; }
+                    if (hi[2] > phi[2]) { ra[nr] = max(lo[2], phi[2] + 1); rb[nr] = hi[2]; ++nr; }
+                }
+                const int nzg = sc->gdim[2], base = (gx * sc->gdim[1] + gy) * nzg;
+                for (int k = 0; k < nr; ++k) {
+                    int za = cc[2] + ra[k], zb = cc[2] + rb[k];
+                    int z2a = 0, z2b = -1;                // the wrapped part, if any
+                    if (S.per[2]) {                       // the window spans at most nzg rows
+                        if (za < 0) {
+                            if (zb < 0) { za += nzg; zb += nzg; }
+                            else { z2a = 0; z2b = zb; za += nzg; zb = nzg - 1; }
+                        } else if (zb >= nzg) {
+                            if (za >= nzg) { za -= nzg; zb -= nzg; }
+                            else { z2a = 0; z2b = zb - nzg; zb = nzg - 1; }
+                        }
+                    }
+                    for (int part = 0; part < 2; ++part) {
+                        const int a0 = part ? z2a : za, a1 = part ? z2b : zb;
+                        if (a1 < a0) continue;
+                        const int qe = ldg(S.gstart + base + a1 + 1);
+                        for (int q = ldg(S.gstart + base + a0); q < qe; ++q) {
+                            const D4 c = ldg(S.gpos + q);
+                            const int sd = (int)c.w;
+                            if ((unsigned)(sd - slo) >= span) continue;   // the other particle set's cells
+                            double d2 = dist2_exact(S, xi, yi, zi, c.x, c.y, c.z, dx, dy, dz);
+                            if (d2 < bestd2 || (d2 == bestd2 && sd < best)) { bestd2 = d2; best = sd; }
+                        }
                     }
                 }
             }
