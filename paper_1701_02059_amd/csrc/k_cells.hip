@@ -1329,6 +1329,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
     if (!S.sc->rebuild) return;
     __shared__ int s_cand[CANDMAX];
     __shared__ int s_ofs[CANDMAX + 1];
+    static_assert(CANDBITS / 32 <= CANDMAX, "the candidate bitmap and its prefix counts overlay s_ofs and s_kofs");
     __shared__ int s_kofs[CANDMAX + 1];
     __shared__ int s_qpos[CANDMAX];
     __shared__ F4 s_u[USTAGE];
@@ -1356,37 +1357,85 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
     const bool have_union = !(ncand <= 0 || ncand > CANDMAX || c1 < c0);
     int nsc = 0, ss = 0;
     if (have_union) {
-        int pw = 1;
-        while (pw < ncand) pw <<= 1;
-        for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? ldg(S.cnbr + q0 + q) : INT_MAX;
-        __syncthreads();
-        for (int kk = 2; kk <= pw; kk <<= 1)
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int t = tid; t < pw; t += BLOCK) {
-                    int ixj = t ^ jj;
-                    if (ixj > t) {
-                        int va = s_cand[t], vb = s_cand[ixj];
-                        bool up = (t & kk) == 0;
-                        if ((va > vb) == up) { s_cand[t] = vb; s_cand[ixj] = va; }
-                    }
-                }
-                __syncthreads();
-            }
-        // deduplicate in place
-        int vals[CANDMAX / BLOCK], fl[CANDMAX / BLOCK], loc = 0;
-        for (int q = 0; q < CANDMAX / BLOCK; ++q) {
-            const int idx = tid * (CANDMAX / BLOCK) + q;
-            vals[q] = idx < pw ? s_cand[idx] : INT_MAX;
-            const int prev = (idx > 0 && idx < pw) ? s_cand[idx - 1] : INT_MIN;
-            fl[q] = (idx < ncand && (idx == 0 || vals[q] != prev)) ? 1 : 0;
-            loc += fl[q];
+        // the range of the candidate cell ids: where it spans at most CANDBITS ids, a
+        // bitmap over it (in s_ofs, with the words' prefix counts in s_kofs, both free
+        // until the stage) sorts and deduplicates them; otherwise a bitonic sort does
+        int mn = INT_MAX, mx = INT_MIN;
+        for (int q = tid; q < ncand; q += BLOCK) {
+            const int v = ldg(S.cnbr + q0 + q);
+            mn = min(mn, v);
+            mx = max(mx, v);
         }
-        int p = block_excl_scan(loc, s_w, nsc);
-        for (int q = 0; q < CANDMAX / BLOCK; ++q)
-            if (fl[q]) s_cand[p++] = vals[q];
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = min(mn, __shfl_xor(mn, o));
+            mx = max(mx, __shfl_xor(mx, o));
+        }
+        if (lane == 0) { s_w[wv] = mn; s_w[8 + wv] = mx; }
         __syncthreads();
-        for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = ldg(S.ccount + s_cand[q]);
-        for (int q = tid; q < ncand; q += BLOCK) s_qpos[q] = lds_lower_bound(s_cand, nsc, ldg(S.cnbr + q0 + q));
+        mn = min(min(s_w[0], s_w[1]), min(s_w[2], s_w[3]));
+        mx = max(max(s_w[8], s_w[9]), max(s_w[10], s_w[11]));
+        __syncthreads();
+        if (mx - mn < CANDBITS) {
+            unsigned *bm = reinterpret_cast<unsigned *>(s_ofs);
+            int *wpre = s_kofs;
+            const int nw = ((mx - mn) >> 5) + 1;
+            for (int w = tid; w < nw; w += BLOCK) bm[w] = 0u;
+            __syncthreads();
+            for (int q = tid; q < ncand; q += BLOCK) {
+                const int v = ldg(S.cnbr + q0 + q) - mn;
+                atomicOr(&bm[v >> 5], 1u << (v & 31));
+            }
+            __syncthreads();
+            for (int w = tid; w < nw; w += BLOCK) wpre[w] = __popc(bm[w]);
+            __syncthreads();
+            nsc = block_scan_lds(wpre, nw, s_w);
+            for (int w = tid; w < nw; w += BLOCK) {
+                unsigned b = bm[w];
+                int r = wpre[w];
+                while (b) {
+                    s_cand[r++] = mn + (w << 5) + (__ffs(b) - 1);
+                    b &= b - 1u;
+                }
+            }
+            for (int q = tid; q < ncand; q += BLOCK) {
+                const int v = ldg(S.cnbr + q0 + q) - mn;
+                s_qpos[q] = wpre[v >> 5] + __popc(bm[v >> 5] & ((1u << (v & 31)) - 1u));
+            }
+            __syncthreads();
+            for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = ldg(S.ccount + s_cand[q]);
+        } else {
+            int pw = 1;
+            while (pw < ncand) pw <<= 1;
+            for (int q = tid; q < pw; q += BLOCK) s_cand[q] = (q < ncand) ? ldg(S.cnbr + q0 + q) : INT_MAX;
+            __syncthreads();
+            for (int kk = 2; kk <= pw; kk <<= 1)
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int t = tid; t < pw; t += BLOCK) {
+                        int ixj = t ^ jj;
+                        if (ixj > t) {
+                            int va = s_cand[t], vb = s_cand[ixj];
+                            bool up = (t & kk) == 0;
+                            if ((va > vb) == up) { s_cand[t] = vb; s_cand[ixj] = va; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            // deduplicate in place
+            int vals[CANDMAX / BLOCK], fl[CANDMAX / BLOCK], loc = 0;
+            for (int q = 0; q < CANDMAX / BLOCK; ++q) {
+                const int idx = tid * (CANDMAX / BLOCK) + q;
+                vals[q] = idx < pw ? s_cand[idx] : INT_MAX;
+                const int prev = (idx > 0 && idx < pw) ? s_cand[idx - 1] : INT_MIN;
+                fl[q] = (idx < ncand && (idx == 0 || vals[q] != prev)) ? 1 : 0;
+                loc += fl[q];
+            }
+            int p = block_excl_scan(loc, s_w, nsc);
+            for (int q = 0; q < CANDMAX / BLOCK; ++q)
+                if (fl[q]) s_cand[p++] = vals[q];
+            __syncthreads();
+            for (int q = tid; q < nsc; q += BLOCK) s_ofs[q] = ldg(S.ccount + s_cand[q]);
+            for (int q = tid; q < ncand; q += BLOCK) s_qpos[q] = lds_lower_bound(s_cand, nsc, ldg(S.cnbr + q0 + q));
+        }
         __syncthreads();
         ss = block_scan_lds(s_ofs, nsc, s_w);
         if (tid == 0) s_ofs[nsc] = ss;

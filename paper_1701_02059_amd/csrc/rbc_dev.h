@@ -21,6 +21,7 @@ constexpr int CNBR_ROW_MAX = 2048;      // cell pairs per cell before the build 
 constexpr int SMAX = 2048;             // stage entries (slots) per 256-particle block
 constexpr int SSTRIDE = SMAX + 32;     // stride of the blocks' stage lists (not a multiple of a large power of two)
 constexpr int CANDMAX = 1024;          // candidate cells (cell-pair entries) per block while staging
+constexpr int CANDBITS = 32 * CANDMAX;    // candidate-cell id range the list build sorts with a bitmap
 constexpr int USTAGE = 2048;           // candidate particles staged in LDS while building a block's lists
 static_assert(USTAGE <= SMAX && USTAGE < 0xffff, "a staged candidate union is the block's stage, indexed in 16 bits");
 constexpr float LIST_EXTENT = 4096.0f; // largest FP32 offset (sigma) allowed in that staging
