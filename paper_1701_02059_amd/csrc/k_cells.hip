@@ -210,6 +210,35 @@ __global__ __launch_bounds__(BLOCK) void k_bbox_partial(const SysDev *Sd, Maps L
     }
 }
 
+// Per-block bounding boxes of the seeds (unwrapped centroids), 256 seeds per block.
+__global__ __launch_bounds__(BLOCK) void k_seed_bbox_partial(const SysDev *Sd, Maps L_maps) {
+    SYS_FROM(c);
+    if (!S.sc->rebuild) return;
+    __shared__ double s_v[6][BLOCK / WAVE];
+    const int c = lb * BLOCK + threadIdx.x;
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (c < S.k) {
+        const D4 p = S.seed[c];
+        const double v[3] = {p.x, p.y, p.z};
+        for (int a = 0; a < 3; ++a) { mn[a] = v[a]; mx[a] = v[a]; }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = fmin(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+        }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) { s_v[a][w] = mn[a]; s_v[3 + a][w] = mx[a]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        double r = s_v[a][0];
+        for (int q = 1; q < BLOCK / WAVE; ++q) r = (a < 3) ? fmin(r, s_v[a][q]) : fmax(r, s_v[a][q]);
+        S.sbox[(size_t)lb * 6 + a] = r;
+    }
+}
+
 // Bounding boxes and grid geometry, one block per system (from the per-block partials).
 // Uniform grid over the seeds: cubic cells holding about one eighth of a seed each,
 // but no smaller than hmin (twice the cell-pair search radius).  A cell-pair query
@@ -226,10 +255,10 @@ __global__ void k_grid_setup(const SysDev *Sd, int nsys, double hmin) {
         const double *r = S.bred + (size_t)b * BRED + 2;
         for (int a = 0; a < 3; ++a) { mn[a] = fmin(mn[a], r[a]); mx[a] = fmax(mx[a], r[3 + a]); }
     }
-    for (int c = threadIdx.x; c < S.k; c += blockDim.x) {
-        D4 p = S.seed[c];
-        double v[3] = {p.x, p.y, p.z};
-        for (int a = 0; a < 3; ++a) { mn[3 + a] = fmin(mn[3 + a], v[a]); mx[3 + a] = fmax(mx[3 + a], v[a]); }
+    const int nsb = (S.k + BLOCK - 1) / BLOCK;
+    for (int b = threadIdx.x; b < nsb; b += blockDim.x) {
+        const double *r = S.sbox + (size_t)b * 6;
+        for (int a = 0; a < 3; ++a) { mn[3 + a] = fmin(mn[3 + a], r[a]); mx[3 + a] = fmax(mx[3 + a], r[3 + a]); }
     }
     for (int a = 0; a < 6; ++a)
         for (int o = 32; o > 0; o >>= 1) {
@@ -450,6 +479,7 @@ __global__ void k_grid_sortcells(const SysDev *Sd, Maps L_maps) {
 
 void launch_grid_build(const LaunchCtx &L) {
     hipLaunchKernelGGL(k_bbox_partial, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+    hipLaunchKernelGGL(k_seed_bbox_partial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_setup, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys, 2.0 * L.prm.cell_search);
     hipLaunchKernelGGL(k_grid_clear, dim3(L.nblk_g), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_grid_count, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
@@ -846,11 +876,10 @@ __global__ void k_seed_bbox(const SysDev *Sd, int nsys) {
     if (!S.sc->rebuild) return;
     __shared__ double s_mn[3][16], s_mx[3][16];
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int c = threadIdx.x; c < S.k; c += blockDim.x) {
-        D4 p = S.seed[c];
-        mn[0] = fmin(mn[0], p.x); mx[0] = fmax(mx[0], p.x);
-        mn[1] = fmin(mn[1], p.y); mx[1] = fmax(mx[1], p.y);
-        mn[2] = fmin(mn[2], p.z); mx[2] = fmax(mx[2], p.z);
+    const int nsb = (S.k + BLOCK - 1) / BLOCK;
+    for (int b = threadIdx.x; b < nsb; b += blockDim.x) {
+        const double *r = S.sbox + (size_t)b * 6;
+        for (int a = 0; a < 3; ++a) { mn[a] = fmin(mn[a], r[a]); mx[a] = fmax(mx[a], r[3 + a]); }
     }
     for (int a = 0; a < 3; ++a)
         for (int o = 32; o > 0; o >>= 1) {
@@ -910,6 +939,7 @@ __global__ void k_seed_permute(const SysDev *Sd, Maps L_maps) {
 }
 
 void launch_morton_sort_seeds(const LaunchCtx &L) {
+    hipLaunchKernelGGL(k_seed_bbox_partial, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     hipLaunchKernelGGL(k_seed_bbox, dim3(L.nsys), dim3(1024), 0, L.st, L.S, L.nsys);
     hipLaunchKernelGGL(k_morton, dim3(L.nblk_c), dim3(BLOCK), 0, L.st, L.S, L.maps);
     sort_segments(L, 1, 64);

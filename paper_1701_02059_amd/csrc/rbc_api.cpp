@@ -271,6 +271,7 @@ size_t layout(HostSys &s, char *base) {
     d.val = c.take<uint32_t>(n); d.val2 = c.take<uint32_t>(n);
     d.hist = c.take<int32_t>((size_t)256 * (std::max(s.ntile_p, s.ntile_s) + 1));   // + digit totals
     d.seed = c.take<D4>(k); d.seed2 = c.take<D4>(k);
+    d.sbox = c.take<double>((size_t)((k + BLOCK - 1) / BLOCK) * 6);
     d.cstart = c.take<int32_t>(k + 1); d.ccount = c.take<int32_t>(k); d.cstart2 = c.take<int32_t>(k + 1);
     d.ccount2 = c.take<int32_t>(k); d.cmap = c.take<int32_t>(k);
     d.cnbr_start = c.take<int32_t>(k + 1); d.cnbr = c.take<int32_t>(s.cnbr_cap);

@@ -121,6 +121,7 @@ struct SysDev {
     uint32_t *val, *val2;
     int32_t *hist;                                  // sort histograms: tiles x 256
     D4 *seed, *seed2;                               // centroid xyz, w = cell radius
+    double *sbox;                                   // per 256-seed block: the seeds' min xyz, max xyz
     int32_t *cstart, *ccount, *cstart2, *ccount2, *cmap;
     int32_t *cnbr_start, *cnbr;                     // full cell-pair CSR (k+1, cnbr_cap)
     int32_t *gstart, *gcount, *gseed, *sgcell;      // seed grid (gcap+1, gcap, k, k)
