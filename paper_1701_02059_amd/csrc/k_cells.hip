@@ -1374,7 +1374,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
     const bool valid = i < S.n;
     if (S.sc->err & ERR_CNBR) {          // no valid cell pairs: publish empty lists (block-uniform)
         if (lane == 0 && chunk_ok) { S.nlk[chunk] = 0; S.ilk[chunk] = 0; }
-        if (tid == 0) { S.scount[lb] = 0; S.iscount[lb] = 0; S.blkrows[lb] = 0; }
+        if (tid == 0) { S.scount[lb] = 0; S.iscount[lb] = 0; }
         return;
     }
     if (tid == 0) { s_rows = 0; s_big = 0; }
@@ -1739,7 +1739,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
     if (tid == 0) {
         S.scount[lb] = staged ? kept : -1;
         S.iscount[lb] = nkept;
-        S.blkrows[lb] = s_rows;
+        if (s_rows > 0) max_if_larger(&S.sc->nlrows, s_rows);   // the build's longest list
     }
 }
 
@@ -1925,7 +1925,10 @@ void launch_mask_maps(const LaunchCtx &L, const unsigned long long m[4], int32_t
 
 // ------------------------------------------------------------------ finish
 
-__global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
+// The drift references of the new lists, and after a cell update (the particles have
+// moved to new slots) the FP32 orientation copies; between updates the step kernel
+// keeps those current.
+__global__ void k_finish_particles(const SysDev *Sd, Maps L_maps, int cells_moved) {
     SYS_FROM(p);
     if (!S.sc->rebuild) return;
     int i = lb * BLOCK + threadIdx.x;
@@ -1933,8 +1936,10 @@ __global__ void k_finish_particles(const SysDev *Sd, Maps L_maps) {
         const V3 p = S.pos[i];
         S.xb[i] = F3{(float)p.x, (float)p.y, (float)p.z};
         S.xp[i] = F3{(float)p.x, (float)p.y, (float)p.z};
-        const V3 o = S.ori[i];
-        S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, __int_as_float((int)S.typ[i] & TYP_MASK)};
+        if (cells_moved) {
+            const V3 o = S.ori[i];
+            S.ori32[i] = F4{(float)o.x, (float)o.y, (float)o.z, __int_as_float((int)S.typ[i] & TYP_MASK)};
+        }
     }
 }
 
@@ -1942,15 +1947,7 @@ __global__ __launch_bounds__(256) void k_finish_sys(const SysDev *Sd, int nsys) 
     const SysDev &S = Sd[blockIdx.x];
     SysScal *sc = S.sc;
     if (!sc->rebuild) return;
-    int m = 0;
-    const int nblk = (S.n + BLOCK - 1) / BLOCK;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = max(m, S.blkrows[b]);
-    m = wave_max_int(m);
-    __shared__ int s_m[4];
-    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
-    __syncthreads();
     if (threadIdx.x == 0) {
-        sc->nlrows = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
         sc->maxdisp2 = 0ull;
         sc->maxv2 = 0ull;
         sc->maxdisp2p = 0ull;
@@ -1958,8 +1955,8 @@ __global__ __launch_bounds__(256) void k_finish_sys(const SysDev *Sd, int nsys) 
     }
 }
 
-void launch_finish_update(const LaunchCtx &L) {
-    hipLaunchKernelGGL(k_finish_particles, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps);
+void launch_finish_update(const LaunchCtx &L, bool cells_moved) {
+    hipLaunchKernelGGL(k_finish_particles, dim3(L.nblk_p), dim3(BLOCK), 0, L.st, L.S, L.maps, cells_moved ? 1 : 0);
     hipLaunchKernelGGL(k_finish_sys, dim3(L.nsys), dim3(256), 0, L.st, L.S, L.nsys);
 }
 

@@ -294,7 +294,6 @@ size_t layout(HostSys &s, char *base) {
     d.ilk = c.take<int32_t>(s.nchunk);
     d.istage = c.take<int32_t>((size_t)nblkp * SSTRIDE);
     d.iscount = c.take<int32_t>(nblkp);
-    d.blkrows = c.take<int32_t>(nblkp);
     d.bred = c.take<double>((size_t)nblkp * BRED);
     d.tsum = c.take<int32_t>((size_t)std::max((k + SCAN_TILE - 1) / SCAN_TILE, (s.gcap + SCAN_TILE - 1) / SCAN_TILE) + 2);
     s.lip = c.take<int32_t>(s.nlip + s.nsrcp);
@@ -401,7 +400,7 @@ bool any_live(const rbc_ctx *h) {
 }
 
 void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd);
-void lists_body(rbc_ctx *h, const LaunchCtx &L);
+void lists_body(rbc_ctx *h, const LaunchCtx &L, bool cells_moved);
 
 // Launch context whose block maps cover only the systems in `which`, with their
 // rebuild flags set: the device builds the restricted prefix maps from the flags,
@@ -460,7 +459,7 @@ void run_update(rbc_ctx *h, const std::vector<int> &which, int lloyd) {
 // distances, so the cell pairs and the lists stay complete.
 void run_lists(rbc_ctx *h, const std::vector<int> &which) {
     if (which.empty()) return;
-    lists_body(h, restricted(h, which));
+    lists_body(h, restricted(h, which), false);
     for (int s : which) h->sys[s].rebuilds++;
 }
 
@@ -508,18 +507,18 @@ void update_body(rbc_ctx *h, const LaunchCtx &L, int bits, int lloyd) {
     launch_morton_sort_seeds(L);
     launch_block_permute(L);
     launch_grid_build(L);
-    lists_body(h, L);
+    lists_body(h, L, true);
 }
 
 // Cell radii, cell pairs and neighbour lists on the current cells.
-void lists_body(rbc_ctx *h, const LaunchCtx &L) {
+void lists_body(rbc_ctx *h, const LaunchCtx &L, bool cells_moved) {
     launch_cell_bounds(L);
     launch_cell_pairs(L);
     const bool t = h->timing && h->ncount < (int)h->nb.size();
     if (t) hipEventRecord(h->nb[h->ncount], L.st);
     launch_nlist(L);
     if (t) hipEventRecord(h->ne[h->ncount++], L.st);
-    launch_finish_update(L);
+    launch_finish_update(L, cells_moved);
 }
 
 // The status and message of one slot's error bits.

@@ -141,7 +141,6 @@ struct SysDev {
     uint16_t *il16;                                 // pruned lists: indices into the pruned stage (0xffff pads)
     int32_t *ilk;                                   // per chunk: rows of the pruned list
     int32_t *istage, *iscount;                      // per block: the pruned stage (SMAX), count (-1: use nl)
-    int32_t *blkrows;                               // per block: largest list row count of the last build
     double *bred;                                   // per particle block: BRED partials (stats, bounding box)
     int32_t *tsum;                                  // segmented-scan tile sums
     SysScal *sc;
@@ -367,7 +366,7 @@ void launch_cell_pairs(const LaunchCtx &L);
 void launch_nlist(const LaunchCtx &L);
 void launch_prune(const LaunchCtx &L);                    // pruned lists of the systems in L's particle map
 void launch_mask_maps(const LaunchCtx &L, const unsigned long long m[4], int32_t *out);   // particle map of a mask
-void launch_finish_update(const LaunchCtx &L);
+void launch_finish_update(const LaunchCtx &L, bool cells_moved);
 void launch_pack(const LaunchCtx &L, int sys, const double *x, const double *n, const int32_t *type,
                  const double *v, const double *w, int count);
 
