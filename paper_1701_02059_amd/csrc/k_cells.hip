@@ -1620,12 +1620,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     }
                 };
                 int k = s_kofs[pos];
-                for (; k + 1 < ke; k += 2) {                      // two candidates per trip
-                    const F4 a0 = s_u[k], a1 = s_u[k + 1];
+                for (; k + 3 < ke; k += 4) {                      // four candidates per trip
+                    const F4 a0 = s_u[k], a1 = s_u[k + 1], a2 = s_u[k + 2], a3 = s_u[k + 3];
                     test(a0, k);
                     test(a1, k + 1);
+                    test(a2, k + 2);
+                    test(a3, k + 3);
                 }
-                if (k < ke) test(s_u[k], k);
+                for (; k < ke; ++k) test(s_u[k], k);
             }
             // the pruned list: the entries just written (read back by the lane that wrote
             // them) within the pruned radius
@@ -1819,7 +1821,7 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     int cnt = 0;
     const uint16_t *col = S.nl16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
     uint16_t *icol = S.il16 + (size_t)(chunk_ok ? chunk : 0) * MAXNB * CHUNK + lane;
-    constexpr int BATCH = 8;     // list rows whose entries are loaded together
+    constexpr int BATCH = 32;    // list rows whose entries are loaded together
     if (valid && chunk_ok) {
         const int ti = (int)pi.w;
         const float oix = (float)minimg1(pi.x - ref.x, S.per[0], S.box[0]);
