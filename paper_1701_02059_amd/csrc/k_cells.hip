@@ -1615,7 +1615,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     const int w = __float_as_int(c.w);
                     const float rl = sel3f(w & 3, rlA, rlB, rlC);
                     if (d2 < rl && w != selfw) {
-                        if (cnt < MAXNB) stg(col16 + cnt * CHUNK, (uint16_t)k);
+                        if (cnt < MAXNB) {
+                            stg(col16 + cnt * CHUNK, (uint16_t)k);
+                            // the pruned list: the entries within the pruned radius
+                            if (d2 < sel3f(w & 3, riA, riB, riC)) {
+                                stg(icol + pc * CHUNK, (uint16_t)k);
+                                ++pc;
+                                s_pflag[k] = 1;
+                            }
+                        }
                         ++cnt;
                     }
                 };
@@ -1628,31 +1636,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 3))) v
                     test(a3, k + 3);
                 }
                 for (; k < ke; ++k) test(s_u[k], k);
-            }
-            // the pruned list: the entries just written (read back by the lane that wrote
-            // them) within the pruned radius
-            const int mine = min(cnt, MAXNB);
-            for (int r0 = 0; r0 < mine; r0 += 8) {
-                int e[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) e[q] = r0 + q < mine ? (int)ldg(col16 + (r0 + q) * CHUNK) : 0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (r0 + q >= mine) break;
-                    const F4 c = s_u[e[q]];
-                    float dx = c.x - oix, dy = c.y - oiy, dz = c.z - oiz;
-                    if constexpr (PER) {
-                        dx -= Lx * rintf(dx * iLx);
-                        dy -= Ly * rintf(dy * iLy);
-                        dz -= Lz * rintf(dz * iLz);
-                    }
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 < sel3f(__float_as_int(c.w) & 3, riA, riB, riC)) {
-                        stg(icol + pc * CHUNK, (uint16_t)e[q]);
-                        ++pc;
-                        s_pflag[e[q]] = 1;
-                    }
-                }
             }
         };
         if (periodic) scan_cells(std::true_type{});
@@ -1795,16 +1778,16 @@ __global__ __launch_bounds__(BLOCK) void k_prune(const SysDev *Sd, Maps L_maps, 
     for (int w = tid; w < SMAX / 4; w += BLOCK) reinterpret_cast<unsigned *>(s_flag)[w] = 0u;
     const D4 ref = ld3(S.pos + (size_t)lb * BLOCK);
     bool far = false;
-    // four entries per thread in flight: their slots, then their positions
-    for (int q0 = tid; q0 < scnt; q0 += 4 * BLOCK) {
-        int slot[4];
+    // eight entries per thread in flight: their slots, then their positions
+    for (int q0 = tid; q0 < scnt; q0 += 8 * BLOCK) {
+        int slot[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int q = q0 + k * BLOCK;
             slot[k] = q < scnt ? ldg(S.stage + (size_t)lb * SSTRIDE + q) : -1;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int q = q0 + k * BLOCK;
             if (slot[k] < 0) break;
             const D4 pj = ldpos(S, slot[k]);
