@@ -47,8 +47,8 @@ PEAK_HBM = 8000.0           # GB/s
 # HBM traffic of that kernel per launch at the whole-cell workload, mixed precision,
 # skins 0.65 and 0.15: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB -> bytes; factors from a
 # plain 512 MiB device copy), valid only for the kernel sources whose digest is given.
-FORCE_TRAFFIC = {"sources_sha256": "8fdd62a948db3da5", "skin": 0.65, "inner_skin": 0.15,
-                 "bytes": 1512654751, "fetch_kib": 504498, "write_kib": 468205,
+FORCE_TRAFFIC = {"sources_sha256": "f735d1ee4833da80", "skin": 0.65, "inner_skin": 0.15,
+                 "bytes": 1512659236, "fetch_kib": 504500, "write_kib": 468206,
                  "valu_insts": 181583857}   # SQ_INSTS_VALU per launch (wavefront instructions)
 BYTES_BUILD_READ = 25       # list build: position (3 x 8 B) and type (1 B) of every particle, read once
 CU_COUNT, SIMDS_PER_CU, CLOCK_GHZ = 256, 4, 2.4
